@@ -1,0 +1,231 @@
+/*
+ * bipart.h - C ABI of the MI355X (gfx950) implementation of BiPart's
+ * deterministic multilevel hypergraph partitioner (Maleki, Agarwal,
+ * Burtscher, Pingali, "BiPart: A Parallel and Deterministic Multilevel
+ * Hypergraph Partitioner", PPoPP 2021).
+ *
+ * The problem (Section 1.1): given a hypergraph G = (V, E) with node weights
+ * and hyperedge weights, k >= 1 and an imbalance eps >= 0, find a partition of
+ * V into k parts, each of weight at most (1 + eps) * W / k, minimising
+ * cut(G, P) = sum over hyperedges of w(e) * (lambda_e - 1), where lambda_e is
+ * the number of parts hyperedge e touches.  The method (Section 3) is a
+ * multilevel bisection - multi-node matching and contraction (Algorithms 1
+ * and 2), initial bisection of the coarsest graph (Algorithms 3 and 4),
+ * projection with parallel swap refinement and a balance step (Algorithm 5)
+ * - applied as a nested recursive bisection for k parts (Algorithm 6).
+ *
+ * The result is fully deterministic: the same input and parameters give the
+ * same partition on every run, for every launch configuration, and whether a
+ * graph is partitioned alone or inside a batch.
+ *
+ * Conventions for every entry point:
+ *   - Hypergraphs are CSR over hyperedges (bp_hypergraph).  Node ids are
+ *     0..num_nodes-1, hyperedge ids 0..num_hedges-1 in input order.
+ *   - The caller owns every buffer passed in or out.  The library never keeps
+ *     a caller pointer after the call returns.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the current device.  Device entry points take the HIP
+ *     stream (hipStream_t) as a void*; NULL means the null stream.  Their
+ *     outputs are complete when the call returns unless stated otherwise.
+ *   - Every entry point returns a bp_status: 0 success, > 0 warning (outputs
+ *     valid), < 0 error (outputs unspecified).  bp_status_string() names a
+ *     code; bp_last_error() gives the detail of the calling thread's last
+ *     error (for BP_ERR_DEVICE it holds the HIP error text).
+ *   - Entry points are thread-safe; concurrent calls use separate memory.
+ */
+#ifndef BIPART_H
+#define BIPART_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t bp_status;
+
+#define BP_OK                   0
+#define BP_WARN_IMBALANCED      1  /* valid partition, but a part exceeds (1+eps)W/k        */
+#define BP_ERR_INVALID_ARG     -1  /* k < 1, eps < 0 or NaN, NULL required pointer, ...    */
+#define BP_ERR_INVALID_CSR     -2  /* offsets not monotone, pin out of range, repeated pin */
+#define BP_ERR_WEIGHT_OVERFLOW -3  /* negative weight, or a weight sum >= 2^31            */
+#define BP_ERR_OUT_OF_MEMORY   -4  /* device allocation failed                             */
+#define BP_ERR_DEVICE          -5  /* HIP runtime error (text in bp_last_error)            */
+#define BP_ERR_REJECTED        -6  /* server: request footprint above the memory budget    */
+#define BP_ERR_SHUTDOWN        -7  /* server: destroyed before the request completed       */
+#define BP_ERR_NOT_FOUND       -8  /* server: unknown ticket                               */
+
+/* Matching policies of Table 1 (priority of a hyperedge in Algorithm 1). */
+#define BP_LDH  0  /* lower degree first (default)    */
+#define BP_HDH  1  /* higher degree first             */
+#define BP_LWD  2  /* lower hyperedge weight first    */
+#define BP_HWD  3  /* higher hyperedge weight first   */
+#define BP_RAND 4  /* hash of the hyperedge id        */
+
+/*
+ * A hypergraph in CSR form.
+ *   hedge_offsets[num_hedges+1]: hedge_offsets[0] = 0, non-decreasing; the
+ *       pins of hyperedge e are pins[hedge_offsets[e] .. hedge_offsets[e+1]).
+ *   pins[P], P = hedge_offsets[num_hedges] < 2^31: node ids in [0, num_nodes),
+ *       no node twice in one hyperedge; any order within a hyperedge.
+ *   node_weights[num_nodes]: >= 0, sum < 2^31; NULL means all 1.
+ *   hedge_weights[num_hedges]: >= 0, sum < 2^31; NULL means all 1.
+ * Hyperedges with fewer than two pins are allowed; they can never be cut.
+ */
+typedef struct {
+    int32_t num_nodes;
+    int32_t num_hedges;
+    const int32_t *hedge_offsets;
+    const int32_t *pins;
+    const int32_t *node_weights;
+    const int32_t *hedge_weights;
+} bp_hypergraph;
+
+/*
+ * Tuning parameters of Section 3.4.
+ *   policy: BP_LDH .. BP_RAND (Table 1).
+ *   max_levels: at most this many coarsening steps per bisection (25).
+ *   refine_iters: swap rounds per level in Algorithm 5 (2).
+ *   min_coarse_nodes: stop coarsening a graph once it has at most this many
+ *       nodes (100; 0 coarsens until no hyperedge is left or max_levels).
+ */
+typedef struct {
+    int32_t policy;
+    int32_t max_levels;
+    int32_t refine_iters;
+    int32_t min_coarse_nodes;
+} bp_params;
+
+/* Optional result details. */
+typedef struct {
+    int64_t cut;               /* connectivity-1 cut (problem statement)      */
+    int64_t max_part_weight;   /* heaviest part                               */
+    int64_t part_weight_limit; /* max(ceil(W/k), floor((1+eps) W / k))        */
+    int32_t balanced;          /* max_part_weight <= part_weight_limit         */
+    int32_t tree_levels;       /* bisection tree depth, ceil(log2 k)          */
+    int32_t bisections;        /* bisection problems solved                   */
+    int32_t coarsen_levels;    /* coarsening steps of the first bisection      */
+    int64_t pins_coarsened;    /* sum of pins over every level coarsened      */
+    int64_t pins_refined;      /* sum of pins over every gain evaluation      */
+    int32_t host_syncs;        /* device-to-host waits the call needed        */
+    int32_t kernel_launches;   /* kernels launched by the call                */
+} bp_report;
+
+/* Fills *p with the defaults listed above. */
+void bp_default_params(bp_params *p);
+
+/* Name of a status code (static string). */
+const char *bp_status_string(bp_status s);
+
+/* Detail of the calling thread's most recent error ("" if none). */
+const char *bp_last_error(void);
+
+/*
+ * k-way partition of a host hypergraph (Sections 1.1 and 3, Algorithm 6).
+ * hg: host pointers as in bp_hypergraph.  k >= 1; eps >= 0.
+ * params: NULL for the defaults.  part_out: host int32[num_nodes], receives
+ * part ids in [0, k).  Part ids follow the bisection tree: for a sub-problem
+ * owning parts [lo, lo+k'), side 0 of its bisection gets [lo, lo+ceil(k'/2)).
+ * cut_out (nullable): the connectivity-1 cut.  report (nullable).
+ * Input is validated on the host (all BP_ERR_INVALID_* / OVERFLOW checks,
+ * including repeated pins) and copied to the device; the partition runs on
+ * the current HIP device.  Returns BP_WARN_IMBALANCED when the result
+ * violates the balance constraint (possible only with heavy nodes).
+ */
+bp_status bp_partition(const bp_hypergraph *hg, int32_t k, double eps, const bp_params *params,
+                       int32_t *part_out, int64_t *cut_out, bp_report *report);
+
+/*
+ * Same as bp_partition for a hypergraph already in device memory.
+ * hg: the struct itself is host memory, its arrays are device pointers.
+ * d_part_out: device int32[num_nodes].  cut_out (nullable): host int64.
+ * stream: hipStream_t the work is ordered on.  The call validates offsets,
+ * pin ranges and weight sums on the device; a hyperedge listing a node twice
+ * is NOT detected here (bp_partition checks it) and gives an unspecified but
+ * memory-safe result.
+ */
+bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
+                              const bp_params *params, int32_t *d_part_out, int64_t *cut_out,
+                              bp_report *report, void *stream);
+
+/*
+ * Connectivity-1 cut and heaviest part of a given partition (problem
+ * statement, Section 1.1), computed on the device.  Host pointers; part[v] in
+ * [0, k).  cut and max_part_weight are host outputs (nullable).
+ */
+bp_status bp_compute_cut(const bp_hypergraph *hg, int32_t k, const int32_t *part, int64_t *cut,
+                         int64_t *max_part_weight);
+
+/* Same for device pointers (hg arrays and d_part); outputs are host values. */
+bp_status bp_compute_cut_device(const bp_hypergraph *hg, int32_t k, const int32_t *d_part,
+                                int64_t *cut, int64_t *max_part_weight, void *stream);
+
+/* ---- single steps, for step-by-step checking (device pointers) ----------- */
+
+/*
+ * Algorithm 1: d_match[v] = the incident hyperedge of highest priority
+ * (policy of Table 1, ties by the hash of the hyperedge id), -1 if v has no
+ * hyperedge.  hg: device arrays.
+ */
+bp_status bp_step_match(const bp_hypergraph *hg, int32_t policy, int32_t *d_match, void *stream);
+
+/*
+ * Algorithm 2: one coarsening step.  Outputs (device, caller-allocated at the
+ * fine sizes): d_parent[num_nodes], d_coarse_offsets[num_hedges+1],
+ * d_coarse_pins[P], d_coarse_node_w[num_nodes], d_coarse_hedge_w[num_hedges];
+ * *coarse_nodes, *coarse_hedges (host) receive the coarse sizes.  Coarse
+ * nodes are numbered by the smallest fine id they contain; coarse hyperedges
+ * hold their sorted distinct parent ids, appear in source order, and identical
+ * ones are merged with summed weight.
+ */
+bp_status bp_step_coarsen(const bp_hypergraph *hg, int32_t policy, int32_t *d_parent,
+                          int32_t *d_coarse_offsets, int32_t *d_coarse_pins,
+                          int32_t *d_coarse_node_w, int32_t *d_coarse_hedge_w,
+                          int32_t *coarse_nodes, int32_t *coarse_hedges, void *stream);
+
+/* Algorithm 4: d_gain[v] for the bisection d_side[v] in {0,1} (device). */
+bp_status bp_step_gains(const bp_hypergraph *hg, const uint8_t *d_side, int32_t *d_gain,
+                        void *stream);
+
+/* Algorithm 3: initial bisection into k0 : k1 shares, d_side[num_nodes] out. */
+bp_status bp_step_initial(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint8_t *d_side,
+                          void *stream);
+
+/*
+ * Algorithm 5 on one level: iters swap rounds then the balance step against
+ * the side bounds max0/max1.  d_side is updated in place.  *stuck (host,
+ * nullable) is 1 when balancing had to stop with a side over its bound.
+ */
+bp_status bp_step_refine(const bp_hypergraph *hg, int32_t iters, int64_t max0, int64_t max1,
+                         uint8_t *d_side, int32_t *stuck, void *stream);
+
+/*
+ * One multilevel bisection into k0 : k1 shares with the 32.32 fixed-point
+ * imbalance factor F = floor((1+eps')*2^32): coarsen, initial bisection,
+ * project and refine.  d_side out; *levels (host, nullable) = steps taken.
+ */
+bp_status bp_step_bisect(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint64_t F,
+                         const bp_params *params, uint8_t *d_side, int32_t *levels,
+                         void *stream);
+
+/* ---- kernel timing (diagnostics) ------------------------------------------ */
+
+typedef struct {
+    char name[40];      /* kernel family                                   */
+    int64_t launches;   /* launches timed                                  */
+    double total_ms;    /* summed device time of those launches (hipEvents) */
+    double bytes;       /* summed algorithmic bytes of those launches      */
+} bp_kernel_stat;
+
+/* Enables (1) or disables (0) per-launch hipEvent timing of every kernel
+ * family on the launching stream.  Off by default; adds a small overhead. */
+void bp_profile_enable(int32_t on);
+/* Clears the accumulated statistics. */
+void bp_profile_reset(void);
+/* Copies up to cap entries into out (host) and returns how many exist. */
+int32_t bp_profile_read(bp_kernel_stat *out, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BIPART_H */

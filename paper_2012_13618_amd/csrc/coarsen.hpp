@@ -1,0 +1,500 @@
+// One coarsening step over all active segments of a level (Algorithms 1, 2).
+//
+//  match     Algorithm 1: every node takes the 64-bit minimum of
+//            (priority << 32 | hash(local id + 1)) over its hyperedges with one
+//            atomicMin per pin; the hash is a bijection, so the winning
+//            hyperedge is decoded from the key itself.
+//  group     Algorithm 2, first loop: |S(e)| and the weight of S(e) by
+//            integer atomics; sets of two or more are merged.
+//  attach    Algorithm 2, second loop: a singleton joins the lightest merged
+//            set among its hyperedge's pins (ties: smaller node id) as a
+//            64-bit min of (set weight << 32 | node id).
+//  ids       coarse node ids by prefix scan over group leaders (smallest
+//            member), weights summed with atomics.
+//  hedges    Algorithm 2, third loop: sorted distinct parents per hyperedge
+//            (registers / wave LDS / workgroup LDS / global by degree),
+//            kept when at least two.
+//  dedup     identical pin sets merged: fingerprint hash table with atomicMin
+//            of the source id, then an exact pin-by-pin check; weights added
+//            into the surviving (smallest) source; compaction by scan.
+#pragma once
+#include "level.hpp"
+#include "scan.hpp"
+
+namespace bp {
+
+constexpr uint64_t kEmptySlot = ~0ull;
+
+struct CoarsenBufs {
+    uint64_t *key;     // [N]
+    int32_t *match;    // [N]
+    int32_t *grp;      // [N]
+    int32_t *cid;      // [N]
+    int32_t *cnt, *gw; // [E]
+    int32_t *lead;     // [E]
+    int32_t *qpins;    // [P]
+    int32_t *qlen;     // [E]
+    uint64_t *fp;      // [E]
+    int32_t *hslot;    // [E]
+    int32_t *rep;      // [E]
+    int32_t *wsum;     // [E]
+    int32_t *hdst;     // [E]
+    int32_t *hb_tmp;   // [S]
+    uint64_t *tkeys;   // [T]
+    int32_t *tmin;     // [T]
+    int32_t tmask;
+    int32_t *counters; // [8]: unresolved, nmid, nbig, nhuge
+    int32_t *totN;     // scan total
+    uint64_t *totEP;   // scan total
+    int32_t *huge_scratch;
+};
+
+__global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, int32_t *grp,
+                               int32_t *cnw, int32_t *cnt, int32_t *gw, int32_t *lead,
+                               int32_t *wsum, uint64_t *tkeys, int32_t *tmin, int32_t *counters)
+{
+    int64_t n = N > E ? N : E;
+    if (T > n) n = T;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (i < N) {
+            key[i] = kNoKey;
+            grp[i] = -1;
+            cnw[i] = 0;
+        }
+        if (i < E) {
+            cnt[i] = 0;
+            gw[i] = 0;
+            lead[i] = INT32_MAX;
+            wsum[i] = 0;
+        }
+        if (i < T) {
+            tkeys[i] = kEmptySlot;
+            tmin[i] = INT32_MAX;
+        }
+        if (i < 8) counters[i] = 0;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_match(int32_t count, const int32_t *list,
+                                                  const int32_t *off, const int32_t *pins,
+                                                  const int32_t *hw, const int32_t *hseg,
+                                                  const int32_t *hbase, const uint8_t *sact,
+                                                  int policy, unsigned long long *key)
+{
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    int32_t s = hseg[e];
+    if (!sact[s]) return;
+    unsigned long long K = hedge_key(policy, (uint32_t)(e - hbase[s]), d, hw[e]);
+    for (int i = lane; i < d; i += stride) atomicMin(&key[pins[b + i]], K);
+}
+
+__global__ __launch_bounds__(kBlock) void k_decode(int32_t N, const uint64_t *key,
+                                                   const int32_t *nseg, const int32_t *hbase,
+                                                   const uint8_t *sact, const int32_t *nw,
+                                                   int32_t *match, int32_t *cnt, int32_t *gw)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int32_t s = nseg[v];
+    uint64_t k = key[v];
+    if (!sact[s] || k == kNoKey) {
+        match[v] = -1;
+        return;
+    }
+    int32_t e = hbase[s] + (int32_t)(fmix32_inv((uint32_t)k) - 1u);
+    match[v] = e;
+    atomicAdd(&cnt[e], 1);
+    atomicAdd(&gw[e], nw[v]);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_attach(int32_t count, const int32_t *list,
+                                                   const int32_t *off, const int32_t *pins,
+                                                   const int32_t *hseg, const uint8_t *sact,
+                                                   const int32_t *match, const int32_t *cnt,
+                                                   const int32_t *gw, int32_t *grp)
+{
+    __shared__ unsigned long long lds[16];
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    if (cnt[e] != 1 || !sact[hseg[e]]) return;
+    unsigned long long best = kNoKey, uu = kNoKey;
+    for (int i = lane; i < d; i += stride) {
+        int32_t v = pins[b + i];
+        int32_t m = match[v];
+        if (m == e) {
+            uu = (unsigned long long)v;
+        } else if (cnt[m] >= 2) {
+            unsigned long long c = ((unsigned long long)(uint32_t)gw[m] << 32) | (uint32_t)v;
+            best = c < best ? c : best;
+        }
+    }
+    best = group_min<S>(best, lds);
+    uu = group_min<S>(uu, lds);
+    if (lane == 0 && best != kNoKey) grp[(int32_t)uu] = match[(int32_t)(best & 0xffffffffu)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_lead(int32_t N, const int32_t *nseg,
+                                                 const uint8_t *sact, const int32_t *match,
+                                                 const int32_t *cnt, int32_t *grp, int32_t *lead)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N || !sact[nseg[v]]) return;
+    int32_t m = match[v];
+    int32_t g = (m >= 0 && cnt[m] >= 2) ? m : grp[v];
+    grp[v] = g;
+    if (g >= 0) atomicMin(&lead[g], (int32_t)v);
+}
+
+__global__ __launch_bounds__(kBlock) void k_parent(int32_t N, const int32_t *nseg,
+                                                   const uint8_t *sact, const int32_t *grp,
+                                                   const int32_t *lead, const int32_t *cid,
+                                                   const int32_t *nw, int32_t *parent,
+                                                   int32_t *cnw, int32_t *cnseg)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int32_t s = nseg[v];
+    if (!sact[s]) return;
+    int32_t g = grp[v];
+    int32_t l = g < 0 ? (int32_t)v : lead[g];
+    int32_t c = cid[l];
+    parent[v] = c;
+    atomicAdd(&cnw[c], nw[v]);
+    if (l == v) cnseg[c] = s;
+}
+
+__device__ __forceinline__ uint64_t fp_finish(uint64_t sum, int32_t len)
+{
+    uint64_t f = sum + (uint64_t)len * 0x9E3779B97F4A7C15ull;
+    return f == kEmptySlot ? f - 1 : f;
+}
+__device__ __forceinline__ uint64_t fp_term(int32_t q, uint64_t salt)
+{
+    return mix64((uint64_t)(uint32_t)q + salt);
+}
+
+// Third loop of Algorithm 2 for hyperedges of degree <= 8: parents sorted in
+// registers by an odd-even transposition network.
+__global__ __launch_bounds__(kBlock) void k_qbuild_small(int32_t E, const int32_t *off,
+                                                         const int32_t *pins,
+                                                         const int32_t *hseg,
+                                                         const uint8_t *sact,
+                                                         const int32_t *parent, int32_t *qpins,
+                                                         int32_t *qlen, uint64_t *fp)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (d > kSmallMax) return;
+    if (!sact[hseg[e]]) {
+        qlen[e] = 0;
+        return;
+    }
+    int32_t q[kSmallMax];
+#pragma unroll
+    for (int i = 0; i < kSmallMax; i++) q[i] = i < d ? parent[pins[b + i]] : INT32_MAX;
+#pragma unroll
+    for (int r = 0; r < kSmallMax; r++) {
+#pragma unroll
+        for (int i = r & 1; i + 1 < kSmallMax; i += 2) {
+            int32_t x = q[i], y = q[i + 1];
+            q[i] = x < y ? x : y;
+            q[i + 1] = x < y ? y : x;
+        }
+    }
+    int32_t len = 0;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < kSmallMax; i++) {
+        bool first = i < d && (i == 0 || q[i] != q[i - 1]);
+        if (first) {
+            qpins[b + len] = q[i];
+            sum += fp_term(q[i], 0);
+            len++;
+        }
+    }
+    qlen[e] = len >= 2 ? len : 0;
+    fp[e] = fp_finish(sum, len);
+}
+
+// Degree 9..256: each wavefront sorts its hyperedge's parents in a 256-entry
+// LDS slice.  Waves without a hyperedge sort padding so barriers line up.
+__global__ __launch_bounds__(kBlock) void k_qbuild_wave(int32_t count, const int32_t *list,
+                                                        const int32_t *off, const int32_t *pins,
+                                                        const int32_t *hseg,
+                                                        const uint8_t *sact,
+                                                        const int32_t *parent, int32_t *qpins,
+                                                        int32_t *qlen, uint64_t *fp)
+{
+    __shared__ int32_t buf[kBlock / kWave][kMidMax];
+    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int64_t gw_ = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int32_t e = gw_ < count ? list[gw_] : -1;
+    int32_t b = 0, d = 0;
+    bool act = false;
+    if (e >= 0) {
+        b = off[e];
+        d = off[e + 1] - b;
+        act = sact[hseg[e]] != 0;
+    }
+    int32_t *a = buf[w];
+    for (int i = lane; i < kMidMax; i += 64) a[i] = (act && i < d) ? parent[pins[b + i]] : INT32_MAX;
+    __syncthreads();
+    wave_bitonic_sort(a, kMidMax);
+    // each lane owns 4 consecutive sorted entries
+    int32_t flags = 0, cntl = 0;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        int i = lane * 4 + j;
+        bool first = act && i < d && (i == 0 || a[i] != a[i - 1]);
+        if (first) {
+            flags |= 1 << j;
+            cntl++;
+            sum += fp_term(a[i], 0);
+        }
+    }
+    int32_t incl = wave_incl_scan(cntl);
+    int32_t len = __shfl(incl, 63, 64);
+    sum = wave_sum(sum);
+    int32_t pos = incl - cntl;
+#pragma unroll
+    for (int j = 0; j < 4; j++)
+        if (flags & (1 << j)) qpins[b + pos++] = a[lane * 4 + j];
+    if (e >= 0 && lane == 0) {
+        qlen[e] = (act && len >= 2) ? len : 0;
+        fp[e] = fp_finish(sum, len);
+    }
+}
+
+// Sorted distinct parents of one hyperedge by a whole workgroup: a is a
+// power-of-two buffer (LDS for degree <= 8192, else global scratch).
+__device__ void block_unique_emit(int32_t *a, int n2, int32_t d, int32_t b, int32_t *qpins,
+                                  int32_t *len_out, uint64_t *sum_out)
+{
+    __shared__ int32_t ldsi[16];
+    __shared__ uint64_t ldsu[16];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    uint64_t sum = 0;
+    for (int base = 0; base < n2; base += blockDim.x) {
+        int i = base + threadIdx.x;
+        int32_t x = i < n2 ? a[i] : INT32_MAX;
+        bool first = i < d && (i == 0 || x != a[i - 1]);
+        int32_t tot;
+        int32_t ex = block_excl_scan((int32_t)first, ldsi, &tot);
+        if (first) {
+            qpins[b + carry + ex] = x;
+            sum += fp_term(x, 0);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    sum = block_sum(sum, ldsu);
+    *len_out = carry;
+    *sum_out = sum;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qbuild_block(int32_t count, const int32_t *list,
+                                                         const int32_t *off, const int32_t *pins,
+                                                         const int32_t *hseg,
+                                                         const uint8_t *sact,
+                                                         const int32_t *parent, int32_t *qpins,
+                                                         int32_t *qlen, uint64_t *fp)
+{
+    extern __shared__ int32_t dyn[];
+    int32_t e = list[blockIdx.x];
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (d > kBigMax) return;  // handled by k_qbuild_huge
+    if (!sact[hseg[e]]) {
+        if (threadIdx.x == 0) qlen[e] = 0;
+        return;
+    }
+    int n2 = next_pow2(d);
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) dyn[i] = i < d ? parent[pins[b + i]] : INT32_MAX;
+    __syncthreads();
+    block_bitonic_sort(dyn, n2);
+    int32_t len;
+    uint64_t sum;
+    block_unique_emit(dyn, n2, d, b, qpins, &len, &sum);
+    if (threadIdx.x == 0) {
+        qlen[e] = len >= 2 ? len : 0;
+        fp[e] = fp_finish(sum, len);
+    }
+}
+
+// Hyperedges above the LDS capacity: one launch each, sorted in global scratch.
+__global__ __launch_bounds__(1024) void k_qbuild_huge(const int32_t *lhuge, int32_t idx,
+                                                      const int32_t *off, const int32_t *pins,
+                                                      const int32_t *hseg, const uint8_t *sact,
+                                                      const int32_t *parent, int32_t *scratch,
+                                                      int32_t *qpins, int32_t *qlen, uint64_t *fp)
+{
+    int32_t e = lhuge[idx];
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (!sact[hseg[e]]) {
+        if (threadIdx.x == 0) qlen[e] = 0;
+        return;
+    }
+    int n2 = next_pow2(d);
+    for (int i = threadIdx.x; i < n2; i += blockDim.x) scratch[i] = i < d ? parent[pins[b + i]] : INT32_MAX;
+    __syncthreads();
+    block_bitonic_sort(scratch, n2);
+    int32_t len;
+    uint64_t sum;
+    block_unique_emit(scratch, n2, d, b, qpins, &len, &sum);
+    if (threadIdx.x == 0) {
+        qlen[e] = len >= 2 ? len : 0;
+        fp[e] = fp_finish(sum, len);
+    }
+}
+
+// Re-fingerprint with a new salt (only after a fingerprint collision between
+// different pin sets left hyperedges unresolved; practically never).
+__global__ void k_refingerprint(int32_t E, const int32_t *off, const int32_t *qpins,
+                                const int32_t *qlen, const int32_t *rep, uint64_t salt,
+                                uint64_t *fp)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E || rep[e] != -2) return;
+    uint64_t sum = 0;
+    int32_t len = qlen[e];
+    for (int i = 0; i < len; i++) sum += fp_term(qpins[off[e] + i], salt);
+    fp[e] = fp_finish(sum, len);
+}
+
+__global__ __launch_bounds__(kBlock) void k_dd_insert(int32_t E, const int32_t *qlen,
+                                                      const uint64_t *fp, const int32_t *rep,
+                                                      int only_unresolved,
+                                                      unsigned long long *tkeys, int32_t *tmin,
+                                                      int32_t tmask, int32_t *hslot)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E || qlen[e] < 2) return;
+    if (only_unresolved && rep[e] != -2) return;
+    unsigned long long f = fp[e];
+    uint32_t h = (uint32_t)(f ^ (f >> 32)) & (uint32_t)tmask;
+    for (;;) {
+        unsigned long long prev = atomicCAS(&tkeys[h], kEmptySlot, f);
+        if (prev == kEmptySlot || prev == f) break;
+        h = (h + 1) & (uint32_t)tmask;
+    }
+    atomicMin(&tmin[h], (int32_t)e);
+    hslot[e] = (int32_t)h;
+}
+
+__global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t *off,
+                                                       const int32_t *qpins, const int32_t *qlen,
+                                                       const int32_t *hw, const int32_t *hslot,
+                                                       const int32_t *tmin, int only_unresolved,
+                                                       int32_t *rep, int32_t *wsum,
+                                                       int32_t *unresolved)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t len = qlen[e];
+    if (only_unresolved) {
+        if (rep[e] != -2) return;
+    } else if (len < 2) {
+        rep[e] = -1;
+        return;
+    }
+    int32_t r = tmin[hslot[e]];
+    bool same = true;
+    if (r != e) {
+        same = qlen[r] == len;
+        const int32_t *a = qpins + off[e], *c = qpins + off[r];
+        for (int i = 0; same && i < len; i++) same = a[i] == c[i];
+    }
+    if (same) {
+        rep[e] = r;
+        atomicAdd(&wsum[r], hw[e]);
+    } else {
+        rep[e] = -2;
+        atomicAdd(unresolved, 1);
+    }
+}
+
+// Appends a hyperedge of the given degree to the schedule lists.
+__device__ __forceinline__ void classify_append(int32_t id, int32_t d, int32_t *lmid,
+                                                int32_t *lbig, int32_t *lhuge, int32_t *counters)
+{
+    if (d <= kSmallMax) return;
+    if (d <= kMidMax) {
+        lmid[atomicAdd(&counters[1], 1)] = id;
+    } else {
+        lbig[atomicAdd(&counters[2], 1)] = id;
+        if (d > kBigMax) lhuge[atomicAdd(&counters[3], 1)] = id;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_copy_pins(int32_t count, const int32_t *list,
+                                                      const int32_t *off, const int32_t *rep,
+                                                      const int32_t *qlen, const int32_t *qpins,
+                                                      const int32_t *hdst, int32_t *cpins)
+{
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e];
+    if (S == SMALL && off[e + 1] - b > kSmallMax) return;
+    if (rep[e] != e) return;
+    int32_t len = qlen[e], dst = hdst[e];
+    for (int i = lane; i < len; i += stride) cpins[dst + i] = qpins[b + i];
+}
+
+// Sizes of the coarse level, its segment tables and which segments continue.
+__global__ void k_level_fixup(int32_t S, int32_t N, int32_t E, const int32_t *nbase,
+                              const int32_t *hbase, const int32_t *cid, const int32_t *hb_tmp,
+                              const int32_t *totN, const uint64_t *totEP, int32_t level_next,
+                              int32_t max_levels, int32_t min_nodes, const uint8_t *sact,
+                              uint8_t *sact_next, int32_t *coarsest, int32_t *c_nbase, int32_t *c_hbase,
+                              int32_t *c_off, const int32_t *counters, LevelInfo *info)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t Nc = *totN;
+    int32_t Ec = (int32_t)(*totEP >> 32), Pc = (int32_t)(*totEP & 0xffffffffu);
+    c_off[Ec] = Pc;
+    c_hbase[S] = Ec;
+    for (int32_t s = S - 1; s >= 0; s--) c_hbase[s] = hbase[s] == hbase[s + 1] ? c_hbase[s + 1] : hb_tmp[s];
+    c_nbase[S] = Nc;
+    int32_t active = 0, maxn = 0;
+    for (int32_t s = 0; s < S; s++) {
+        c_nbase[s] = nbase[s] < N ? cid[nbase[s]] : Nc;
+    }
+    for (int32_t s = 0; s < S; s++) {
+        int32_t ns = c_nbase[s + 1] - c_nbase[s], es = c_hbase[s + 1] - c_hbase[s];
+        if (ns > maxn) maxn = ns;
+        bool go = false;
+        if (sact[s]) {
+            coarsest[s] = level_next;
+            go = level_next < max_levels && es > 0 && ns > min_nodes;
+            active += go ? 1 : 0;
+        }
+        sact_next[s] = go ? 1 : 0;
+    }
+    info->N = Nc;
+    info->E = Ec;
+    info->P = Pc;
+    info->nmid = counters[1];
+    info->nbig = counters[2];
+    info->nhuge = counters[3];
+    info->unresolved = counters[0];
+    info->active = active;
+    info->maxseg_nodes = maxn;
+}
+
+}  // namespace bp

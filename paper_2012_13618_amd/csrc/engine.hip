@@ -1,0 +1,1187 @@
+// Multilevel bisection engine and the C ABI (include/bipart.h).
+#include <cmath>
+
+#include "engine.hpp"
+
+namespace bp {
+
+// ---- one coarsening step ------------------------------------------------------
+
+void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
+                   Level &c)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    const int32_t N = f.N, E = f.E, P = f.P, S = f.S;
+    cx.pins_coarsened += P;
+    CoarsenBufs b;
+    b.key = ar.get<uint64_t>(N);
+    b.match = ar.get<int32_t>(N);
+    b.grp = ar.get<int32_t>(N);
+    b.cid = ar.get<int32_t>(N);
+    b.cnt = ar.get<int32_t>(E);
+    b.gw = ar.get<int32_t>(E);
+    b.lead = ar.get<int32_t>(E);
+    b.qpins = ar.get<int32_t>(P);
+    b.qlen = ar.get<int32_t>(E);
+    b.fp = ar.get<uint64_t>(E);
+    b.hslot = ar.get<int32_t>(E);
+    b.rep = ar.get<int32_t>(E);
+    b.wsum = ar.get<int32_t>(E);
+    b.hdst = ar.get<int32_t>(E);
+    b.hb_tmp = ar.get<int32_t>(S);
+    int64_t T = 1024;
+    while (T < 2 * (int64_t)E) T <<= 1;
+    b.tmask = (int32_t)(T - 1);
+    b.tkeys = ar.get<uint64_t>(T);
+    b.tmin = ar.get<int32_t>(T);
+    b.counters = ar.get<int32_t>(8);
+    b.totN = ar.get<int32_t>(1);
+    b.totEP = ar.get<uint64_t>(1);
+
+    f.parent = ar.get<int32_t>(N);
+    c.S = S;
+    c.nw = ar.get<int32_t>(N);
+    c.nseg = ar.get<int32_t>(N);
+    c.off = ar.get<int32_t>((int64_t)E + 1);
+    c.pins = ar.get<int32_t>(P);
+    c.hw = ar.get<int32_t>(E);
+    c.hseg = ar.get<int32_t>(E);
+    c.nbase = ar.get<int32_t>(S + 1);
+    c.hbase = ar.get<int32_t>(S + 1);
+    alloc_lists(ar, c, E);
+
+    int64_t initn = std::max<int64_t>(std::max<int64_t>(N, E), T);
+    launch(lc, "coarsen_init", 8.0 * N + 16.0 * E + 12.0 * T, k_coarsen_init,
+           std::min<int64_t>(ceil_div(initn, kBlock), 8192), kBlock, 0, N, E, T, b.key, b.grp,
+           c.nw, b.cnt, b.gw, b.lead, b.wsum, b.tkeys, b.tmin, b.counters);
+
+    // Algorithm 1
+    unsigned long long *key = (unsigned long long *)b.key;
+    double mbytes = 4.0 * E + 4.0 * P + 8.0 * N;
+    launch(lc, "match", mbytes, k_match<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+           (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
+           (const uint8_t *)sact, cx.prm.policy, key);
+    launch(lc, "match", 0.0, k_match<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
+           (const uint8_t *)sact, cx.prm.policy, key);
+    launch(lc, "match", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
+           (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
+           (const uint8_t *)sact, cx.prm.policy, key);
+    launch(lc, "decode", 16.0 * N, k_decode, ceil_div(N, kBlock), kBlock, 0, N,
+           (const uint64_t *)b.key, (const int32_t *)f.nseg, (const int32_t *)f.hbase,
+           (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
+
+    // Algorithm 2, singletons
+    launch(lc, "attach", 4.0 * E, k_attach<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+           (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
+           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
+    launch(lc, "attach", 0.0, k_attach<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
+           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
+    launch(lc, "attach", 0.0, k_attach<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
+           (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
+           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
+    launch(lc, "lead", 12.0 * N, k_lead, ceil_div(N, kBlock), kBlock, 0, N,
+           (const int32_t *)f.nseg, (const uint8_t *)sact, (const int32_t *)b.match,
+           (const int32_t *)b.cnt, b.grp, b.lead);
+
+    // coarse node ids: exclusive scan of leader flags
+    {
+        const int32_t *nseg = f.nseg, *grp = b.grp, *lead = b.lead;
+        const uint8_t *sa = sact;
+        int32_t *cid = b.cid;
+        scan<int32_t>(
+            lc, ar, "node_ids", N,
+            [=] __device__(int64_t v) -> int32_t {
+                if (!sa[nseg[v]]) return 0;
+                int32_t g = grp[v];
+                return (g < 0 || lead[g] == v) ? 1 : 0;
+            },
+            [=] __device__(int64_t v, int32_t ex, int32_t) { cid[v] = ex; }, b.totN);
+    }
+    launch(lc, "parent", 20.0 * N, k_parent, ceil_div(N, kBlock), kBlock, 0, N,
+           (const int32_t *)f.nseg, (const uint8_t *)sact, (const int32_t *)b.grp,
+           (const int32_t *)b.lead, (const int32_t *)b.cid, (const int32_t *)f.nw, f.parent, c.nw,
+           c.nseg);
+
+    // Algorithm 2, coarse hyperedges
+    launch(lc, "qbuild", 4.0 * E + 12.0 * P, k_qbuild_small, sched_grid<SMALL>(E), kBlock, 0, E,
+           (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
+           (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
+    launch(lc, "qbuild", 0.0, k_qbuild_wave, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins,
+           b.qlen, b.fp);
+    launch(lc, "qbuild", 0.0, k_qbuild_block, sched_grid<BLOCK>(f.nbig), kBlock,
+           (size_t)kBigMax * sizeof(int32_t), f.nbig, (const int32_t *)f.lbig,
+           (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
+           (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
+    if (f.nhuge > 0) {
+        b.huge_scratch = ar.get<int32_t>(next_pow2(P > 0 ? P : 1));
+        for (int32_t i = 0; i < f.nhuge; i++)
+            launch(lc, "qbuild_huge", 0.0, k_qbuild_huge, 1, 1024, 0, (const int32_t *)f.lhuge, i,
+                   (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
+                   (const uint8_t *)sact, (const int32_t *)f.parent, b.huge_scratch, b.qpins,
+                   b.qlen, b.fp);
+    }
+
+    // duplicate pin sets
+    launch(lc, "dedup", 16.0 * E, k_dd_insert, ceil_div(E, kBlock), kBlock, 0, E,
+           (const int32_t *)b.qlen, (const uint64_t *)b.fp, (const int32_t *)b.rep, 0,
+           (unsigned long long *)b.tkeys, b.tmin, b.tmask, b.hslot);
+    launch(lc, "dedup", 20.0 * E, k_dd_resolve, ceil_div(E, kBlock), kBlock, 0, E,
+           (const int32_t *)f.off, (const int32_t *)b.qpins, (const int32_t *)b.qlen,
+           (const int32_t *)f.hw, (const int32_t *)b.hslot, (const int32_t *)b.tmin, 0, b.rep,
+           b.wsum, b.counters);
+
+    auto compact = [&]() {
+        const int32_t *rep = b.rep, *qlen = b.qlen, *hseg = f.hseg, *hbase = f.hbase,
+                      *wsum = b.wsum;
+        int32_t *coff = c.off, *chw = c.hw, *chseg = c.hseg, *hdst = b.hdst, *hbt = b.hb_tmp;
+        int32_t *lmid = c.lmid, *lbig = c.lbig, *lhuge = c.lhuge, *ctr = b.counters;
+        scan<uint64_t>(
+            lc, ar, "hedge_ids", E,
+            [=] __device__(int64_t e) -> uint64_t {
+                return rep[e] == e ? ((1ull << 32) | (uint32_t)qlen[e]) : 0ull;
+            },
+            [=] __device__(int64_t e, uint64_t ex, uint64_t val) {
+                int32_t s = hseg[e];
+                if (e == hbase[s]) hbt[s] = (int32_t)(ex >> 32);
+                if (!val) return;
+                int32_t id = (int32_t)(ex >> 32);
+                coff[id] = (int32_t)ex;
+                chw[id] = wsum[e];
+                chseg[id] = s;
+                hdst[e] = (int32_t)ex;
+                classify_append(id, qlen[e], lmid, lbig, lhuge, ctr);
+            },
+            b.totEP);
+        launch(lc, "copy_pins", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+               (const int32_t *)nullptr, (const int32_t *)f.off, rep, qlen,
+               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
+        launch(lc, "copy_pins", 0.0, k_copy_pins<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+               (const int32_t *)f.lmid, (const int32_t *)f.off, rep, qlen,
+               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
+        launch(lc, "copy_pins", 0.0, k_copy_pins<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0,
+               f.nbig, (const int32_t *)f.lbig, (const int32_t *)f.off, rep, qlen,
+               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
+        launch(lc, "level_fixup", 0.0, k_level_fixup, 1, 1, 0, S, N, E, (const int32_t *)f.nbase,
+               (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
+               (const int32_t *)b.totN, (const uint64_t *)b.totEP, l + 1, cx.prm.max_levels,
+               cx.prm.min_coarse_nodes, (const uint8_t *)sact, sact_next, sg.coarsest, c.nbase,
+               c.hbase, c.off, (const int32_t *)b.counters, cx.info_d);
+    };
+    compact();
+    LevelInfo inf = cx.readback();
+    if (inf.unresolved > 0) {
+        // a fingerprint shared by different pin sets: re-hash the open ones
+        for (uint64_t salt = 1; inf.unresolved > 0; salt++) {
+            if (salt > 64) throw Error(BP_ERR_DEVICE, "duplicate check did not converge");
+            fill(lc, b.tkeys, T, kEmptySlot);
+            fill(lc, b.tmin, T, INT32_MAX);
+            fill(lc, b.counters, 8, 0);
+            launch(lc, "dedup", 0.0, k_refingerprint, ceil_div(E, kBlock), kBlock, 0, E,
+                   (const int32_t *)f.off, (const int32_t *)b.qpins, (const int32_t *)b.qlen,
+                   (const int32_t *)b.rep, salt * 0x9E3779B97F4A7C15ull, b.fp);
+            launch(lc, "dedup", 0.0, k_dd_insert, ceil_div(E, kBlock), kBlock, 0, E,
+                   (const int32_t *)b.qlen, (const uint64_t *)b.fp, (const int32_t *)b.rep, 1,
+                   (unsigned long long *)b.tkeys, b.tmin, b.tmask, b.hslot);
+            launch(lc, "dedup", 0.0, k_dd_resolve, ceil_div(E, kBlock), kBlock, 0, E,
+                   (const int32_t *)f.off, (const int32_t *)b.qpins, (const int32_t *)b.qlen,
+                   (const int32_t *)f.hw, (const int32_t *)b.hslot, (const int32_t *)b.tmin, 1,
+                   b.rep, b.wsum, b.counters);
+            launch(lc, "dedup", 0.0, k_level_fixup, 1, 1, 0, S, N, E, (const int32_t *)f.nbase,
+                   (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
+                   (const int32_t *)b.totN, (const uint64_t *)b.totEP, l + 1, cx.prm.max_levels,
+                   cx.prm.min_coarse_nodes, (const uint8_t *)sact, sact_next, sg.coarsest,
+                   c.nbase, c.hbase, c.off, (const int32_t *)b.counters, cx.info_d);
+            inf = cx.readback();
+        }
+        fill(lc, b.counters, 8, 0);
+        compact();
+        inf = cx.readback();
+    }
+    c.N = inf.N;
+    c.E = inf.E;
+    c.P = inf.P;
+    c.nmid = inf.nmid;
+    c.nbig = inf.nbig;
+    c.nhuge = inf.nhuge;
+    c.maxseg_nodes = inf.maxseg_nodes;
+    std::swap(sact, sact_next);
+}
+
+// ---- gains and selection -----------------------------------------------------------
+
+void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    cx.pins_refined += L.P;
+    fill(lc, gain, L.N, 0);
+    double bytes = 8.0 * L.E + 4.0 * L.P + 1.0 * L.N + 4.0 * L.N;
+    launch(lc, "gain", bytes, k_gain<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
+           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, gain);
+    launch(lc, "gain", 0.0, k_gain<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, gain);
+    launch(lc, "gain", 0.0, k_gain<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, gain);
+}
+
+void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    int32_t nl = 2 * L.S;
+    int64_t gh = ceil_div(L.N, kSelNodesPerBlock);
+    int64_t gp = ceil_div((int64_t)nl * 64, kBlock);
+    for (int pass = 0; pass < 8; pass++) {
+        launch(lc, "select_hist", 10.0 * L.N, k_sel_hist, gh, kBlock, 0, L.N, pass, gain,
+               (const uint8_t *)L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
+               (const uint64_t *)sg.prefix, (const uint8_t *)sg.ldone, sg.hist);
+        launch(lc, "select_pick", 0.0, k_sel_pick, gp, kBlock, 0, nl, pass, (const uint8_t *)sg.mode,
+               (const int32_t *)sg.m, sg.hist, sg.prefix, sg.rem, sg.rsel, sg.ldone, sg.thr);
+        if (pass == 0)
+            launch(lc, "select_clear", 0.0, k_sel_clear, std::min<int64_t>(ceil_div((int64_t)nl * 256, kBlock), 1024),
+                   kBlock, 0, (int64_t)nl * 256, sg.hist);
+    }
+}
+
+// ---- Algorithms 3 and 5 over all segments of a level ------------------------------
+
+static void initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    int64_t gs = ceil_div(L.S, kBlock);
+    int64_t rounds = 0;
+    for (int first = 1;; first = 0) {
+        // every round moves at least one node of each running segment
+        if (++rounds > (int64_t)L.N + 2) throw Error(BP_ERR_DEVICE, "initial bisection did not terminate");
+        cx.clear_info();
+        launch(lc, "mode", 0.0, k_mode_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
+               (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
+               (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1,
+               (const int32_t *)sg.rsel, first, sg.mode, sg.gmask, sg.m, cx.info_d);
+        if (cx.readback().flag == 0) break;
+        run_gains(cx, L, sg, gain);
+        run_select(cx, L, sg, gain);
+        launch(lc, "apply", 6.0 * L.N, k_apply_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+               (const int32_t *)gain, L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
+               (const int32_t *)sg.rsel, (const uint64_t *)sg.thr, (const int32_t *)L.nw,
+               (unsigned long long *)sg.w);
+    }
+}
+
+static void refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    int64_t gs = ceil_div(L.S, kBlock);
+    launch(lc, "mode", 0.0, k_mode_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
+           sg.mode, sg.gmask, sg.done);
+    for (int it = 0; it < cx.prm.refine_iters; it++) {
+        run_gains(cx, L, sg, gain);
+        run_select(cx, L, sg, gain);
+        launch(lc, "apply", 6.0 * L.N, k_apply_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+               (const int32_t *)gain, L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
+               (const int32_t *)sg.rsel, (const uint64_t *)sg.thr, (const int32_t *)L.nw,
+               (unsigned long long *)sg.w);
+    }
+    // balance step: every round moves at least one node or retires a segment
+    int64_t rounds = 0;
+    for (;;) {
+        if (++rounds > (int64_t)L.N + (int64_t)L.S + 2) throw Error(BP_ERR_DEVICE, "balance step did not terminate");
+        cx.clear_info();
+        launch(lc, "mode", 0.0, k_mode_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
+               (const unsigned long long *)sg.w, (const int64_t *)sg.max0,
+               (const int64_t *)sg.max1, sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room,
+               sg.ccount, cx.info_d);
+        if (cx.readback().flag == 0) break;
+        run_gains(cx, L, sg, gain);
+        run_select(cx, L, sg, gain);
+        launch(lc, "balance", 10.0 * L.N, k_bal_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+               (const int32_t *)gain, (const uint8_t *)L.side, (const int32_t *)L.nseg,
+               (const uint8_t *)sg.mode, (const int32_t *)sg.rsel, (const uint64_t *)sg.thr,
+               sg.ccount, sg.cand, sg.cand_stride);
+        int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
+        launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
+               (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
+               (const int32_t *)L.nw,
+               (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
+               (unsigned long long *)sg.w, sg.done, sg.stuck);
+    }
+}
+
+// ---- the multilevel bisection of every segment of a level-0 CSR ---------------------
+
+void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    std::vector<Level> lv;
+    lv.push_back(L0);
+    std::vector<int32_t> stops;  // segments whose coarsest level is l
+    stops.push_back(L0.S - active0);
+    uint8_t *sact = sg.active;
+    uint8_t *sact_next = ar.get<uint8_t>(L0.S);
+    int32_t active = active0;
+    int32_t l = 0;
+    while (active > 0) {
+        Level c;
+        coarsen_level(cx, lv[l], sg, sact, sact_next, l, c);
+        lv.push_back(c);
+        int32_t now = cx.info_h->active;
+        stops.push_back(active - now);
+        active = now;
+        l++;
+    }
+    if (cx.first_levels < 0) cx.first_levels = l;
+    int32_t Lmax = l;
+
+    // balance candidate buffers sized for the largest segment
+    int32_t maxn = 1;
+    for (auto &x : lv) maxn = std::max(maxn, x.maxseg_nodes);
+    int32_t mmax = (int32_t)ceil_sqrt_i64(maxn);
+    sg.cand_stride = next_pow2(std::max(mmax, 1));
+    sg.cand = ar.get<uint64_t>((int64_t)sg.S * sg.cand_stride);
+    int32_t *gain = ar.get<int32_t>(lv[0].N);
+    fill(lc, sg.hist, (int64_t)2 * sg.S * 256, 0u);
+    fill(lc, sg.rsel, (int64_t)2 * sg.S, 0);
+
+    for (int32_t j = Lmax; j >= 0; j--) {
+        Level &L = lv[j];
+        L.side = ar.get<uint8_t>(L.N);
+        launch(lc, "project", 6.0 * L.N, k_project, ceil_div(L.N, kBlock), kBlock, 0, L.N, j,
+               (const int32_t *)L.nseg, (const int32_t *)sg.coarsest,
+               (const int32_t *)(j < Lmax ? L.parent : nullptr),
+               (const uint8_t *)(j < Lmax ? lv[j + 1].side : nullptr), L.side);
+        fill(lc, sg.w, (int64_t)2 * sg.S, (int64_t)0);
+        launch(lc, "side_weights", 5.0 * L.N, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+               (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
+               (unsigned long long *)sg.w);
+        if (stops[j] > 0) initial_rounds(cx, L, sg, j, gain);
+        refine_level(cx, L, sg, j, gain);
+    }
+    L0.side = lv[0].side;
+}
+
+// ---- nested k-way --------------------------------------------------------------------
+
+struct TreeLevel {
+    Level L;
+    Segs sg;
+    int32_t *ksub;  // [S]
+    int32_t *orig;  // [N] input node id
+    int32_t active0;
+};
+
+static void seg_setup(Ctx &cx, TreeLevel &t, uint64_t F, const int32_t *k0_fixed = nullptr)
+{
+    LaunchCtx &lc = cx.lc;
+    Level &L = t.L;
+    fill(lc, t.sg.W, (int64_t)L.S, (int64_t)0);
+    launch(lc, "seg_setup", 8.0 * L.N, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)t.sg.W);
+    launch(lc, "seg_setup", 0.0, k_seg_setup, ceil_div(L.S, kBlock), kBlock, 0, L.S,
+           (const int32_t *)t.ksub, k0_fixed, (const int64_t *)t.sg.W, F, (const int32_t *)L.nbase,
+           (const int32_t *)L.hbase, cx.prm.max_levels, cx.prm.min_coarse_nodes, t.sg.k0, t.sg.k1,
+           t.sg.max0, t.sg.max1, t.sg.active, t.sg.coarsest, t.sg.stuck, cx.info_d);
+}
+
+// Children of every bisection of tree level t (cut-net splitting); final
+// children write their part id.  Returns false when no child continues.
+static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    Level &L = t.L;
+    const int32_t N = L.N, E = L.E, S = L.S;
+    int32_t *n1 = ar.get<int32_t>(E);
+    launch(lc, "extract", 4.0 * E + 5.0 * L.P, k_count_side1<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
+           E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const uint8_t *)L.side, n1);
+    launch(lc, "extract", 0.0, k_count_side1<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const uint8_t *)L.side, n1);
+    launch(lc, "extract", 0.0, k_count_side1<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const uint8_t *)L.side, n1);
+    uint64_t *nscan = ar.get<uint64_t>(N), *hs0 = ar.get<uint64_t>(E), *hs1 = ar.get<uint64_t>(E);
+    uint64_t *tots = ar.get<uint64_t>(3);
+    {
+        const uint8_t *side = L.side;
+        scan<uint64_t>(
+            lc, ar, "extract_scan", N,
+            [=] __device__(int64_t v) -> uint64_t { return side[v] ? (1ull << 32) : 1ull; },
+            [=] __device__(int64_t v, uint64_t ex, uint64_t) { nscan[v] = ex; }, tots);
+        const int32_t *off = L.off, *hseg = L.hseg, *k0 = t.sg.k0, *k1 = t.sg.k1, *cn1 = n1;
+        for (int sd = 0; sd < 2; sd++) {
+            uint64_t *hs = sd ? hs1 : hs0;
+            scan<uint64_t>(
+                lc, ar, "extract_scan", E,
+                [=] __device__(int64_t e) -> uint64_t {
+                    int32_t s = hseg[e];
+                    int32_t kk = sd ? k1[s] : k0[s];
+                    int32_t d = off[e + 1] - off[e];
+                    int32_t ns = sd ? cn1[e] : d - cn1[e];
+                    return (kk >= 2 && ns >= 2) ? ((1ull << 32) | (uint32_t)ns) : 0ull;
+                },
+                [=] __device__(int64_t e, uint64_t ex, uint64_t) { hs[e] = ex; }, tots + 1 + sd);
+        }
+    }
+    ChildTable ct;
+    ct.idx = ar.get<int32_t>(2 * S);
+    ct.nbase = ar.get<int32_t>(2 * S + 1);
+    ct.hbase = ar.get<int32_t>(2 * S + 1);
+    ct.pbase = ar.get<int32_t>(2 * S + 1);
+    ct.k = ar.get<int32_t>(2 * S);
+    ct.lo = ar.get<int32_t>(2 * S);
+    cx.clear_info();
+    launch(lc, "extract", 0.0, k_child_table, 1, 1, 0, S, N, E, (const int32_t *)L.nbase,
+           (const int32_t *)L.hbase, (const int32_t *)t.sg.k0, (const int32_t *)t.sg.k1,
+           (const int32_t *)t.sg.lo, (const uint64_t *)nscan, (const uint64_t *)hs0,
+           (const uint64_t *)hs1, (const uint64_t *)tots, (const uint64_t *)(tots + 1),
+           (const uint64_t *)(tots + 2), ct, cx.info_d);
+    LevelInfo inf = cx.readback();
+    int32_t C = inf.active;
+    Level &c = nx.L;
+    c.S = C;
+    c.N = inf.N;
+    c.E = inf.E;
+    c.P = inf.P;
+    int32_t *map = ar.get<int32_t>(N);
+    nx.orig = ar.get<int32_t>(c.N);
+    c.nw = ar.get<int32_t>(c.N);
+    c.nseg = ar.get<int32_t>(c.N);
+    launch(lc, "extract", 24.0 * N, k_extract_nodes, ceil_div(N, kBlock), kBlock, 0, N,
+           (const int32_t *)L.nseg, (const int32_t *)L.nbase, (const uint8_t *)L.side,
+           (const uint64_t *)nscan, (const int32_t *)t.orig, (const int32_t *)L.nw,
+           (const int32_t *)t.sg.k0, (const int32_t *)t.sg.lo, ct, map, nx.orig, c.nw, c.nseg,
+           d_part);
+    if (C == 0) return false;
+    c.off = ar.get<int32_t>((int64_t)c.E + 1);
+    c.pins = ar.get<int32_t>(c.P);
+    c.hw = ar.get<int32_t>(c.E);
+    c.hseg = ar.get<int32_t>(c.E);
+    launch(lc, "extract", 12.0 * E + 9.0 * L.P, k_extract_hedges<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
+           E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
+           (const uint64_t *)hs1, (const int32_t *)map, ct, c.off, c.pins, c.hw, c.hseg);
+    launch(lc, "extract", 0.0, k_extract_hedges<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
+           (const uint64_t *)hs1, (const int32_t *)map, ct, c.off, c.pins, c.hw, c.hseg);
+    launch(lc, "extract", 0.0, k_extract_hedges<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
+           (const uint64_t *)hs1, (const int32_t *)map, ct, c.off, c.pins, c.hw, c.hseg);
+    launch(lc, "extract", 4.0, k_set_i32, 1, 1, 0, c.off + c.E, c.P);
+    c.nbase = ct.nbase;
+    c.hbase = ct.hbase;
+    nx.ksub = ct.k;
+    nx.sg = alloc_segs(ar, C);
+    BP_HIP(hipMemcpyAsync(nx.sg.lo, ct.lo, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, lc.stream));
+    return true;
+}
+
+static void prepare_tree_level(Ctx &cx, TreeLevel &t, uint64_t F)
+{
+    int32_t *ctr = cx.ar->get<int32_t>(8);
+    fill(cx.lc, ctr, 8, 0);
+    classify(cx, t.L, ctr);
+    cx.clear_info();
+    seg_setup(cx, t, F);
+    // fold the schedule counts into the same readback
+    BP_HIP(hipMemcpyAsync(&cx.info_d->nmid, ctr + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                          cx.lc.stream));
+    LevelInfo inf = cx.readback();
+    t.L.nmid = inf.nmid;
+    t.L.nbig = inf.nbig;
+    t.L.nhuge = inf.nhuge;
+    t.L.maxseg_nodes = inf.maxseg_nodes;
+    t.active0 = inf.active;
+}
+
+uint64_t eps_factor(int32_t k, double eps)
+{
+    int32_t levels = 0;
+    while (((int64_t)1 << levels) < (int64_t)k) levels++;
+    if (levels < 1) levels = 1;
+    double f = std::pow(1.0 + eps, 1.0 / (double)levels);
+    return (uint64_t)std::floor(std::ldexp(f, 32));
+}
+
+struct CutResult {
+    int64_t cut = 0, maxw = 0, total_w = 0;
+};
+
+static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *nw_in, int32_t k,
+                             const int32_t *d_part)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    unsigned long long *acc = ar.get<unsigned long long>(4);
+    fill(lc, acc, 4, 0ull);
+    if (k <= 64) {
+        launch(lc, "cut", 8.0 * L.E + 8.0 * L.P, k_cut_mask<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0,
+               L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+        launch(lc, "cut", 0.0, k_cut_mask<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+               (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+        launch(lc, "cut", 0.0, k_cut_mask<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+               (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+    } else {
+        launch(lc, "cut", 8.0 * L.E + 8.0 * L.P, k_cut_general<SMALL>, sched_grid<SMALL>(L.E), kBlock,
+               0, L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+        launch(lc, "cut", 0.0, k_cut_general<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+               (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+        launch(lc, "cut", 0.0, k_cut_general<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+               (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+               (const int32_t *)L.hw, d_part, acc);
+    }
+    unsigned long long *pw = ar.get<unsigned long long>(k);
+    fill(lc, pw, k, 0ull);
+    launch(lc, "cut", 8.0 * N_nodes, k_part_weights, ceil_div(N_nodes, kBlock), kBlock, 0, N_nodes, k,
+           d_part, nw_in, pw);
+    launch(lc, "cut", 0.0, k_max_u64, 1, 1024, 0, k, (const unsigned long long *)pw, acc + 1);
+    BP_HIP(hipMemcpyAsync(cx.info_h, acc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, lc.stream));
+    cx.lc.sync();
+    CutResult r;
+    r.cut = (int64_t)((uint64_t *)cx.info_h)[0];
+    r.maxw = (int64_t)((uint64_t *)cx.info_h)[1];
+    return r;
+}
+
+// Checks the CSR and weight sums on the device; returns the node weight total.
+static int64_t validate_device(Ctx &cx, const Input &in)
+{
+    ValidateOut *vo = cx.ar->get<ValidateOut>(1);
+    fill(cx.lc, (int32_t *)vo, (int64_t)(sizeof(ValidateOut) / 4), 0);
+    int64_t work = std::max<int64_t>(std::max<int64_t>(in.N, in.E), 1);
+    launch(cx.lc, "validate", 0.0, k_validate, std::min<int64_t>(ceil_div(work, kBlock), 2048), kBlock, 0,
+           in.N, in.E, in.off, in.pins, in.nw, in.hw, vo);
+    BP_HIP(hipMemcpyAsync(cx.info_h, vo, sizeof(ValidateOut), hipMemcpyDeviceToHost, cx.lc.stream));
+    cx.lc.sync();
+    ValidateOut v = *(ValidateOut *)cx.info_h;
+    if (v.bad_offsets || v.bad_pins) throw Error(BP_ERR_INVALID_CSR, "invalid CSR (offsets or pin range)");
+    if (v.bad_weights) throw Error(BP_ERR_WEIGHT_OVERFLOW, "negative weight");
+    int64_t sn = in.nw ? (int64_t)v.sum_nw : in.N, sh = in.hw ? (int64_t)v.sum_hw : in.E;
+    if (sn >= (int64_t(1) << 31) || sh >= (int64_t(1) << 31))
+        throw Error(BP_ERR_WEIGHT_OVERFLOW, "weight sum >= 2^31");
+    return sn;
+}
+
+bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int32_t *d_part,
+                           int64_t *cut_out, bp_report *rep)
+{
+    LaunchCtx &lc = cx.lc;
+    int64_t W = validate_device(cx, in);
+    Level root = normalize(cx, in);
+    CutResult cr;
+    int32_t tree_levels = 0;
+    if (k == 1 || in.N == 0) {
+        fill(lc, d_part, in.N, 0);
+    } else {
+        uint64_t F = eps_factor(k, eps);
+        TreeLevel t;
+        t.L = root;
+        t.sg = alloc_segs(*cx.ar, 1);
+        t.ksub = cx.ar->get<int32_t>(1);
+        launch(lc, "seg_setup", 4.0, k_set_i32, 1, 1, 0, t.ksub, k);
+        fill(lc, t.sg.lo, 1, 0);
+        t.orig = cx.ar->get<int32_t>(in.N);
+        launch(lc, "seg_setup", 4.0 * in.N, k_iota, std::min<int64_t>(ceil_div(in.N, kBlock), 4096), kBlock,
+               0, (int64_t)in.N, t.orig);
+        prepare_tree_level(cx, t, F);
+        root.nmid = t.L.nmid;
+        root.nbig = t.L.nbig;
+        root.nhuge = t.L.nhuge;
+        for (;;) {
+            tree_levels++;
+            cx.bisections += t.L.S;
+            bisect_all(cx, t.L, t.sg, t.active0);
+            TreeLevel nx;
+            if (!extract(cx, t, d_part, nx)) break;
+            prepare_tree_level(cx, nx, F);
+            t = nx;
+        }
+    }
+    if (k > 1 && in.N > 0) cr = compute_cut(cx, root, in.N, in.nw, k, d_part);
+    else {
+        cr.cut = 0;
+        cr.maxw = W;
+    }
+    if (cut_out) *cut_out = cr.cut;
+    uint64_t F0 = (uint64_t)std::floor(std::ldexp(1.0 + eps, 32));
+    unsigned __int128 a = (unsigned __int128)(uint64_t)W * F0;
+    int64_t lim_f = (int64_t)(a / ((unsigned __int128)(uint64_t)k << 32));
+    int64_t lim_c = (W + k - 1) / k;
+    int64_t limit = std::max(lim_f, lim_c);
+    bool balanced = cr.maxw <= limit;
+    if (rep) {
+        rep->cut = cr.cut;
+        rep->max_part_weight = cr.maxw;
+        rep->part_weight_limit = limit;
+        rep->balanced = balanced ? 1 : 0;
+        rep->tree_levels = tree_levels;
+        rep->bisections = cx.bisections;
+        rep->coarsen_levels = cx.first_levels < 0 ? 0 : cx.first_levels;
+        rep->pins_coarsened = cx.pins_coarsened;
+        rep->pins_refined = cx.pins_refined;
+        rep->host_syncs = lc.syncs;
+        rep->kernel_launches = lc.launches;
+    }
+    return balanced ? BP_OK : BP_WARN_IMBALANCED;
+}
+
+// ---- context pool -------------------------------------------------------------------
+
+struct Pool {
+    std::mutex mu;
+    std::vector<Arena *> arenas;
+    std::vector<void *> pinned;
+    static Pool &get()
+    {
+        static Pool p;
+        return p;
+    }
+};
+
+struct CtxGuard {
+    Ctx cx;
+    CtxGuard(hipStream_t stream, const bp_params *p)
+    {
+        Pool &pl = Pool::get();
+        {
+            std::lock_guard<std::mutex> g(pl.mu);
+            if (!pl.arenas.empty()) {
+                cx.ar = pl.arenas.back();
+                pl.arenas.pop_back();
+            }
+            if (!pl.pinned.empty()) {
+                cx.info_h = (LevelInfo *)pl.pinned.back();
+                pl.pinned.pop_back();
+            }
+        }
+        if (!cx.ar) cx.ar = new Arena();
+        if (!cx.info_h) BP_HIP(hipHostMalloc((void **)&cx.info_h, 4096, hipHostMallocDefault));
+        cx.lc.stream = stream;
+        cx.lc.prof = Profiler::get().on;
+        cx.info_d = cx.ar->get<LevelInfo>(1);
+        bp_default_params(&cx.prm);
+        if (p) cx.prm = *p;
+    }
+    ~CtxGuard()
+    {
+        try {
+            cx.lc.flush();
+        } catch (...) {
+        }
+        // everything queued must finish before the arena is reused
+        (void)hipStreamSynchronize(cx.lc.stream);
+        cx.ar->reset();
+        Pool &pl = Pool::get();
+        std::lock_guard<std::mutex> g(pl.mu);
+        pl.arenas.push_back(cx.ar);
+        pl.pinned.push_back(cx.info_h);
+    }
+};
+
+}  // namespace bp
+
+// ==== C ABI ==============================================================================
+
+using namespace bp;
+
+static thread_local std::string g_last_error;
+
+static bp_status fail(bp_status s, const std::string &msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+#define BP_GUARD_BEGIN try {
+#define BP_GUARD_END                                                   \
+    }                                                                  \
+    catch (const bp::Error &e) { return fail(e.status, e.what()); }     \
+    catch (const std::exception &e) { return fail(BP_ERR_DEVICE, e.what()); }
+
+static bp_status check_params(const bp_params *p)
+{
+    if (!p) return BP_OK;
+    if (p->policy < BP_LDH || p->policy > BP_RAND || p->max_levels < 0 || p->max_levels > 1000 ||
+        p->refine_iters < 0 || p->min_coarse_nodes < 0)
+        return fail(BP_ERR_INVALID_ARG, "invalid bp_params");
+    return BP_OK;
+}
+
+// Host-side validation of a host CSR (including repeated pins).
+static bp_status validate_host(const bp_hypergraph *hg)
+{
+    if (!hg) return fail(BP_ERR_INVALID_ARG, "hypergraph is NULL");
+    int32_t N = hg->num_nodes, E = hg->num_hedges;
+    if (N < 0 || E < 0) return fail(BP_ERR_INVALID_ARG, "negative size");
+    if (!hg->hedge_offsets) return fail(BP_ERR_INVALID_ARG, "hedge_offsets is NULL");
+    const int32_t *off = hg->hedge_offsets;
+    if (off[0] != 0) return fail(BP_ERR_INVALID_CSR, "hedge_offsets[0] != 0");
+    for (int32_t e = 0; e < E; e++)
+        if (off[e + 1] < off[e]) return fail(BP_ERR_INVALID_CSR, "hedge_offsets not monotone");
+    int64_t P = off[E];
+    if (P > 0 && !hg->pins) return fail(BP_ERR_INVALID_ARG, "pins is NULL");
+    std::vector<int32_t> stamp(N > 0 ? N : 1, -1);
+    for (int32_t e = 0; e < E; e++)
+        for (int32_t i = off[e]; i < off[e + 1]; i++) {
+            int32_t v = hg->pins[i];
+            if (v < 0 || v >= N) return fail(BP_ERR_INVALID_CSR, "pin out of range");
+            if (stamp[v] == e) return fail(BP_ERR_INVALID_CSR, "node repeated in a hyperedge");
+            stamp[v] = e;
+        }
+    int64_t s = 0;
+    if (hg->node_weights)
+        for (int32_t v = 0; v < N; v++) {
+            if (hg->node_weights[v] < 0) return fail(BP_ERR_WEIGHT_OVERFLOW, "negative node weight");
+            s += hg->node_weights[v];
+        }
+    else
+        s = N;
+    if (s >= (int64_t(1) << 31)) return fail(BP_ERR_WEIGHT_OVERFLOW, "node weight sum >= 2^31");
+    s = 0;
+    if (hg->hedge_weights)
+        for (int32_t e = 0; e < E; e++) {
+            if (hg->hedge_weights[e] < 0) return fail(BP_ERR_WEIGHT_OVERFLOW, "negative hedge weight");
+            s += hg->hedge_weights[e];
+        }
+    else
+        s = E;
+    if (s >= (int64_t(1) << 31)) return fail(BP_ERR_WEIGHT_OVERFLOW, "hedge weight sum >= 2^31");
+    return BP_OK;
+}
+
+// Copies a host CSR into arena memory; returns the device view.
+static Input upload(Ctx &cx, const bp_hypergraph *hg)
+{
+    Input in;
+    in.N = hg->num_nodes;
+    in.E = hg->num_hedges;
+    int64_t P = hg->hedge_offsets[in.E];
+    int32_t *off = cx.ar->get<int32_t>((int64_t)in.E + 1);
+    int32_t *pins = cx.ar->get<int32_t>(P);
+    BP_HIP(hipMemcpyAsync(off, hg->hedge_offsets, sizeof(int32_t) * ((size_t)in.E + 1),
+                          hipMemcpyHostToDevice, cx.lc.stream));
+    if (P > 0)
+        BP_HIP(hipMemcpyAsync(pins, hg->pins, sizeof(int32_t) * (size_t)P, hipMemcpyHostToDevice,
+                              cx.lc.stream));
+    in.off = off;
+    in.pins = pins;
+    if (hg->node_weights) {
+        int32_t *nw = cx.ar->get<int32_t>(in.N);
+        BP_HIP(hipMemcpyAsync(nw, hg->node_weights, sizeof(int32_t) * (size_t)in.N,
+                              hipMemcpyHostToDevice, cx.lc.stream));
+        in.nw = nw;
+    }
+    if (hg->hedge_weights) {
+        int32_t *hw = cx.ar->get<int32_t>(in.E);
+        BP_HIP(hipMemcpyAsync(hw, hg->hedge_weights, sizeof(int32_t) * (size_t)in.E,
+                              hipMemcpyHostToDevice, cx.lc.stream));
+        in.hw = hw;
+    }
+    return in;
+}
+
+static Input device_input(const bp_hypergraph *hg)
+{
+    Input in;
+    in.N = hg->num_nodes;
+    in.E = hg->num_hedges;
+    in.off = hg->hedge_offsets;
+    in.pins = hg->pins;
+    in.nw = hg->node_weights;
+    in.hw = hg->hedge_weights;
+    return in;
+}
+
+static bp_status check_device_hg(const bp_hypergraph *hg)
+{
+    if (!hg) return fail(BP_ERR_INVALID_ARG, "hypergraph is NULL");
+    if (hg->num_nodes < 0 || hg->num_hedges < 0) return fail(BP_ERR_INVALID_ARG, "negative size");
+    if (!hg->hedge_offsets) return fail(BP_ERR_INVALID_ARG, "hedge_offsets is NULL");
+    if (!hg->pins && hg->num_hedges > 0) return fail(BP_ERR_INVALID_ARG, "pins is NULL");
+    return BP_OK;
+}
+
+extern "C" {
+
+void bp_default_params(bp_params *p)
+{
+    if (!p) return;
+    p->policy = BP_LDH;
+    p->max_levels = 25;
+    p->refine_iters = 2;
+    p->min_coarse_nodes = 100;
+}
+
+const char *bp_status_string(bp_status s)
+{
+    switch (s) {
+    case BP_OK: return "BP_OK";
+    case BP_WARN_IMBALANCED: return "BP_WARN_IMBALANCED";
+    case BP_ERR_INVALID_ARG: return "BP_ERR_INVALID_ARG";
+    case BP_ERR_INVALID_CSR: return "BP_ERR_INVALID_CSR";
+    case BP_ERR_WEIGHT_OVERFLOW: return "BP_ERR_WEIGHT_OVERFLOW";
+    case BP_ERR_OUT_OF_MEMORY: return "BP_ERR_OUT_OF_MEMORY";
+    case BP_ERR_DEVICE: return "BP_ERR_DEVICE";
+    case BP_ERR_REJECTED: return "BP_ERR_REJECTED";
+    case BP_ERR_SHUTDOWN: return "BP_ERR_SHUTDOWN";
+    case BP_ERR_NOT_FOUND: return "BP_ERR_NOT_FOUND";
+    default: return "BP_UNKNOWN_STATUS";
+    }
+}
+
+const char *bp_last_error(void) { return g_last_error.c_str(); }
+
+bp_status bp_partition(const bp_hypergraph *hg, int32_t k, double eps, const bp_params *params,
+                       int32_t *part_out, int64_t *cut_out, bp_report *report)
+{
+    bp_status st = validate_host(hg);
+    if (st != BP_OK) return st;
+    if ((st = check_params(params)) != BP_OK) return st;
+    if (k < 1 || !(eps >= 0.0) || std::isinf(eps)) return fail(BP_ERR_INVALID_ARG, "k < 1 or bad eps");
+    if (!part_out && hg->num_nodes > 0) return fail(BP_ERR_INVALID_ARG, "part_out is NULL");
+    BP_GUARD_BEGIN
+    CtxGuard g(nullptr, params);
+    Input in = upload(g.cx, hg);
+    int32_t *d_part = g.cx.ar->get<int32_t>(hg->num_nodes);
+    bp_status r = partition_device(g.cx, in, k, eps, d_part, cut_out, report);
+    if (hg->num_nodes > 0)
+        BP_HIP(hipMemcpyAsync(part_out, d_part, sizeof(int32_t) * (size_t)hg->num_nodes,
+                              hipMemcpyDeviceToHost, g.cx.lc.stream));
+    BP_HIP(hipStreamSynchronize(g.cx.lc.stream));
+    return r;
+    BP_GUARD_END
+}
+
+bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
+                              const bp_params *params, int32_t *d_part_out, int64_t *cut_out,
+                              bp_report *report, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if ((st = check_params(params)) != BP_OK) return st;
+    if (k < 1 || !(eps >= 0.0) || std::isinf(eps)) return fail(BP_ERR_INVALID_ARG, "k < 1 or bad eps");
+    if (!d_part_out && hg->num_nodes > 0) return fail(BP_ERR_INVALID_ARG, "d_part_out is NULL");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, params);
+    return partition_device(g.cx, device_input(hg), k, eps, d_part_out, cut_out, report);
+    BP_GUARD_END
+}
+
+bp_status bp_compute_cut_device(const bp_hypergraph *hg, int32_t k, const int32_t *d_part,
+                                int64_t *cut, int64_t *max_part_weight, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if (k < 1 || (!d_part && hg->num_nodes > 0)) return fail(BP_ERR_INVALID_ARG, "bad k or part");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Input in = device_input(hg);
+    validate_device(g.cx, in);
+    Level L = view_level(g.cx, in);
+    int32_t *ctr = g.cx.ar->get<int32_t>(8);
+    fill(g.cx.lc, ctr, 8, 0);
+    classify(g.cx, L, ctr);
+    BP_HIP(hipMemcpyAsync(g.cx.info_h, ctr, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, g.cx.lc.stream));
+    g.cx.lc.sync();
+    L.nmid = ((int32_t *)g.cx.info_h)[1];
+    L.nbig = ((int32_t *)g.cx.info_h)[2];
+    CutResult r = compute_cut(g.cx, L, in.N, in.nw, k, d_part);
+    if (cut) *cut = r.cut;
+    if (max_part_weight) *max_part_weight = r.maxw;
+    return BP_OK;
+    BP_GUARD_END
+}
+
+bp_status bp_compute_cut(const bp_hypergraph *hg, int32_t k, const int32_t *part, int64_t *cut,
+                         int64_t *max_part_weight)
+{
+    bp_status st = validate_host(hg);
+    if (st != BP_OK) return st;
+    if (k < 1 || (!part && hg->num_nodes > 0)) return fail(BP_ERR_INVALID_ARG, "bad k or part");
+    for (int32_t v = 0; v < hg->num_nodes; v++)
+        if (part[v] < 0 || part[v] >= k) return fail(BP_ERR_INVALID_ARG, "part id out of range");
+    BP_GUARD_BEGIN
+    CtxGuard g(nullptr, nullptr);
+    Input in = upload(g.cx, hg);
+    int32_t *d_part = g.cx.ar->get<int32_t>(hg->num_nodes);
+    if (hg->num_nodes > 0)
+        BP_HIP(hipMemcpyAsync(d_part, part, sizeof(int32_t) * (size_t)hg->num_nodes,
+                              hipMemcpyHostToDevice, g.cx.lc.stream));
+    Level L = view_level(g.cx, in);
+    int32_t *ctr = g.cx.ar->get<int32_t>(8);
+    fill(g.cx.lc, ctr, 8, 0);
+    classify(g.cx, L, ctr);
+    BP_HIP(hipMemcpyAsync(g.cx.info_h, ctr, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, g.cx.lc.stream));
+    g.cx.lc.sync();
+    L.nmid = ((int32_t *)g.cx.info_h)[1];
+    L.nbig = ((int32_t *)g.cx.info_h)[2];
+    CutResult r = compute_cut(g.cx, L, in.N, in.nw, k, d_part);
+    if (cut) *cut = r.cut;
+    if (max_part_weight) *max_part_weight = r.maxw;
+    return BP_OK;
+    BP_GUARD_END
+}
+
+// ---- single steps ----------------------------------------------------------------------
+
+// Prepares a one-segment level over the caller's device CSR with its schedule.
+static Level step_level(Ctx &cx, const bp_hypergraph *hg)
+{
+    Input in = device_input(hg);
+    Level L = view_level(cx, in);
+    int32_t *ctr = cx.ar->get<int32_t>(8);
+    fill(cx.lc, ctr, 8, 0);
+    classify(cx, L, ctr);
+    BP_HIP(hipMemcpyAsync(cx.info_h, ctr, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, cx.lc.stream));
+    cx.lc.sync();
+    L.nmid = ((int32_t *)cx.info_h)[1];
+    L.nbig = ((int32_t *)cx.info_h)[2];
+    L.nhuge = ((int32_t *)cx.info_h)[3];
+    L.maxseg_nodes = L.N;
+    return L;
+}
+
+bp_status bp_step_match(const bp_hypergraph *hg, int32_t policy, int32_t *d_match, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if (policy < BP_LDH || policy > BP_RAND) return fail(BP_ERR_INVALID_ARG, "bad policy");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Ctx &cx = g.cx;
+    cx.prm.policy = policy;
+    Level L = step_level(cx, hg);
+    uint8_t *sact = cx.ar->get<uint8_t>(1);
+    fill(cx.lc, sact, 1, (uint8_t)1);
+    uint64_t *key = cx.ar->get<uint64_t>(L.N);
+    int32_t *cnt = cx.ar->get<int32_t>(L.E), *gw = cx.ar->get<int32_t>(L.E);
+    fill(cx.lc, key, L.N, kNoKey);
+    unsigned long long *k = (unsigned long long *)key;
+    launch(cx.lc, "match", 0.0, k_match<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
+           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)sact, policy, k);
+    launch(cx.lc, "match", 0.0, k_match<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)sact, policy, k);
+    launch(cx.lc, "match", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
+           (const uint8_t *)sact, policy, k);
+    fill(cx.lc, cnt, L.E, 0);
+    fill(cx.lc, gw, L.E, 0);
+    launch(cx.lc, "decode", 0.0, k_decode, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           (const uint64_t *)key, (const int32_t *)L.nseg, (const int32_t *)L.hbase,
+           (const uint8_t *)sact, (const int32_t *)L.nw, d_match, cnt, gw);
+    return BP_OK;
+    BP_GUARD_END
+}
+
+bp_status bp_step_coarsen(const bp_hypergraph *hg, int32_t policy, int32_t *d_parent,
+                          int32_t *d_coarse_offsets, int32_t *d_coarse_pins,
+                          int32_t *d_coarse_node_w, int32_t *d_coarse_hedge_w,
+                          int32_t *coarse_nodes, int32_t *coarse_hedges, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if (policy < BP_LDH || policy > BP_RAND) return fail(BP_ERR_INVALID_ARG, "bad policy");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Ctx &cx = g.cx;
+    cx.prm.policy = policy;
+    cx.prm.max_levels = 1000;
+    cx.prm.min_coarse_nodes = 0;
+    Level L = step_level(cx, hg);
+    Segs sg = alloc_segs(*cx.ar, 1);
+    uint8_t *sact = sg.active, *sact_next = cx.ar->get<uint8_t>(1);
+    fill(cx.lc, sact, 1, (uint8_t)1);
+    Level c;
+    coarsen_level(cx, L, sg, sact, sact_next, 0, c);
+    hipStream_t s = cx.lc.stream;
+    if (L.N > 0) {
+        BP_HIP(hipMemcpyAsync(d_parent, L.parent, sizeof(int32_t) * L.N, hipMemcpyDeviceToDevice, s));
+        if (c.N > 0)
+            BP_HIP(hipMemcpyAsync(d_coarse_node_w, c.nw, sizeof(int32_t) * c.N, hipMemcpyDeviceToDevice, s));
+    }
+    BP_HIP(hipMemcpyAsync(d_coarse_offsets, c.off, sizeof(int32_t) * ((size_t)c.E + 1), hipMemcpyDeviceToDevice, s));
+    if (c.P > 0)
+        BP_HIP(hipMemcpyAsync(d_coarse_pins, c.pins, sizeof(int32_t) * c.P, hipMemcpyDeviceToDevice, s));
+    if (c.E > 0)
+        BP_HIP(hipMemcpyAsync(d_coarse_hedge_w, c.hw, sizeof(int32_t) * c.E, hipMemcpyDeviceToDevice, s));
+    if (coarse_nodes) *coarse_nodes = c.N;
+    if (coarse_hedges) *coarse_hedges = c.E;
+    return BP_OK;
+    BP_GUARD_END
+}
+
+bp_status bp_step_gains(const bp_hypergraph *hg, const uint8_t *d_side, int32_t *d_gain, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Ctx &cx = g.cx;
+    Level L = step_level(cx, hg);
+    Segs sg = alloc_segs(*cx.ar, 1);
+    fill(cx.lc, sg.gmask, 1, (uint8_t)1);
+    L.side = const_cast<uint8_t *>(d_side);
+    run_gains(cx, L, sg, d_gain);
+    return BP_OK;
+    BP_GUARD_END
+}
+
+// one segment of k0 : k1 with explicit bounds, for the initial/refine steps
+static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, int64_t max1)
+{
+    Segs sg = alloc_segs(*cx.ar, 1);
+    fill(cx.lc, sg.k0, 1, k0);
+    fill(cx.lc, sg.k1, 1, k1);
+    fill(cx.lc, sg.coarsest, 1, 0);
+    fill(cx.lc, sg.stuck, 1, 0);
+    fill(cx.lc, sg.max0, 1, max0);
+    fill(cx.lc, sg.max1, 1, max1);
+    fill(cx.lc, sg.hist, 512, 0u);
+    fill(cx.lc, sg.rsel, 2, 0);
+    fill(cx.lc, sg.W, 1, (int64_t)0);
+    launch(cx.lc, "seg_setup", 0.0, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)sg.W);
+    int32_t mm = (int32_t)ceil_sqrt_i64(L.N);
+    sg.cand_stride = next_pow2(std::max(mm, 1));
+    sg.cand = cx.ar->get<uint64_t>(sg.cand_stride);
+    return sg;
+}
+
+bp_status bp_step_initial(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint8_t *d_side, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if (k0 < 1 || k1 < 1) return fail(BP_ERR_INVALID_ARG, "k0, k1 must be >= 1");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Ctx &cx = g.cx;
+    Level L = step_level(cx, hg);
+    Segs sg = step_segs(cx, L, k0, k1, INT64_MAX, INT64_MAX);
+    L.side = d_side;
+    int32_t *gain = cx.ar->get<int32_t>(L.N);
+    launch(cx.lc, "project", 0.0, k_project, ceil_div(L.N, kBlock), kBlock, 0, L.N, 0,
+           (const int32_t *)L.nseg, (const int32_t *)sg.coarsest, (const int32_t *)nullptr,
+           (const uint8_t *)nullptr, L.side);
+    fill(cx.lc, sg.w, 2, (int64_t)0);
+    launch(cx.lc, "side_weights", 0.0, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
+           (unsigned long long *)sg.w);
+    initial_rounds(cx, L, sg, 0, gain);
+    return BP_OK;
+    BP_GUARD_END
+}
+
+bp_status bp_step_refine(const bp_hypergraph *hg, int32_t iters, int64_t max0, int64_t max1,
+                         uint8_t *d_side, int32_t *stuck, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if (iters < 0) return fail(BP_ERR_INVALID_ARG, "iters < 0");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    Ctx &cx = g.cx;
+    cx.prm.refine_iters = iters;
+    Level L = step_level(cx, hg);
+    Segs sg = step_segs(cx, L, 1, 1, max0, max1);
+    L.side = d_side;
+    int32_t *gain = cx.ar->get<int32_t>(L.N);
+    fill(cx.lc, sg.w, 2, (int64_t)0);
+    launch(cx.lc, "side_weights", 0.0, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
+           (unsigned long long *)sg.w);
+    refine_level(cx, L, sg, 0, gain);
+    BP_HIP(hipMemcpyAsync(cx.info_h, sg.stuck, sizeof(int32_t), hipMemcpyDeviceToHost, cx.lc.stream));
+    cx.lc.sync();
+    if (stuck) *stuck = *(int32_t *)cx.info_h;
+    return BP_OK;
+    BP_GUARD_END
+}
+
+bp_status bp_step_bisect(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint64_t F,
+                         const bp_params *params, uint8_t *d_side, int32_t *levels, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if ((st = check_params(params)) != BP_OK) return st;
+    if (k0 < 1 || k1 < 1) return fail(BP_ERR_INVALID_ARG, "k0, k1 must be >= 1");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, params);
+    Ctx &cx = g.cx;
+    Level L = step_level(cx, hg);
+    TreeLevel t;
+    t.L = L;
+    t.sg = alloc_segs(*cx.ar, 1);
+    t.ksub = cx.ar->get<int32_t>(1);
+    fill(cx.lc, t.ksub, 1, k0 + k1);
+    int32_t *k0_fixed = cx.ar->get<int32_t>(1);
+    fill(cx.lc, k0_fixed, 1, k0);
+    cx.clear_info();
+    seg_setup(cx, t, F, k0_fixed);
+    LevelInfo inf = cx.readback();
+    t.active0 = inf.active;
+    bisect_all(cx, t.L, t.sg, t.active0);
+    if (L.N > 0)
+        BP_HIP(hipMemcpyAsync(d_side, t.L.side, L.N, hipMemcpyDeviceToDevice, cx.lc.stream));
+    if (levels) *levels = cx.first_levels < 0 ? 0 : cx.first_levels;
+    return BP_OK;
+    BP_GUARD_END
+}
+
+// ---- profiling -----------------------------------------------------------------------
+
+void bp_profile_enable(int32_t on) { Profiler::get().on = on != 0; }
+
+void bp_profile_reset(void)
+{
+    Profiler &p = Profiler::get();
+    std::lock_guard<std::mutex> g(p.mu);
+    p.acc.clear();
+}
+
+int32_t bp_profile_read(bp_kernel_stat *out, int32_t cap)
+{
+    Profiler &p = Profiler::get();
+    std::lock_guard<std::mutex> g(p.mu);
+    int32_t n = (int32_t)p.acc.size();
+    for (int32_t i = 0; i < n && i < cap && out; i++) {
+        memset(&out[i], 0, sizeof(bp_kernel_stat));
+        strncpy(out[i].name, p.acc[i].name.c_str(), sizeof(out[i].name) - 1);
+        out[i].launches = p.acc[i].launches;
+        out[i].total_ms = p.acc[i].ms;
+        out[i].bytes = p.acc[i].bytes;
+    }
+    return n;
+}
+
+}  // extern "C"

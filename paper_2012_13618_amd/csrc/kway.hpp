@@ -1,0 +1,373 @@
+// Input normalisation, nested k-way subgraph extraction (Algorithm 6), the
+// connectivity-1 cut (problem statement) and device-side input validation.
+#pragma once
+#include "level.hpp"
+#include "scan.hpp"
+
+namespace bp {
+
+// ---- validation -----------------------------------------------------------------
+
+struct ValidateOut {
+    int32_t bad_offsets;
+    int32_t bad_pins;
+    int32_t bad_weights;
+    int32_t pad;
+    unsigned long long sum_nw, sum_hw;
+};
+
+__global__ __launch_bounds__(kBlock) void k_validate(int32_t N, int32_t E, const int32_t *off,
+                                                     const int32_t *pins, const int32_t *nw,
+                                                     const int32_t *hw, ValidateOut *out)
+{
+    __shared__ int64_t lds[16];
+    int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t P = off[E];
+    int64_t snw = 0, shw = 0;
+    int bo = 0, bp_ = 0, bw = 0;
+    for (int64_t e = tid; e < E; e += stride) {
+        if (off[e + 1] < off[e]) bo = 1;
+        if (hw) {
+            if (hw[e] < 0) bw = 1;
+            shw += hw[e];
+        }
+    }
+    if (tid == 0 && (off[0] != 0 || P < 0)) bo = 1;
+    for (int64_t i = tid; i < P && !bo; i += stride) {
+        int32_t v = pins[i];
+        if (v < 0 || v >= N) bp_ = 1;
+    }
+    for (int64_t v = tid; v < N; v += stride) {
+        if (nw) {
+            if (nw[v] < 0) bw = 1;
+            snw += nw[v];
+        }
+    }
+    snw = block_sum(snw, lds);
+    shw = block_sum(shw, lds);
+    if (bo) atomicOr(&out->bad_offsets, 1);
+    if (bp_) atomicOr(&out->bad_pins, 1);
+    if (bw) atomicOr(&out->bad_weights, 1);
+    if (threadIdx.x == 0) {
+        atomicAdd(&out->sum_nw, (unsigned long long)snw);
+        atomicAdd(&out->sum_hw, (unsigned long long)shw);
+    }
+}
+
+// ---- level 0: drop hyperedges that cannot be cut --------------------------------
+
+// copy the kept hyperedges' pins (degree >= 2) to their compacted place
+__global__ __launch_bounds__(kBlock) void k_norm_copy(int32_t E, const int32_t *off,
+                                                      const int32_t *pins, const int32_t *dst,
+                                                      int32_t *cpins)
+{
+    // one wavefront per hyperedge would waste lanes on degree-2 edges; instead
+    // each thread copies one hyperedge, long ones are split across the wave
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (d < 2) return;
+    int32_t o = dst[e];
+    for (int i = 0; i < d; i++) cpins[o + i] = pins[b + i];
+}
+
+__global__ void k_iota(int64_t n, int32_t *p)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+__global__ void k_copy_weights(int64_t n, const int32_t *src, int32_t *dst)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src ? src[i] : 1;
+}
+
+// Schedule lists of a freshly built level.
+__global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *off, int32_t *lmid,
+                                                     int32_t *lbig, int32_t *lhuge,
+                                                     int32_t *counters)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t d = off[e + 1] - off[e];
+    if (d <= kSmallMax) return;
+    if (d <= kMidMax) {
+        lmid[atomicAdd(&counters[1], 1)] = (int32_t)e;
+    } else {
+        lbig[atomicAdd(&counters[2], 1)] = (int32_t)e;
+        if (d > kBigMax) lhuge[atomicAdd(&counters[3], 1)] = (int32_t)e;
+    }
+}
+
+// ---- Algorithm 6: children of every bisection, by cut-net splitting -------------
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_count_side1(int32_t count, const int32_t *list,
+                                                        const int32_t *off, const int32_t *pins,
+                                                        const uint8_t *side, int32_t *n1out)
+{
+    __shared__ int32_t lds[16];
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    int32_t n1 = 0;
+    for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
+    n1 = group_sum<S>(n1, lds);
+    if (lane == 0) n1out[e] = n1;
+}
+
+// Child table: child (s, side) continues when it still has >= 2 parts.
+struct ChildTable {
+    int32_t *idx;     // [2S] child segment index or -1 (final part)
+    int32_t *nbase;   // [C+1]
+    int32_t *hbase;   // [C+1]
+    int32_t *pbase;   // [C+1]
+    int32_t *k;       // [C] parts of each child
+    int32_t *lo;      // [C]
+};
+
+__global__ void k_child_table(int32_t S, int32_t N, int32_t E, const int32_t *nbase,
+                              const int32_t *hbase, const int32_t *k0, const int32_t *k1,
+                              const int32_t *lo, const uint64_t *nscan, const uint64_t *hscan0,
+                              const uint64_t *hscan1, const uint64_t *ntot, const uint64_t *htot0,
+                              const uint64_t *htot1, ChildTable ct, LevelInfo *info)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int32_t c = 0, nb = 0, hb = 0, pb = 0;
+    auto at = [&](const uint64_t *scan, const uint64_t *tot, int32_t i, int32_t n) -> uint64_t {
+        return i < n ? scan[i] : *tot;
+    };
+    for (int32_t s = 0; s < S; s++) {
+        uint64_t na = at(nscan, ntot, nbase[s], N), nz = at(nscan, ntot, nbase[s + 1], N);
+        for (int sd = 0; sd < 2; sd++) {
+            int32_t kk = sd ? k1[s] : k0[s];
+            if (kk < 2) {
+                ct.idx[2 * s + sd] = -1;
+                continue;
+            }
+            const uint64_t *hs = sd ? hscan1 : hscan0;
+            const uint64_t *ht = sd ? htot1 : htot0;
+            uint64_t ha = at(hs, ht, hbase[s], E), hz = at(hs, ht, hbase[s + 1], E);
+            int32_t nn = sd ? (int32_t)((nz >> 32) - (na >> 32)) : (int32_t)((nz & 0xffffffffu) - (na & 0xffffffffu));
+            int32_t ne = (int32_t)((hz >> 32) - (ha >> 32));
+            int32_t np = (int32_t)((hz & 0xffffffffu) - (ha & 0xffffffffu));
+            ct.idx[2 * s + sd] = c;
+            ct.nbase[c] = nb;
+            ct.hbase[c] = hb;
+            ct.pbase[c] = pb;
+            ct.k[c] = kk;
+            ct.lo[c] = lo[s] + (sd ? k0[s] : 0);
+            nb += nn;
+            hb += ne;
+            pb += np;
+            c++;
+        }
+    }
+    ct.nbase[c] = nb;
+    ct.hbase[c] = hb;
+    ct.pbase[c] = pb;
+    info->N = nb;
+    info->E = hb;
+    info->P = pb;
+    info->active = c;
+}
+
+// nodes: renumber into their child, or write the final part id
+__global__ __launch_bounds__(kBlock) void k_extract_nodes(
+    int32_t N, const int32_t *nseg, const int32_t *nbase, const uint8_t *side,
+    const uint64_t *nscan, const int32_t *orig, const int32_t *nw, const int32_t *k0,
+    const int32_t *lo, ChildTable ct, int32_t *map, int32_t *c_orig, int32_t *c_nw,
+    int32_t *c_nseg, int32_t *part)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int32_t s = nseg[v], sd = side[v];
+    int32_t ci = ct.idx[2 * s + sd];
+    if (ci < 0) {
+        part[orig[v]] = lo[s] + (sd ? k0[s] : 0);
+        map[v] = -1;
+        return;
+    }
+    uint64_t a = nscan[v], z = nscan[nbase[s]];
+    int32_t rank = sd ? (int32_t)((a >> 32) - (z >> 32)) : (int32_t)((a & 0xffffffffu) - (z & 0xffffffffu));
+    int32_t id = ct.nbase[ci] + rank;
+    map[v] = id;
+    c_orig[id] = orig[v];
+    c_nw[id] = nw[v];
+    c_nseg[id] = ci;
+}
+
+// hyperedges: emit each side's part when it keeps >= 2 pins
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_extract_hedges(
+    int32_t count, const int32_t *list, const int32_t *off, const int32_t *pins,
+    const int32_t *hw, const int32_t *hseg, const int32_t *hbase, const uint8_t *side,
+    const int32_t *n1, const uint64_t *hscan0, const uint64_t *hscan1, const int32_t *map,
+    ChildTable ct, int32_t *c_off, int32_t *c_pins, int32_t *c_hw, int32_t *c_hseg)
+{
+    __shared__ int32_t lds[16];
+    __shared__ int32_t carry;
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    int32_t s = hseg[e];
+    int32_t cnt1 = n1[e];
+    for (int sd = 0; sd < 2; sd++) {
+        int32_t ci = ct.idx[2 * s + sd];
+        int32_t ns = sd ? cnt1 : d - cnt1;
+        if (ci < 0 || ns < 2) continue;  // uniform over the group
+        const uint64_t *hs = sd ? hscan1 : hscan0;
+        uint64_t a = hs[e], z = hs[hbase[s]];
+        int32_t id = ct.hbase[ci] + (int32_t)((a >> 32) - (z >> 32));
+        int32_t po = ct.pbase[ci] + (int32_t)((a & 0xffffffffu) - (z & 0xffffffffu));
+        if (lane == 0) {
+            c_off[id] = po;
+            c_hw[id] = hw[e];
+            c_hseg[id] = ci;
+        }
+        if (S == SMALL) {
+            int32_t k = 0;
+            for (int i = 0; i < d; i++) {
+                int32_t v = pins[b + i];
+                if (side[v] == sd) c_pins[po + k++] = map[v];
+            }
+        } else if (S == WAVE) {
+            int32_t base = 0;
+            for (int i0 = 0; i0 < d; i0 += 64) {
+                int i = i0 + lane;
+                int32_t v = i < d ? pins[b + i] : 0;
+                bool in = i < d && side[v] == sd;
+                unsigned long long m = __ballot(in);
+                if (in) c_pins[po + base + __popcll(m & ((1ull << lane) - 1))] = map[v];
+                base += __popcll(m);
+            }
+        } else {
+            if (threadIdx.x == 0) carry = 0;
+            __syncthreads();
+            for (int i0 = 0; i0 < d; i0 += blockDim.x) {
+                int i = i0 + threadIdx.x;
+                int32_t v = i < d ? pins[b + i] : 0;
+                int32_t in = (i < d && side[v] == sd) ? 1 : 0;
+                int32_t tot;
+                int32_t ex = block_excl_scan(in, lds, &tot);
+                if (in) c_pins[po + carry + ex] = map[v];
+                __syncthreads();
+                if (threadIdx.x == 0) carry += tot;
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// ---- connectivity-1 cut of the final partition ----------------------------------
+
+// k <= 64: a part-set bitmask per hyperedge.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_cut_mask(int32_t count, const int32_t *list,
+                                                     const int32_t *off, const int32_t *pins,
+                                                     const int32_t *hw, const int32_t *part,
+                                                     unsigned long long *cut)
+{
+    __shared__ unsigned long long lds[16];
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    int64_t contrib = 0;
+    if (e >= 0) {
+        int32_t b = off[e], d = off[e + 1] - b;
+        if (!(S == SMALL && d > kSmallMax)) {
+            unsigned long long m = 0;
+            for (int i = lane; i < d; i += stride) m |= 1ull << (part[pins[b + i]] & 63);
+            if (S == WAVE) {
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
+            } else if (S == BLOCK) {
+                // OR-reduce through LDS
+                __shared__ unsigned long long orl[16];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
+                if ((threadIdx.x & 63) == 0) orl[threadIdx.x >> 6] = m;
+                __syncthreads();
+                m = 0;
+                for (int i = 0; i < (int)(blockDim.x >> 6); i++) m |= orl[i];
+            }
+            int lam = __popcll(m);
+            if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+        }
+    }
+    if (S == SMALL) {
+        contrib = block_sum(contrib, (int64_t *)lds);
+        if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
+    } else if (lane == 0 && contrib) {
+        atomicAdd(cut, (unsigned long long)contrib);
+    }
+}
+
+// any k: per hyperedge, count parts not seen at an earlier pin (O(d^2) for the
+// rare large hyperedges; small ones sort parts in registers)
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_cut_general(int32_t count, const int32_t *list,
+                                                        const int32_t *off, const int32_t *pins,
+                                                        const int32_t *hw, const int32_t *part,
+                                                        unsigned long long *cut)
+{
+    __shared__ int64_t lds[16];
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    int64_t contrib = 0;
+    if (e >= 0) {
+        int32_t b = off[e], d = off[e + 1] - b;
+        if (!(S == SMALL && d > kSmallMax)) {
+            int32_t lam = 0;
+            for (int i = lane; i < d; i += stride) {
+                int32_t p = part[pins[b + i]];
+                bool first = true;
+                for (int j = 0; j < i && first; j++) first = part[pins[b + j]] != p;
+                lam += first ? 1 : 0;
+            }
+            lam = group_sum<S>(lam, (int32_t *)lds);
+            if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+        }
+    }
+    if (S == SMALL) {
+        contrib = block_sum(contrib, lds);
+        if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
+    } else if (lane == 0 && contrib) {
+        atomicAdd(cut, (unsigned long long)contrib);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_part_weights(int32_t N, int32_t k, const int32_t *part,
+                                                         const int32_t *nw,
+                                                         unsigned long long *pw)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N) return;
+    int32_t p = part[v];
+    if (p < 0 || p >= k) return;  // range is the caller's contract; never write outside pw
+    atomicAdd(&pw[p], (unsigned long long)(nw ? nw[v] : 1));
+}
+
+__global__ void k_max_u64(int32_t n, const unsigned long long *a, unsigned long long *out)
+{
+    __shared__ unsigned long long lds[16];
+    unsigned long long m = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) m = a[i] > m ? a[i] : m;
+    m = wave_max(m);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) r = lds[i] > r ? lds[i] : r;
+        *out = r;
+    }
+}
+
+}  // namespace bp

@@ -1,0 +1,72 @@
+// Device-resident hypergraph levels and per-segment state.
+//
+// A Level holds the disjoint union of S independent (sub)hypergraphs
+// ("segments") in one CSR: segment s owns nodes [nbase[s], nbase[s+1]) and
+// hyperedges [hbase[s], hbase[s+1]).  Node and hyperedge ids inside a segment
+// are ordered as in the segment's own numbering, so every comparison by id
+// and every hash of a local id gives the same result as if the segment were
+// partitioned alone (the nested k-way scheme of Algorithm 6).
+#pragma once
+#include "sched.hpp"
+
+namespace bp {
+
+struct Level {
+    int32_t N = 0, E = 0, P = 0, S = 0;
+    int32_t *off = nullptr;   // [E+1]
+    int32_t *pins = nullptr;  // [P]
+    int32_t *nw = nullptr;    // [N] node weights
+    int32_t *hw = nullptr;    // [E] hyperedge weights
+    int32_t *nseg = nullptr;  // [N] segment of each node
+    int32_t *hseg = nullptr;  // [E] segment of each hyperedge
+    int32_t *nbase = nullptr; // [S+1]
+    int32_t *hbase = nullptr; // [S+1]
+    // schedule lists (hyperedge ids) of the WAVE and BLOCK buckets; lhuge is
+    // the subset of lbig above the LDS sort capacity
+    int32_t *lmid = nullptr, *lbig = nullptr, *lhuge = nullptr;
+    int32_t nmid = 0, nbig = 0, nhuge = 0;
+    int32_t maxseg_nodes = 0;   // largest segment node count
+    int32_t *parent = nullptr;  // [N] -> ids of the next level, once coarsened
+    uint8_t *side = nullptr;    // [N] bisection side
+};
+
+// Sizes and counters read back once per level.
+struct LevelInfo {
+    int32_t N, E, P;
+    int32_t nmid, nbig, nhuge;
+    int32_t unresolved;     // duplicate-check collisions still open
+    int32_t active;         // segments that keep coarsening
+    int32_t maxseg_nodes;   // largest segment
+    int32_t flag;           // general-purpose count (rounds still running)
+    int32_t pad[6];
+};
+
+// Per-segment bisection state (device arrays; 2S entries where per side).
+struct Segs {
+    int32_t S = 0;
+    int32_t *k0, *k1;         // parts on each side of this bisection
+    int32_t *lo;              // first part id of the segment
+    int64_t *W;               // total node weight
+    int64_t *max0, *max1;     // side weight bounds
+    uint8_t *active;          // still coarsening
+    int32_t *coarsest;        // index of the coarsest level
+    int64_t *w;               // [2S] side weights at the current level
+    int32_t *cnt1;            // nodes on side 1 (initial bisection)
+    uint8_t *mode;            // selection mode (see refine.hpp)
+    uint8_t *gmask;           // segments whose gains are needed
+    int32_t *m;               // ceil(sqrt(nodes)) at the current level
+    int64_t *need, *room;     // balance step
+    uint8_t *done;
+    int32_t *stuck;           // balance stopped over the bound (any level)
+    int32_t *root_levels;     // coarsening steps
+    // radix-select state, per list (2S lists: segment x side)
+    uint32_t *hist;           // [2S * 256]
+    uint64_t *prefix, *thr;
+    int32_t *rem, *rsel;
+    uint8_t *ldone;
+    int32_t *ccount;          // balance candidates per segment
+    uint64_t *cand;           // [S * cand_stride]
+    int32_t cand_stride = 0;
+};
+
+}  // namespace bp

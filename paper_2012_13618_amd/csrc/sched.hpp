@@ -1,0 +1,128 @@
+// Degree-bucketed hyperedge schedules and block sorting helpers.
+//
+// A sweep over hyperedges runs as up to three launches: SMALL covers every
+// hyperedge of degree <= 8 with one thread each (the vast majority in
+// netlist and sparse-matrix hypergraphs), WAVE gives each listed hyperedge of
+// degree 9..256 a wavefront, BLOCK gives each listed larger hyperedge a
+// workgroup.  All per-pin updates are integer atomics (min/add), so results
+// do not depend on which schedule processed a hyperedge.
+#pragma once
+#include "common.hpp"
+
+namespace bp {
+
+enum Sched { SMALL = 0, WAVE = 1, BLOCK = 2 };
+
+// Hyperedge handled by this thread's group, or -1.  lane/stride give the
+// thread's position within the group.  For SMALL the caller still has to skip
+// hyperedges above kSmallMax.
+template <int S>
+__device__ __forceinline__ int32_t sched_hedge(int32_t count, const int32_t *list, int &lane,
+                                               int &stride)
+{
+    if (S == SMALL) {
+        int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        lane = 0;
+        stride = 1;
+        return e < count ? (int32_t)e : -1;
+    } else if (S == WAVE) {
+        int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        lane = threadIdx.x & 63;
+        stride = 64;
+        return w < count ? list[w] : -1;
+    } else {
+        lane = threadIdx.x;
+        stride = blockDim.x;
+        return blockIdx.x < (unsigned)count ? list[blockIdx.x] : -1;
+    }
+}
+
+template <int S> inline int64_t sched_grid(int64_t count)
+{
+    if (S == SMALL) return ceil_div(count, kBlock);
+    if (S == WAVE) return ceil_div(count, kBlock / kWave);
+    return count;
+}
+
+// Group-wide reductions matching the schedule (SMALL: the thread is the group).
+template <int S, typename T> __device__ __forceinline__ T group_sum(T v, T *lds)
+{
+    if (S == SMALL) return v;
+    if (S == WAVE) return wave_sum(v);
+    return block_sum(v, lds);
+}
+template <int S, typename T> __device__ __forceinline__ T group_min(T v, T *lds)
+{
+    if (S == SMALL) return v;
+    if (S == WAVE) return wave_min(v);
+    return block_min(v, lds);
+}
+
+// Ascending bitonic sort of n (a power of two) keys by the whole workgroup.
+// a may point to LDS or to global memory private to the workgroup.
+template <typename K> __device__ void block_bitonic_sort(K *a, int n)
+{
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                int p = i ^ j;
+                if (p > i) {
+                    K x = a[i], y = a[p];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Same, but each wavefront sorts its own n-key slice (n a power of two); the
+// loop shape is identical for every wave so a workgroup barrier can be used.
+template <typename K> __device__ void wave_bitonic_sort(K *a, int n)
+{
+    int lane = threadIdx.x & 63;
+    for (int k = 2; k <= n; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = lane; i < n; i += 64) {
+                int p = i ^ j;
+                if (p > i) {
+                    K x = a[i], y = a[p];
+                    bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        a[i] = y;
+                        a[p] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__host__ __device__ inline int next_pow2(int x)
+{
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+template <typename T> __global__ void k_fill(T *p, int64_t n, T v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+template <typename T> inline void fill(LaunchCtx &lc, T *p, int64_t n, T v)
+{
+    if (n <= 0) return;
+    int64_t g = ceil_div(n, kBlock);
+    if (g > 4096) g = 4096;
+    launch(lc, "fill", (double)n * sizeof(T), k_fill<T>, g, kBlock, 0, p, n, v);
+}
+
+}  // namespace bp

@@ -1,0 +1,76 @@
+"""CPU checks of the C ABI: the library loads, exports every declared entry
+point, and rejects bad input on the host before touching a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2012_13618_amd as bp
+from paper_2012_13618_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "bipart.h")).read()
+    return sorted(set(re.findall(r"\b(bp_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declarations_are_exported():
+    lib = bp.lib()
+    names = _declared()
+    assert len(names) >= 16
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(bp.EXPORTS) == names
+
+
+def test_default_params_and_status_strings():
+    p = bp.default_params()
+    assert (p.policy, p.max_levels, p.refine_iters, p.min_coarse_nodes) == (bp.LDH, 25, 2, 100)
+    for code, name in bp.STATUS.items():
+        assert bp.lib().bp_status_string(code).decode() == name
+
+
+def _expect(status, fn):
+    with pytest.raises(bp.BipartError) as ei:
+        fn()
+    assert ei.value.status == status, str(ei.value)
+
+
+def test_host_validation_errors():
+    h = I.random_small(20, 15, 2, 4, 0)
+    n, off, pins = h.num_nodes, h.offsets, h.pins
+    bad = off.copy()
+    bad[3] = bad[2] - 1
+    _expect(-2, lambda: bp.partition(n, bad, pins, 2, 0.05))
+    bad0 = off.copy()
+    bad0[0] = 1
+    _expect(-2, lambda: bp.partition(n, bad0, pins, 2, 0.05))
+    p2 = pins.copy()
+    p2[0] = n
+    _expect(-2, lambda: bp.partition(n, off, p2, 2, 0.05))
+    p3 = pins.copy()
+    p3[1] = p3[0]  # node repeated inside hyperedge 0
+    _expect(-2, lambda: bp.partition(n, off, p3, 2, 0.05))
+    _expect(-1, lambda: bp.partition(n, off, pins, 0, 0.05))
+    _expect(-1, lambda: bp.partition(n, off, pins, 2, -0.1))
+    _expect(-1, lambda: bp.partition(n, off, pins, 2, float("nan")))
+    _expect(-3, lambda: bp.partition(n, off, pins, 2, 0.05, nw=-np.ones(n, np.int32)))
+    _expect(-3, lambda: bp.partition(n, off, pins, 2, 0.05,
+                                     nw=np.full(n, 2 ** 30, np.int32)))
+    _expect(-3, lambda: bp.partition(n, off, pins, 2, 0.05,
+                                     hw=np.full(len(off) - 1, 2 ** 29, np.int32)))
+    _expect(-1, lambda: bp.partition(n, off, pins, 2, 0.05, prm=bp.params(policy=9)))
+    _expect(-1, lambda: bp.partition(n, off, pins, 2, 0.05, prm=bp.params(refine_iters=-1)))
+    _expect(-1, lambda: bp.compute_cut(n, off, pins, np.full(n, 5, np.int32), 2))
+
+
+def test_library_has_no_cpu_fallback():
+    # On a machine without a GPU the device work must fail loudly.
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = I.random_small(20, 15, 2, 4, 0)
+    _expect(-5, lambda: bp.partition(h.num_nodes, h.offsets, h.pins, 2, 0.05))
