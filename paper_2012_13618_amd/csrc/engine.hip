@@ -5,6 +5,13 @@
 
 namespace bp {
 
+// A sweep must never launch over a bucket whose list was not built.
+static void check_lists(const Level &L)
+{
+    if ((L.nmid > 0 && !L.lmid) || (L.nbig > 0 && !L.lbig) || (L.nhuge > 0 && !L.lhuge))
+        throw Error(BP_ERR_DEVICE, "internal: hyperedge schedule lists missing");
+}
+
 // ---- one coarsening step ------------------------------------------------------
 
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
@@ -13,6 +20,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     Arena &ar = *cx.ar;
     LaunchCtx &lc = cx.lc;
     const int32_t N = f.N, E = f.E, P = f.P, S = f.S;
+    check_lists(f);
     cx.pins_coarsened += P;
     CoarsenBufs b;
     b.key = ar.get<uint64_t>(N);
@@ -223,6 +231,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
 void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain)
 {
     LaunchCtx &lc = cx.lc;
+    check_lists(L);
     cx.pins_refined += L.P;
     fill(lc, gain, L.N, 0);
     double bytes = 8.0 * L.E + 4.0 * L.P + 1.0 * L.N + 4.0 * L.N;
@@ -406,6 +415,7 @@ static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
     LaunchCtx &lc = cx.lc;
     Level &L = t.L;
     const int32_t N = L.N, E = L.E, S = L.S;
+    check_lists(L);
     int32_t *n1 = ar.get<int32_t>(E);
     launch(lc, "extract", 4.0 * E + 5.0 * L.P, k_count_side1<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
            E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
@@ -533,6 +543,7 @@ static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *
 {
     Arena &ar = *cx.ar;
     LaunchCtx &lc = cx.lc;
+    check_lists(L);
     unsigned long long *acc = ar.get<unsigned long long>(4);
     fill(lc, acc, 4, 0ull);
     if (k <= 64) {
@@ -610,9 +621,7 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         launch(lc, "seg_setup", 4.0 * in.N, k_iota, std::min<int64_t>(ceil_div(in.N, kBlock), 4096), kBlock,
                0, (int64_t)in.N, t.orig);
         prepare_tree_level(cx, t, F);
-        root.nmid = t.L.nmid;
-        root.nbig = t.L.nbig;
-        root.nhuge = t.L.nhuge;
+        root = t.L;  // keep the schedule lists for the final cut
         for (;;) {
             tree_levels++;
             cx.bisections += t.L.S;

@@ -110,8 +110,8 @@ __global__ __launch_bounds__(kBlock) void k_sel_hist(int32_t N, int pass, const 
         int32_t c;
         uint64_t k;
         if (!sel_eligible(v, gain, side, nseg, mode, &c, &k)) continue;
-        if (ldone[c]) continue;
-        if (pass > 0 && ((k ^ prefix[c]) >> (shift + 8)) != 0) continue;
+        // pass 0 sees every eligible node; its pick resets the per-list state
+        if (pass > 0 && (ldone[c] || ((k ^ prefix[c]) >> (shift + 8)) != 0)) continue;
         int dig = (int)((k >> shift) & 0xff);
         if (use_lds) atomicAdd(&h[(c - cbase) * 256 + dig], 1u);
         else atomicAdd(&hist[(int64_t)c * 256 + dig], 1u);
