@@ -67,15 +67,15 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     // Algorithm 1
     unsigned long long *key = (unsigned long long *)b.key;
     double mbytes = 4.0 * E + 4.0 * P + 8.0 * N;
-    launch(lc, "match", mbytes, k_match<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+    launch(lc, "match_small", mbytes, k_match<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
            (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
            (const uint8_t *)sact, cx.prm.policy, key);
-    launch(lc, "match", 0.0, k_match<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+    launch(lc, "match_wave", 0.0, k_match<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
            (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
            (const uint8_t *)sact, cx.prm.policy, key);
-    launch(lc, "match", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
+    launch(lc, "match_block", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
            (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
            (const uint8_t *)sact, cx.prm.policy, key);
@@ -84,15 +84,15 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
            (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
 
     // Algorithm 2, singletons
-    launch(lc, "attach", 4.0 * E, k_attach<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+    launch(lc, "attach_small", 4.0 * E, k_attach<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
            (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
            (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
-    launch(lc, "attach", 0.0, k_attach<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+    launch(lc, "attach_wave", 0.0, k_attach<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
            (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
            (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
-    launch(lc, "attach", 0.0, k_attach<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
+    launch(lc, "attach_block", 0.0, k_attach<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
            (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
            (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
@@ -120,14 +120,14 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
            c.nseg);
 
     // Algorithm 2, coarse hyperedges
-    launch(lc, "qbuild", 4.0 * E + 12.0 * P, k_qbuild_small, sched_grid<SMALL>(E), kBlock, 0, E,
+    launch(lc, "qbuild_small", 4.0 * E + 12.0 * P, k_qbuild_small, sched_grid<SMALL>(E), kBlock, 0, E,
            (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
            (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
-    launch(lc, "qbuild", 0.0, k_qbuild_wave, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+    launch(lc, "qbuild_wave", 0.0, k_qbuild_wave, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
            (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins,
            b.qlen, b.fp);
-    launch(lc, "qbuild", 0.0, k_qbuild_block, sched_grid<BLOCK>(f.nbig), kBlock,
+    launch(lc, "qbuild_block", 0.0, k_qbuild_block, sched_grid<BLOCK>(f.nbig), kBlock,
            (size_t)kBigMax * sizeof(int32_t), f.nbig, (const int32_t *)f.lbig,
            (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
            (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
@@ -171,13 +171,13 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
                 classify_append(id, qlen[e], lmid, lbig, lhuge, ctr);
             },
             b.totEP);
-        launch(lc, "copy_pins", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+        launch(lc, "copy_pins_small", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
                (const int32_t *)nullptr, (const int32_t *)f.off, rep, qlen,
                (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
-        launch(lc, "copy_pins", 0.0, k_copy_pins<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
+        launch(lc, "copy_pins_wave", 0.0, k_copy_pins<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
                (const int32_t *)f.lmid, (const int32_t *)f.off, rep, qlen,
                (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
-        launch(lc, "copy_pins", 0.0, k_copy_pins<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0,
+        launch(lc, "copy_pins_block", 0.0, k_copy_pins<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0,
                f.nbig, (const int32_t *)f.lbig, (const int32_t *)f.off, rep, qlen,
                (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
         launch(lc, "level_fixup", 0.0, k_level_fixup, 1, 1, 0, S, N, E, (const int32_t *)f.nbase,
@@ -235,15 +235,15 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain)
     cx.pins_refined += L.P;
     fill(lc, gain, L.N, 0);
     double bytes = 8.0 * L.E + 4.0 * L.P + 1.0 * L.N + 4.0 * L.N;
-    launch(lc, "gain", bytes, k_gain<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
+    launch(lc, "gain_small", bytes, k_gain<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
            (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
            (const uint8_t *)L.side, gain);
-    launch(lc, "gain", 0.0, k_gain<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+    launch(lc, "gain_wave", 0.0, k_gain<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
            (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
            (const uint8_t *)L.side, gain);
-    launch(lc, "gain", 0.0, k_gain<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+    launch(lc, "gain_block", 0.0, k_gain<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
            (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
            (const uint8_t *)L.side, gain);
@@ -417,13 +417,13 @@ static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
     const int32_t N = L.N, E = L.E, S = L.S;
     check_lists(L);
     int32_t *n1 = ar.get<int32_t>(E);
-    launch(lc, "extract", 4.0 * E + 5.0 * L.P, k_count_side1<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
+    launch(lc, "extract_small", 4.0 * E + 5.0 * L.P, k_count_side1<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
            E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const uint8_t *)L.side, n1);
-    launch(lc, "extract", 0.0, k_count_side1<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+    launch(lc, "extract_wave", 0.0, k_count_side1<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
            (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const uint8_t *)L.side, n1);
-    launch(lc, "extract", 0.0, k_count_side1<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+    launch(lc, "extract_block", 0.0, k_count_side1<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
            (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const uint8_t *)L.side, n1);
     uint64_t *nscan = ar.get<uint64_t>(N), *hs0 = ar.get<uint64_t>(E), *hs1 = ar.get<uint64_t>(E);
@@ -483,17 +483,17 @@ static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
     c.pins = ar.get<int32_t>(c.P);
     c.hw = ar.get<int32_t>(c.E);
     c.hseg = ar.get<int32_t>(c.E);
-    launch(lc, "extract", 12.0 * E + 9.0 * L.P, k_extract_hedges<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
+    launch(lc, "extract_small", 12.0 * E + 9.0 * L.P, k_extract_hedges<SMALL>, sched_grid<SMALL>(E), kBlock, 0,
            E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
            (const uint64_t *)hs1, (const int32_t *)map, ct, c.off, c.pins, c.hw, c.hseg);
-    launch(lc, "extract", 0.0, k_extract_hedges<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+    launch(lc, "extract_wave", 0.0, k_extract_hedges<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
            (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
            (const uint64_t *)hs1, (const int32_t *)map, ct, c.off, c.pins, c.hw, c.hseg);
-    launch(lc, "extract", 0.0, k_extract_hedges<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+    launch(lc, "extract_block", 0.0, k_extract_hedges<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
            (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)L.side, (const int32_t *)n1, (const uint64_t *)hs0,
@@ -547,23 +547,23 @@ static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *
     unsigned long long *acc = ar.get<unsigned long long>(4);
     fill(lc, acc, 4, 0ull);
     if (k <= 64) {
-        launch(lc, "cut", 8.0 * L.E + 8.0 * L.P, k_cut_mask<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0,
+        launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut_mask<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0,
                L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut", 0.0, k_cut_mask<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+        launch(lc, "cut_wave", 0.0, k_cut_mask<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
                (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut", 0.0, k_cut_mask<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+        launch(lc, "cut_block", 0.0, k_cut_mask<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
                (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
     } else {
-        launch(lc, "cut", 8.0 * L.E + 8.0 * L.P, k_cut_general<SMALL>, sched_grid<SMALL>(L.E), kBlock,
+        launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut_general<SMALL>, sched_grid<SMALL>(L.E), kBlock,
                0, L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut", 0.0, k_cut_general<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+        launch(lc, "cut_wave", 0.0, k_cut_general<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
                (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut", 0.0, k_cut_general<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+        launch(lc, "cut_block", 0.0, k_cut_general<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
                (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
                (const int32_t *)L.hw, d_part, acc);
     }
@@ -992,15 +992,15 @@ bp_status bp_step_match(const bp_hypergraph *hg, int32_t policy, int32_t *d_matc
     int32_t *cnt = cx.ar->get<int32_t>(L.E), *gw = cx.ar->get<int32_t>(L.E);
     fill(cx.lc, key, L.N, kNoKey);
     unsigned long long *k = (unsigned long long *)key;
-    launch(cx.lc, "match", 0.0, k_match<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
+    launch(cx.lc, "match_small", 0.0, k_match<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
            (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)sact, policy, k);
-    launch(cx.lc, "match", 0.0, k_match<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+    launch(cx.lc, "match_wave", 0.0, k_match<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
            (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)sact, policy, k);
-    launch(cx.lc, "match", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+    launch(cx.lc, "match_block", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
            (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
            (const uint8_t *)sact, policy, k);
