@@ -1,9 +1,9 @@
 // One coarsening step over all active segments of a level (Algorithms 1, 2).
 //
 //  match     Algorithm 1: every node takes the 64-bit minimum of
-//            (priority << 32 | hash(local id + 1)) over its hyperedges with one
-//            atomicMin per pin; the hash is a bijection, so the winning
-//            hyperedge is decoded from the key itself.
+//            (priority << 32 | hash(local id + 1)) over its hyperedges (a
+//            per-node reduction over the node-major incidence); the hash is a
+//            bijection, so the winning hyperedge is decoded from the key.
 //  group     Algorithm 2, first loop: |S(e)| and the weight of S(e) by
 //            integer atomics; sets of two or more are merged.
 //  attach    Algorithm 2, second loop: a singleton joins the lightest merged
@@ -74,24 +74,6 @@ __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, i
         }
         if (i < 8) counters[i] = 0;
     }
-}
-
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_match(int32_t count, const int32_t *list,
-                                                  const int32_t *off, const int32_t *pins,
-                                                  const int32_t *hw, const int32_t *hseg,
-                                                  const int32_t *hbase, const uint8_t *sact,
-                                                  int policy, unsigned long long *key)
-{
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
-    if (e < 0) return;
-    int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
-    int32_t s = hseg[e];
-    if (!sact[s]) return;
-    unsigned long long K = hedge_key(policy, (uint32_t)(e - hbase[s]), d, hw[e]);
-    for (int i = lane; i < d; i += stride) atomicMin(&key[pins[b + i]], K);
 }
 
 __global__ __launch_bounds__(kBlock) void k_decode(int32_t N, const uint64_t *key,
@@ -427,17 +409,14 @@ __global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t 
     }
 }
 
-// Appends a hyperedge of the given degree to the schedule lists.
+// Appends a hyperedge of degree d (0 = none) to the schedule lists; every
+// active lane of the wavefront must call it.
 __device__ __forceinline__ void classify_append(int32_t id, int32_t d, int32_t *lmid,
                                                 int32_t *lbig, int32_t *lhuge, int32_t *counters)
 {
-    if (d <= kSmallMax) return;
-    if (d <= kMidMax) {
-        lmid[atomicAdd(&counters[1], 1)] = id;
-    } else {
-        lbig[atomicAdd(&counters[2], 1)] = id;
-        if (d > kBigMax) lhuge[atomicAdd(&counters[3], 1)] = id;
-    }
+    wave_append(d > kSmallMax && d <= kMidMax, id, lmid, &counters[1]);
+    wave_append(d > kMidMax, id, lbig, &counters[2]);
+    wave_append(d > kBigMax, id, lhuge, &counters[3]);
 }
 
 template <int S>

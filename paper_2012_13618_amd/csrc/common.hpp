@@ -344,6 +344,20 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds /* >= 16 */, T *total)
     return before + inc - v;
 }
 
+// Appends id to list for every active lane with take set, using one atomic
+// per wavefront.  Call from all active lanes (the ballot spans them).
+__device__ __forceinline__ void wave_append(bool take, int32_t id, int32_t *list, int32_t *counter)
+{
+    unsigned long long m = __ballot(take);
+    if (!m) return;
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1))] = id;
+}
+
 // Smallest m with m*m >= n.
 __host__ __device__ __forceinline__ int64_t ceil_sqrt_i64(int64_t n)
 {

@@ -64,21 +64,8 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
            std::min<int64_t>(ceil_div(initn, kBlock), 8192), kBlock, 0, N, E, T, b.key, b.grp,
            c.nw, b.cnt, b.gw, b.lead, b.wsum, b.tkeys, b.tmin, b.counters);
 
-    // Algorithm 1
-    unsigned long long *key = (unsigned long long *)b.key;
-    double mbytes = 4.0 * E + 4.0 * P + 8.0 * N;
-    launch(lc, "match_small", mbytes, k_match<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
-           (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
-           (const uint8_t *)sact, cx.prm.policy, key);
-    launch(lc, "match_wave", 0.0, k_match<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
-           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
-           (const uint8_t *)sact, cx.prm.policy, key);
-    launch(lc, "match_block", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
-           (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hw, (const int32_t *)f.hseg, (const int32_t *)f.hbase,
-           (const uint8_t *)sact, cx.prm.policy, key);
+    // Algorithm 1: per-node minimum over its own hyperedges' keys
+    run_match_keys(cx, f, sact, b.key);
     launch(lc, "decode", 16.0 * N, k_decode, ceil_div(N, kBlock), kBlock, 0, N,
            (const uint64_t *)b.key, (const int32_t *)f.nseg, (const int32_t *)f.hbase,
            (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
@@ -162,13 +149,14 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
             [=] __device__(int64_t e, uint64_t ex, uint64_t val) {
                 int32_t s = hseg[e];
                 if (e == hbase[s]) hbt[s] = (int32_t)(ex >> 32);
-                if (!val) return;
                 int32_t id = (int32_t)(ex >> 32);
-                coff[id] = (int32_t)ex;
-                chw[id] = wsum[e];
-                chseg[id] = s;
-                hdst[e] = (int32_t)ex;
-                classify_append(id, qlen[e], lmid, lbig, lhuge, ctr);
+                if (val) {
+                    coff[id] = (int32_t)ex;
+                    chw[id] = wsum[e];
+                    chseg[id] = s;
+                    hdst[e] = (int32_t)ex;
+                }
+                classify_append(id, val ? qlen[e] : 0, lmid, lbig, lhuge, ctr);
             },
             b.totEP);
         launch(lc, "copy_pins_small", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
@@ -224,6 +212,76 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     c.nhuge = inf.nhuge;
     c.maxseg_nodes = inf.maxseg_nodes;
     std::swap(sact, sact_next);
+    build_incidence(cx, c);
+}
+
+// ---- node-major incidence ------------------------------------------------------------
+
+void build_incidence(Ctx &cx, Level &L)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    check_lists(L);
+    const int32_t N = L.N, E = L.E, P = L.P;
+    uint32_t *k0 = ar.get<uint32_t>(P), *k1 = ar.get<uint32_t>(P);
+    int32_t *v0 = ar.get<int32_t>(P), *v1 = ar.get<int32_t>(P);
+    launch(lc, "incidence", 8.0 * P, k_expand_pairs<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
+           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
+    launch(lc, "incidence", 0.0, k_expand_pairs<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
+           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
+    launch(lc, "incidence", 0.0, k_expand_pairs<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)N) bits++;
+    int64_t ntiles = ceil_div(P > 0 ? P : 1, kRsTile);
+    uint32_t *counts = ar.get<uint32_t>(256 * ntiles), *offs = ar.get<uint32_t>(256 * ntiles);
+    uint32_t *tot = ar.get<uint32_t>(1);
+    for (int shift = 0; shift < bits && P > 0; shift += 8) {
+        launch(lc, "radix_hist", 4.0 * P, k_rs_hist, ntiles, kBlock, 0, (const uint32_t *)k0,
+               (int64_t)P, shift, counts, ntiles);
+        const uint32_t *cnt = counts;
+        uint32_t *of = offs;
+        scan<uint32_t>(
+            lc, ar, "radix_scan", 256 * ntiles, [=] __device__(int64_t i) -> uint32_t { return cnt[i]; },
+            [=] __device__(int64_t i, uint32_t ex, uint32_t) { of[i] = ex; }, tot);
+        launch(lc, "radix_scatter", 16.0 * P, k_rs_scatter, ntiles, kBlock, 0, (const uint32_t *)k0,
+               (const int32_t *)v0, (int64_t)P, shift, (const uint32_t *)offs, ntiles, k1, v1);
+        std::swap(k0, k1);
+        std::swap(v0, v1);
+    }
+    L.inc = v0;
+    L.noff = ar.get<int32_t>((int64_t)N + 1);
+    launch(lc, "incidence", 4.0 * N, k_node_offsets, ceil_div((int64_t)N + 1, kBlock), kBlock, 0,
+           (const uint32_t *)k0, (int64_t)P, N, L.noff);
+    L.nmid_bound = std::min<int64_t>(N, P / (kNodeSmallMax + 1)) + 1;
+    L.nbig_bound = std::min<int64_t>(N, P / (kNodeMidMax + 1)) + 1;
+    L.lnmid = ar.get<int32_t>(L.nmid_bound);
+    L.lnbig = ar.get<int32_t>(L.nbig_bound);
+    L.ncount = ar.get<int32_t>(2);
+    fill(lc, L.ncount, 2, 0);
+    launch(lc, "incidence", 8.0 * N, k_classify_nodes, ceil_div(N, kBlock), kBlock, 0, N,
+           (const int32_t *)L.noff, L.lnmid, L.lnbig, L.ncount);
+    L.cc = ar.get<int2>(E);
+}
+
+void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    uint64_t *hkey = ar.get<uint64_t>(L.E);
+    launch(lc, "hedge_keys", 20.0 * L.E, k_hedge_keys, ceil_div(L.E, kBlock), kBlock, 0, L.E,
+           (const int32_t *)L.off, (const int32_t *)L.hw, (const int32_t *)L.hseg,
+           (const int32_t *)L.hbase, sact, cx.prm.policy, hkey);
+    double bytes = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 8.0 * L.N;
+    launch(lc, "match_small", bytes, k_match_nodes<SMALL>, sched_grid<SMALL>(L.N), kBlock, 0, L.N,
+           (const int32_t *)L.ncount, (const int32_t *)nullptr, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
+    launch(lc, "match_wave", 0.0, k_match_nodes<WAVE>, sched_grid<WAVE>(L.nmid_bound), kBlock, 0, L.N,
+           (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
+    launch(lc, "match_block", 0.0, k_match_nodes<BLOCK>, sched_grid<BLOCK>(L.nbig_bound), kBlock, 0,
+           L.N, (const int32_t *)(L.ncount + 1), (const int32_t *)L.lnbig, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
 }
 
 // ---- gains and selection -----------------------------------------------------------
@@ -233,20 +291,34 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain)
     LaunchCtx &lc = cx.lc;
     check_lists(L);
     cx.pins_refined += L.P;
-    fill(lc, gain, L.N, 0);
-    double bytes = 8.0 * L.E + 4.0 * L.P + 1.0 * L.N + 4.0 * L.N;
-    launch(lc, "gain_small", bytes, k_gain<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
+    // hyperedge pass: what a pin on each side gains from its hyperedge
+    double hb = 8.0 * L.E + 4.0 * L.E + 4.0 * L.P + 1.0 * L.P + 8.0 * L.E;
+    launch(lc, "gain_hedge_small", hb, k_hedge_contrib<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
            (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, gain);
-    launch(lc, "gain_wave", 0.0, k_gain<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
-           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const uint8_t *)L.side, L.cc);
+    launch(lc, "gain_hedge_wave", 0.0, k_hedge_contrib<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0,
+           L.nmid, (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, gain);
-    launch(lc, "gain_block", 0.0, k_gain<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
-           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const uint8_t *)L.side, L.cc);
+    launch(lc, "gain_hedge_block", 0.0, k_hedge_contrib<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0,
+           L.nbig, (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, gain);
+           (const uint8_t *)L.side, L.cc);
+    // node pass: sum over the node's hyperedges
+    double nb = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 1.0 * L.N + 4.0 * L.N;
+    launch(lc, "gain_node_small", nb, k_node_gain<SMALL>, sched_grid<SMALL>(L.N), kBlock, 0, L.N,
+           (const int32_t *)L.ncount, (const int32_t *)nullptr, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
+    launch(lc, "gain_node_wave", 0.0, k_node_gain<WAVE>, sched_grid<WAVE>(L.nmid_bound), kBlock, 0, L.N,
+           (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
+    launch(lc, "gain_node_block", 0.0, k_node_gain<BLOCK>, sched_grid<BLOCK>(L.nbig_bound), kBlock, 0,
+           L.N, (const int32_t *)(L.ncount + 1), (const int32_t *)L.lnbig, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
+           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
 }
 
 void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain)
@@ -337,6 +409,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
 {
     Arena &ar = *cx.ar;
     LaunchCtx &lc = cx.lc;
+    if (!L0.noff) build_incidence(cx, L0);
     std::vector<Level> lv;
     lv.push_back(L0);
     std::vector<int32_t> stops;  // segments whose coarsest level is l
@@ -569,7 +642,8 @@ static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *
     }
     unsigned long long *pw = ar.get<unsigned long long>(k);
     fill(lc, pw, k, 0ull);
-    launch(lc, "cut", 8.0 * N_nodes, k_part_weights, ceil_div(N_nodes, kBlock), kBlock, 0, N_nodes, k,
+    launch(lc, "part_weights", 8.0 * N_nodes, k_part_weights,
+           std::max<int64_t>(1, std::min<int64_t>(ceil_div(N_nodes, kBlock), 1024)), kBlock, 0, N_nodes, k,
            d_part, nw_in, pw);
     launch(lc, "cut", 0.0, k_max_u64, 1, 1024, 0, k, (const unsigned long long *)pw, acc + 1);
     BP_HIP(hipMemcpyAsync(cx.info_h, acc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, lc.stream));
@@ -973,6 +1047,7 @@ static Level step_level(Ctx &cx, const bp_hypergraph *hg)
     L.nbig = ((int32_t *)cx.info_h)[2];
     L.nhuge = ((int32_t *)cx.info_h)[3];
     L.maxseg_nodes = L.N;
+    build_incidence(cx, L);
     return L;
 }
 
@@ -990,20 +1065,7 @@ bp_status bp_step_match(const bp_hypergraph *hg, int32_t policy, int32_t *d_matc
     fill(cx.lc, sact, 1, (uint8_t)1);
     uint64_t *key = cx.ar->get<uint64_t>(L.N);
     int32_t *cnt = cx.ar->get<int32_t>(L.E), *gw = cx.ar->get<int32_t>(L.E);
-    fill(cx.lc, key, L.N, kNoKey);
-    unsigned long long *k = (unsigned long long *)key;
-    launch(cx.lc, "match_small", 0.0, k_match<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
-           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
-           (const uint8_t *)sact, policy, k);
-    launch(cx.lc, "match_wave", 0.0, k_match<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
-           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
-           (const uint8_t *)sact, policy, k);
-    launch(cx.lc, "match_block", 0.0, k_match<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
-           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const int32_t *)L.hbase,
-           (const uint8_t *)sact, policy, k);
+    run_match_keys(cx, L, sact, key);
     fill(cx.lc, cnt, L.E, 0);
     fill(cx.lc, gw, L.E, 0);
     launch(cx.lc, "decode", 0.0, k_decode, ceil_div(L.N, kBlock), kBlock, 0, L.N,

@@ -3,6 +3,7 @@
 #include "coarsen.hpp"
 #include "kway.hpp"
 #include "refine.hpp"
+#include "transpose.hpp"
 
 namespace bp {
 
@@ -228,6 +229,8 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
 
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
                    Level &c);
+void build_incidence(Ctx &cx, Level &L);
+void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key);
 void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0);
 void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain);
 void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain);

@@ -92,15 +92,10 @@ __global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *o
                                                      int32_t *counters)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int32_t d = off[e + 1] - off[e];
-    if (d <= kSmallMax) return;
-    if (d <= kMidMax) {
-        lmid[atomicAdd(&counters[1], 1)] = (int32_t)e;
-    } else {
-        lbig[atomicAdd(&counters[2], 1)] = (int32_t)e;
-        if (d > kBigMax) lhuge[atomicAdd(&counters[3], 1)] = (int32_t)e;
-    }
+    int32_t d = e < E ? off[e + 1] - off[e] : 0;
+    wave_append(d > kSmallMax && d <= kMidMax, (int32_t)e, lmid, &counters[1]);
+    wave_append(d > kMidMax, (int32_t)e, lbig, &counters[2]);
+    wave_append(d > kBigMax, (int32_t)e, lhuge, &counters[3]);
 }
 
 // ---- Algorithm 6: children of every bisection, by cut-net splitting -------------
@@ -302,7 +297,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_mask(int32_t count, const int32_
             if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
         }
     }
-    if (S == SMALL) {
+    if (S != BLOCK) {
         contrib = block_sum(contrib, (int64_t *)lds);
         if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
     } else if (lane == 0 && contrib) {
@@ -336,7 +331,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_general(int32_t count, const int
             if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
         }
     }
-    if (S == SMALL) {
+    if (S != BLOCK) {
         contrib = block_sum(contrib, lds);
         if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
     } else if (lane == 0 && contrib) {
@@ -344,15 +339,47 @@ __global__ __launch_bounds__(kBlock) void k_cut_general(int32_t count, const int
     }
 }
 
+// Part weights: registers for k <= 8, an LDS histogram for k <= 4096, else
+// global atomics; one global atomic per part per workgroup otherwise.
 __global__ __launch_bounds__(kBlock) void k_part_weights(int32_t N, int32_t k, const int32_t *part,
                                                          const int32_t *nw,
                                                          unsigned long long *pw)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= N) return;
-    int32_t p = part[v];
-    if (p < 0 || p >= k) return;  // range is the caller's contract; never write outside pw
-    atomicAdd(&pw[p], (unsigned long long)(nw ? nw[v] : 1));
+    __shared__ unsigned long long acc[4096];
+    __shared__ int64_t lds[16];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (k <= 8) {
+        int64_t r[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+            int32_t p = part[v];
+            int64_t w = nw ? nw[v] : 1;
+#pragma unroll
+            for (int j = 0; j < 8; j++) r[j] += p == j ? w : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int64_t t = block_sum(r[j], lds);
+            if (threadIdx.x == 0 && j < k && t) atomicAdd(&pw[j], (unsigned long long)t);
+        }
+        return;
+    }
+    bool in_lds = k <= 4096;
+    if (in_lds) {
+        for (int i = threadIdx.x; i < k; i += blockDim.x) acc[i] = 0;
+        __syncthreads();
+    }
+    for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += stride) {
+        int32_t p = part[v];
+        if (p < 0 || p >= k) continue;  // range is the caller's contract; never write outside
+        unsigned long long w = (unsigned long long)(nw ? nw[v] : 1);
+        if (in_lds) atomicAdd(&acc[p], w);
+        else atomicAdd(&pw[p], w);
+    }
+    if (in_lds) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < k; i += blockDim.x)
+            if (acc[i]) atomicAdd(&pw[i], acc[i]);
+    }
 }
 
 __global__ void k_max_u64(int32_t n, const unsigned long long *a, unsigned long long *out)

@@ -28,6 +28,13 @@ struct Level {
     int32_t maxseg_nodes = 0;   // largest segment node count
     int32_t *parent = nullptr;  // [N] -> ids of the next level, once coarsened
     uint8_t *side = nullptr;    // [N] bisection side
+    // node-major incidence: hyperedges of node v are inc[noff[v] .. noff[v+1])
+    int32_t *noff = nullptr;    // [N+1]
+    int32_t *inc = nullptr;     // [P]
+    int32_t *lnmid = nullptr, *lnbig = nullptr;  // node buckets (degree > 32, > 2048)
+    int32_t *ncount = nullptr;  // device: [0] = |lnmid|, [1] = |lnbig|
+    int64_t nmid_bound = 0, nbig_bound = 0;      // grid bounds for the node buckets
+    int2 *cc = nullptr;         // [E] per-hyperedge gain contributions (scratch)
 };
 
 // Sizes and counters read back once per level.

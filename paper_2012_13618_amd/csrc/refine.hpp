@@ -1,9 +1,9 @@
 // Initial bisection, gains, swap refinement and balancing (Algorithms 3-5).
 //
-// Gains (Algorithm 4) are one sweep over the hyperedges of the segments in
-// play: per hyperedge the number of pins on side 1 (a group reduction), then
-// +w(e) to a pin alone on its side and -w(e) to every pin of an uncut
-// hyperedge, by integer atomicAdd.
+// Gains (Algorithm 4) are computed in transpose.hpp: a hyperedge pass finds
+// what a pin on each side gains from the hyperedge (+w(e) when it is alone on
+// its side, -w(e) when the hyperedge is uncut), a node pass sums that over the
+// node's hyperedges.
 //
 // Every "pick the r best nodes in (gain desc, id asc) order" step - the
 // ceil(sqrt n) moves of Algorithm 3, the two sorted lists of Algorithm 5 and
@@ -19,56 +19,6 @@ namespace bp {
 
 // selection mode bits per segment
 constexpr uint8_t kList0 = 1, kList1 = 2, kGainNonNeg = 4, kMinPair = 8;
-
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_gain(int32_t count, const int32_t *list,
-                                                 const int32_t *off, const int32_t *pins,
-                                                 const int32_t *hw, const int32_t *hseg,
-                                                 const uint8_t *gmask, const uint8_t *side,
-                                                 int32_t *gain)
-{
-    __shared__ int32_t lds[16];
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
-    if (e < 0) return;
-    int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
-    if (!gmask[hseg[e]]) return;
-    int32_t w = hw[e];
-    if (S == SMALL) {
-        int32_t p[kSmallMax];
-        uint8_t sd[kSmallMax];
-        int32_t n1 = 0;
-#pragma unroll
-        for (int i = 0; i < kSmallMax; i++) {
-            if (i < d) {
-                p[i] = pins[b + i];
-                sd[i] = side[p[i]];
-                n1 += sd[i];
-            }
-        }
-        int32_t n0 = d - n1;
-#pragma unroll
-        for (int i = 0; i < kSmallMax; i++) {
-            if (i < d) {
-                int32_t ni = sd[i] ? n1 : n0;
-                int32_t delta = ni == 1 ? w : (ni == d ? -w : 0);
-                if (delta) atomicAdd(&gain[p[i]], delta);
-            }
-        }
-    } else {
-        int32_t n1 = 0;
-        for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
-        n1 = group_sum<S>(n1, lds);
-        int32_t n0 = d - n1;
-        for (int i = lane; i < d; i += stride) {
-            int32_t v = pins[b + i];
-            int32_t ni = side[v] ? n1 : n0;
-            int32_t delta = ni == 1 ? w : (ni == d ? -w : 0);
-            if (delta) atomicAdd(&gain[v], delta);
-        }
-    }
-}
 
 // ---- segmented radix select ---------------------------------------------------
 

@@ -1,0 +1,235 @@
+// Node-major incidence of a level: for every node, the ascending list of its
+// hyperedges (the bipartite graph of Section 1.1 read from the node side).
+//
+// Built by a stable LSD radix sort of (node id, hyperedge id) pairs taken in
+// pin order, 8-bit digits: per-tile digit histograms, one prefix scan of the
+// (digit, tile) counts, and a stable scatter whose in-tile ranks come from
+// wavefront ballots.  Node offsets are binary searches into the sorted keys.
+//
+// With it, the per-node steps - the 64-bit minimum of Algorithm 1 and the gain
+// sum of Algorithm 4 - are gathers over a node's own hyperedges with no
+// atomics, so a node contained in very many hyperedges (a heavy coarse node)
+// is summed by one workgroup instead of receiving that many atomic updates.
+#pragma once
+#include "level.hpp"
+#include "scan.hpp"
+
+namespace bp {
+
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kBlock * kRsItems;   // 4096 pairs per tile
+constexpr int kNodeSmallMax = 32;            // node degree: one thread
+constexpr int kNodeMidMax = 2048;            // one wavefront; above: one workgroup
+
+__global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, int64_t n, int shift,
+                                                    uint32_t *counts, int64_t ntiles)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+    for (int r = 0; r < kRsItems; r++) {
+        int64_t i = base + r * kBlock + threadIdx.x;
+        if (i < n) atomicAdd(&h[(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// Stable scatter of one tile.  Items are taken round by round (item r*256+t
+// of the tile in round r), which is their original order.
+__global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, const int32_t *vin,
+                                                       int64_t n, int shift,
+                                                       const uint32_t *offs, int64_t ntiles,
+                                                       uint32_t *kout, int32_t *vout)
+{
+    __shared__ uint32_t base[256], run[256];
+    __shared__ uint32_t wcnt[kBlock / 64][256];
+    int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    base[t] = offs[(int64_t)t * ntiles + blockIdx.x];
+    run[t] = 0;
+    unsigned long long below = (1ull << lane) - 1;
+    int64_t tile = (int64_t)blockIdx.x * kRsTile;
+    for (int r = 0; r < kRsItems; r++) {
+        for (int j = t; j < (kBlock / 64) * 256; j += kBlock) (&wcnt[0][0])[j] = 0;
+        int64_t i = tile + r * kBlock + t;
+        bool valid = i < n;
+        uint32_t key = valid ? kin[i] : 0u;
+        int32_t val = valid ? vin[i] : 0;
+        uint32_t dig = (key >> shift) & 255u;
+        // lanes holding the same digit
+        unsigned long long same = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            unsigned long long m = __ballot((dig >> b) & 1u);
+            same &= ((dig >> b) & 1u) ? m : ~m;
+        }
+        int rank = __popcll(same & below);
+        __syncthreads();  // wcnt cleared, base/run visible
+        if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int x = 0; x < w; x++) pre += wcnt[x][dig];
+            uint32_t pos = base[dig] + run[dig] + pre + (uint32_t)rank;
+            kout[pos] = key;
+            vout[pos] = val;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+#pragma unroll
+        for (int x = 0; x < kBlock / 64; x++) add += wcnt[x][t];
+        run[t] += add;
+        __syncthreads();
+    }
+}
+
+// pins -> (node, hyperedge) pairs in pin order
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_expand_pairs(int32_t count, const int32_t *list,
+                                                         const int32_t *off, const int32_t *pins,
+                                                         uint32_t *keys, int32_t *vals)
+{
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    for (int i = lane; i < d; i += stride) {
+        keys[b + i] = (uint32_t)pins[b + i];
+        vals[b + i] = e;
+    }
+}
+
+// noff[v] = first position of node v in the sorted keys (lower bound)
+__global__ __launch_bounds__(kBlock) void k_node_offsets(const uint32_t *keys, int64_t P,
+                                                         int32_t N, int32_t *noff)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v > N) return;
+    int64_t lo = 0, hi = P;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < v) lo = mid + 1;
+        else hi = mid;
+    }
+    noff[v] = (int32_t)lo;
+}
+
+__global__ __launch_bounds__(kBlock) void k_classify_nodes(int32_t N, const int32_t *noff,
+                                                           int32_t *lmid, int32_t *lbig,
+                                                           int32_t *counters)
+{
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t d = v < N ? noff[v + 1] - noff[v] : 0;
+    wave_append(d > kNodeSmallMax && d <= kNodeMidMax, (int32_t)v, lmid, &counters[0]);
+    wave_append(d > kNodeMidMax, (int32_t)v, lbig, &counters[1]);
+}
+
+// ---- Algorithm 1, node side ------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_hedge_keys(int32_t E, const int32_t *off,
+                                                       const int32_t *hw, const int32_t *hseg,
+                                                       const int32_t *hbase, const uint8_t *sact,
+                                                       int policy, uint64_t *hkey)
+{
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= E) return;
+    int32_t s = hseg[e];
+    hkey[e] = sact[s] ? hedge_key(policy, (uint32_t)(e - hbase[s]), off[e + 1] - off[e], hw[e]) : kNoKey;
+}
+
+// Node schedule: SMALL = every node of degree <= 32 by one thread, WAVE/BLOCK
+// = listed nodes, their count read on the device (the grid is an upper bound).
+template <int S>
+__device__ __forceinline__ int32_t sched_node(int32_t count, const int32_t *dcount,
+                                              const int32_t *list, int &lane, int &stride)
+{
+    return sched_hedge<S>(S == SMALL ? count : *dcount, list, lane, stride);
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_match_nodes(int32_t count, const int32_t *dcount,
+                                                        const int32_t *list,
+                                                        const int32_t *noff, const int32_t *inc,
+                                                        const int32_t *nseg, const uint8_t *sact,
+                                                        const uint64_t *hkey, uint64_t *key)
+{
+    __shared__ unsigned long long lds[16];
+    int lane, stride;
+    int32_t v = sched_node<S>(count, dcount, list, lane, stride);
+    if (v < 0) return;
+    int32_t b = noff[v], d = noff[v + 1] - b;
+    if (S == SMALL && d > kNodeSmallMax) return;
+    unsigned long long m = kNoKey;
+    if (sact[nseg[v]])
+        for (int i = lane; i < d; i += stride) {
+            unsigned long long k = hkey[inc[b + i]];
+            m = k < m ? k : m;
+        }
+    m = group_min<S>(m, lds);
+    if (lane == 0) key[v] = m;
+}
+
+// ---- Algorithm 4, split into a hyperedge pass and a node pass ---------------------
+
+// Per hyperedge, what a pin on side 0 / side 1 gains from it.
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_hedge_contrib(int32_t count, const int32_t *list,
+                                                          const int32_t *off, const int32_t *pins,
+                                                          const int32_t *hw, const int32_t *hseg,
+                                                          const uint8_t *gmask,
+                                                          const uint8_t *side, int2 *cc)
+{
+    __shared__ int32_t lds[16];
+    int lane, stride;
+    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    if (e < 0) return;
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    if (!gmask[hseg[e]]) return;
+    int32_t n1 = 0;
+    if (S == SMALL) {
+#pragma unroll
+        for (int i = 0; i < kSmallMax; i++)
+            if (i < d) n1 += side[pins[b + i]];
+    } else {
+        for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
+        n1 = group_sum<S>(n1, lds);
+    }
+    if (lane == 0) {
+        int32_t w = hw[e], n0 = d - n1;
+        int2 c;
+        c.x = n0 == 1 ? w : (n0 == d ? -w : 0);
+        c.y = n1 == 1 ? w : (n1 == d ? -w : 0);
+        cc[e] = c;
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(kBlock) void k_node_gain(int32_t count, const int32_t *dcount,
+                                                      const int32_t *list,
+                                                      const int32_t *noff, const int32_t *inc,
+                                                      const int32_t *nseg, const uint8_t *gmask,
+                                                      const uint8_t *side, const int2 *cc,
+                                                      int32_t *gain)
+{
+    __shared__ int32_t lds[16];
+    int lane, stride;
+    int32_t v = sched_node<S>(count, dcount, list, lane, stride);
+    if (v < 0) return;
+    int32_t b = noff[v], d = noff[v + 1] - b;
+    if (S == SMALL && d > kNodeSmallMax) return;
+    if (!gmask[nseg[v]]) return;
+    int sd = side[v];
+    int32_t g = 0;
+    for (int i = lane; i < d; i += stride) {
+        int2 c = cc[inc[b + i]];
+        g += sd ? c.y : c.x;
+    }
+    g = group_sum<S>(g, lds);
+    if (lane == 0) gain[v] = g;
+}
+
+}  // namespace bp
