@@ -36,7 +36,7 @@ inline void hip_check(hipError_t e, const char *what)
 }
 #define BP_HIP(call) ::bp::hip_check((call), #call)
 
-inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+__host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // ---- per-kernel timing (bp_profile_*) ---------------------------------------
 

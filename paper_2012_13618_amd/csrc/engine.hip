@@ -1,5 +1,7 @@
 // Multilevel bisection engine and the C ABI (include/bipart.h).
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 
 #include "engine.hpp"
 
@@ -286,121 +288,152 @@ void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key)
 
 // ---- gains and selection -----------------------------------------------------------
 
-void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain)
+// Gains of the segments in sg.gmask: two launches.  With stats, the node pass
+// also fills the per-list counts / gain extremes used by the selection.
+void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int32_t *go)
 {
     LaunchCtx &lc = cx.lc;
     check_lists(L);
     cx.pins_refined += L.P;
-    // hyperedge pass: what a pin on each side gains from its hyperedge
+    int64_t hv = ceil_div(L.E, kBlock) + ceil_div(L.nmid, kBlock / 64) + L.nbig;
     double hb = 8.0 * L.E + 4.0 * L.E + 4.0 * L.P + 1.0 * L.P + 8.0 * L.E;
-    launch(lc, "gain_hedge_small", hb, k_hedge_contrib<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0, L.E,
-           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
+    launch(lc, "gain_hedges", hb, k_gain_hedges, hv, kBlock, 0, L.E, (const int32_t *)L.lmid, L.nmid,
+           (const int32_t *)L.lbig, L.nbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, L.cc);
-    launch(lc, "gain_hedge_wave", 0.0, k_hedge_contrib<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0,
-           L.nmid, (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, L.cc);
-    launch(lc, "gain_hedge_block", 0.0, k_hedge_contrib<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0,
-           L.nbig, (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, L.cc);
-    // node pass: sum over the node's hyperedges
+           (const uint8_t *)L.side, L.cc, go);
+    int64_t nv = ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64) + L.nbig_bound;
     double nb = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 1.0 * L.N + 4.0 * L.N;
-    launch(lc, "gain_node_small", nb, k_node_gain<SMALL>, sched_grid<SMALL>(L.N), kBlock, 0, L.N,
-           (const int32_t *)L.ncount, (const int32_t *)nullptr, (const int32_t *)L.noff,
+    launch(lc, "gain_nodes", nb, k_gain_nodes, nv, kBlock, 0, L.N, (const int32_t *)L.lnmid,
+           (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)L.noff,
            (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
-    launch(lc, "gain_node_wave", 0.0, k_node_gain<WAVE>, sched_grid<WAVE>(L.nmid_bound), kBlock, 0, L.N,
-           (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
-           (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
-    launch(lc, "gain_node_block", 0.0, k_node_gain<BLOCK>, sched_grid<BLOCK>(L.nbig_bound), kBlock, 0,
-           L.N, (const int32_t *)(L.ncount + 1), (const int32_t *)L.lnbig, (const int32_t *)L.noff,
-           (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, (const int2 *)L.cc, gain);
+           (const uint8_t *)L.side, (const int2 *)L.cc, gain, (const uint8_t *)sg.mode,
+           stats ? sg.st.tot : nullptr, sg.st.gmax, sg.st.gmin, go);
 }
 
-void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain)
+static int id_bits(const Level &L)
+{
+    int bits = 0;
+    while (bits < 31 && ((int64_t)1 << bits) < (int64_t)std::max(L.maxseg_nodes, 1)) bits++;
+    return bits;
+}
+
+static SelView sel_view(Level &L, Segs &sg, const int32_t *gain)
+{
+    SelView sv;
+    sv.gain = gain;
+    sv.nseg = L.nseg;
+    sv.nbase = L.nbase;
+    sv.side = L.side;
+    sv.mode = sg.mode;
+    sv.m = sg.m;
+    return sv;
+}
+
+// The first r nodes of every list in (gain desc, id asc) order: up to three
+// digit passes over the gain span and then over the node id; passes that no
+// list needs return at once.
+void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
     LaunchCtx &lc = cx.lc;
+    int idb = id_bits(L);
+    int passes = 3 + (idb + kDigit - 1) / kDigit;
     int32_t nl = 2 * L.S;
-    int64_t gh = ceil_div(L.N, kSelNodesPerBlock);
-    int64_t gp = ceil_div((int64_t)nl * 64, kBlock);
-    for (int pass = 0; pass < 8; pass++) {
-        launch(lc, "select_hist", 10.0 * L.N, k_sel_hist, gh, kBlock, 0, L.N, pass, gain,
-               (const uint8_t *)L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
-               (const uint64_t *)sg.prefix, (const uint8_t *)sg.ldone, sg.hist);
-        launch(lc, "select_pick", 0.0, k_sel_pick, gp, kBlock, 0, nl, pass, (const uint8_t *)sg.mode,
-               (const int32_t *)sg.m, sg.hist, sg.prefix, sg.rem, sg.rsel, sg.ldone, sg.thr);
-        if (pass == 0)
-            launch(lc, "select_clear", 0.0, k_sel_clear, std::min<int64_t>(ceil_div((int64_t)nl * 256, kBlock), 1024),
-                   kBlock, 0, (int64_t)nl * 256, sg.hist);
+    bool fused = nl <= kFusedPickLists;
+    SelView sv = sel_view(L, sg, gain);
+    int64_t grid = std::max<int64_t>(1, ceil_div(L.N, kSelNodes));
+    for (int p = 0; p < passes; p++) {
+        launch(lc, "select", 10.0 * L.N, k_select_pass, grid, kBlock, 0, L.N, p, nl, idb, sv, sg.st,
+               fused ? 1 : 0, go);
+        if (!fused)
+            launch(lc, "select_pick", 0.0, k_select_pick, nl, kBlock, 0, nl, p, idb, sv, sg.st, go);
     }
 }
 
-// ---- Algorithms 3 and 5 over all segments of a level ------------------------------
-
-static void initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
-    LaunchCtx &lc = cx.lc;
-    int64_t gs = ceil_div(L.S, kBlock);
-    int64_t rounds = 0;
-    for (int first = 1;; first = 0) {
-        // every round moves at least one node of each running segment
-        if (++rounds > (int64_t)L.N + 2) throw Error(BP_ERR_DEVICE, "initial bisection did not terminate");
-        cx.clear_info();
-        launch(lc, "mode", 0.0, k_mode_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
-               (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
-               (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1,
-               (const int32_t *)sg.rsel, first, sg.mode, sg.gmask, sg.m, cx.info_d);
-        if (cx.readback().flag == 0) break;
-        run_gains(cx, L, sg, gain);
-        run_select(cx, L, sg, gain);
-        launch(lc, "apply", 6.0 * L.N, k_apply_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
-               (const int32_t *)gain, L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
-               (const int32_t *)sg.rsel, (const uint64_t *)sg.thr, (const int32_t *)L.nw,
-               (unsigned long long *)sg.w);
-    }
+    launch(cx.lc, "flip", 6.0 * L.N, k_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+           sel_view(L, sg, gain), sg.st, L.side, (const int32_t *)L.nw, (unsigned long long *)sg.w, go);
 }
 
-static void refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+// Rounds issued in chunks with one readback per chunk: the round kernels keep
+// a device counter of segments still running and every later kernel of a
+// finished round returns at once.
+template <typename Round>
+static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
 {
-    LaunchCtx &lc = cx.lc;
-    int64_t gs = ceil_div(L.S, kBlock);
-    launch(lc, "mode", 0.0, k_mode_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
-           sg.mode, sg.gmask, sg.done);
-    for (int it = 0; it < cx.prm.refine_iters; it++) {
-        run_gains(cx, L, sg, gain);
-        run_select(cx, L, sg, gain);
-        launch(lc, "apply", 6.0 * L.N, k_apply_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
-               (const int32_t *)gain, L.side, (const int32_t *)L.nseg, (const uint8_t *)sg.mode,
-               (const int32_t *)sg.rsel, (const uint64_t *)sg.thr, (const int32_t *)L.nw,
-               (unsigned long long *)sg.w);
-    }
-    // balance step: every round moves at least one node or retires a segment
-    int64_t rounds = 0;
+    int64_t issued = 0;
+    int chunk = 2;
     for (;;) {
-        if (++rounds > (int64_t)L.N + (int64_t)L.S + 2) throw Error(BP_ERR_DEVICE, "balance step did not terminate");
-        cx.clear_info();
-        launch(lc, "mode", 0.0, k_mode_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
-               (const unsigned long long *)sg.w, (const int64_t *)sg.max0,
-               (const int64_t *)sg.max1, sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room,
-               sg.ccount, cx.info_d);
-        if (cx.readback().flag == 0) break;
-        run_gains(cx, L, sg, gain);
-        run_select(cx, L, sg, gain);
-        launch(lc, "balance", 10.0 * L.N, k_bal_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
-               (const int32_t *)gain, (const uint8_t *)L.side, (const int32_t *)L.nseg,
-               (const uint8_t *)sg.mode, (const int32_t *)sg.rsel, (const uint64_t *)sg.thr,
-               sg.ccount, sg.cand, sg.cand_stride);
-        int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
+        for (int i = 0; i < chunk; i++) {
+            round(issued == 0);
+            launch(cx.lc, "round", 0.0, k_round_end, 1, 1, 0, sg.go);
+            issued++;
+        }
+        BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, cx.lc.stream));
+        cx.lc.sync();
+        int32_t *g = (int32_t *)cx.info_h;
+        if (g[1] == 0) return g[2];
+        if (issued > limit) throw Error(BP_ERR_DEVICE, "round loop did not terminate");
+        chunk = std::min(chunk * 2, 32);
+    }
+}
+
+static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    int64_t gs = ceil_div(L.S, kBlock);
+    fill(lc, sg.go, 4, 0);
+    return chunked_rounds(cx, sg, (int64_t)L.N + 2, [&](bool first) {
+        launch(lc, "round", 0.0, k_round_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
+               (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
+               (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, first ? 1 : 0,
+               sg.mode, sg.gmask, sg.m, sg.st, sg.go);
+        run_gains(cx, L, sg, gain, true, sg.go);
+        run_select(cx, L, sg, gain, sg.go);
+        flip(cx, L, sg, gain, sg.go);
+    });
+}
+
+static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
+{
+    LaunchCtx &lc = cx.lc;
+    int64_t gs = ceil_div(L.S, kBlock);
+    for (int it = 0; it < cx.prm.refine_iters; it++) {
+        launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
+               sg.mode, sg.gmask, sg.done, sg.st, sg.go);
+        run_gains(cx, L, sg, gain, true, nullptr);
+        run_select(cx, L, sg, gain, nullptr);
+        flip(cx, L, sg, gain, nullptr);
+    }
+    if (cx.prm.refine_iters == 0)
+        launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
+               sg.mode, sg.gmask, sg.done, sg.st, sg.go);
+    // balance step
+    fill(lc, sg.go, 4, 0);
+    int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
+    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, [&](bool) {
+        launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
+               (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
+               sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go);
+        run_gains(cx, L, sg, gain, true, sg.go);
+        run_select(cx, L, sg, gain, sg.go);
+        launch(lc, "balance", 10.0 * L.N, k_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+               sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, (const int32_t *)sg.go);
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
                (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
-               (const int32_t *)L.nw,
-               (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
+               (const int32_t *)L.nw, (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
                (unsigned long long *)sg.w, sg.done, sg.stuck);
+    });
+}
+
+static bool trace_on()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("BP_TRACE");
+        on = (e && *e && *e != '0') ? 1 : 0;
     }
+    return on == 1;
 }
 
 // ---- the multilevel bisection of every segment of a level-0 CSR ---------------------
@@ -437,8 +470,9 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     sg.cand_stride = next_pow2(std::max(mmax, 1));
     sg.cand = ar.get<uint64_t>((int64_t)sg.S * sg.cand_stride);
     int32_t *gain = ar.get<int32_t>(lv[0].N);
-    fill(lc, sg.hist, (int64_t)2 * sg.S * 256, 0u);
-    fill(lc, sg.rsel, (int64_t)2 * sg.S, 0);
+    fill(lc, sg.st.hist, (int64_t)2 * sg.S * kBins, 0u);
+    fill(lc, sg.st.ctl, 4, 0);
+    fill(lc, sg.st.rsel, (int64_t)2 * sg.S, 0);
 
     for (int32_t j = Lmax; j >= 0; j--) {
         Level &L = lv[j];
@@ -451,8 +485,11 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
         launch(lc, "side_weights", 5.0 * L.N, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
                (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
                (unsigned long long *)sg.w);
-        if (stops[j] > 0) initial_rounds(cx, L, sg, j, gain);
-        refine_level(cx, L, sg, j, gain);
+        int64_t ir = stops[j] > 0 ? initial_rounds(cx, L, sg, j, gain) : 0;
+        int64_t br = refine_level(cx, L, sg, j, gain);
+        if (trace_on())
+            fprintf(stderr, "[bp] level %d: S=%d N=%d E=%d P=%d initial_rounds=%lld balance_rounds=%lld\n", j,
+                    L.S, L.N, L.E, L.P, (long long)ir, (long long)br);
     }
     L0.side = lv[0].side;
 }
@@ -1123,7 +1160,7 @@ bp_status bp_step_gains(const bp_hypergraph *hg, const uint8_t *d_side, int32_t 
     Segs sg = alloc_segs(*cx.ar, 1);
     fill(cx.lc, sg.gmask, 1, (uint8_t)1);
     L.side = const_cast<uint8_t *>(d_side);
-    run_gains(cx, L, sg, d_gain);
+    run_gains(cx, L, sg, d_gain, false, nullptr);
     return BP_OK;
     BP_GUARD_END
 }
@@ -1138,8 +1175,9 @@ static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, i
     fill(cx.lc, sg.stuck, 1, 0);
     fill(cx.lc, sg.max0, 1, max0);
     fill(cx.lc, sg.max1, 1, max1);
-    fill(cx.lc, sg.hist, 512, 0u);
-    fill(cx.lc, sg.rsel, 2, 0);
+    fill(cx.lc, sg.st.hist, 2 * kBins, 0u);
+    fill(cx.lc, sg.st.ctl, 4, 0);
+    fill(cx.lc, sg.st.rsel, 2, 0);
     fill(cx.lc, sg.W, 1, (int64_t)0);
     launch(cx.lc, "seg_setup", 0.0, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)sg.W);

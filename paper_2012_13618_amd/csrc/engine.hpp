@@ -3,6 +3,7 @@
 #include "coarsen.hpp"
 #include "kway.hpp"
 #include "refine.hpp"
+#include "uncoarsen.hpp"
 #include "transpose.hpp"
 
 namespace bp {
@@ -217,12 +218,21 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     g.done = ar.get<uint8_t>(S);
     g.stuck = ar.get<int32_t>(S);
     g.root_levels = ar.get<int32_t>(1);
-    g.hist = ar.get<uint32_t>((int64_t)2 * S * 256);
-    g.prefix = ar.get<uint64_t>(2 * S);
-    g.thr = ar.get<uint64_t>(2 * S);
-    g.rem = ar.get<int32_t>(2 * S);
-    g.rsel = ar.get<int32_t>(2 * S);
-    g.ldone = ar.get<uint8_t>(2 * S);
+    SelState &st = g.st;
+    st.hist = ar.get<uint32_t>((int64_t)2 * S * kBins);
+    st.tot = ar.get<int32_t>(2 * S);
+    st.gmax = ar.get<int32_t>(2 * S);
+    st.gmin = ar.get<int32_t>(2 * S);
+    st.rsel = ar.get<int32_t>(2 * S);
+    st.rem = ar.get<int32_t>(2 * S);
+    st.gpass = ar.get<int32_t>(2 * S);
+    st.upre = ar.get<uint32_t>(2 * S);
+    st.uthr = ar.get<uint32_t>(2 * S);
+    st.lpre = ar.get<uint32_t>(2 * S);
+    st.lthr = ar.get<uint32_t>(2 * S);
+    st.done = ar.get<uint8_t>(2 * S);
+    st.ctl = ar.get<int32_t>(4);
+    g.go = ar.get<int32_t>(4);
     g.ccount = ar.get<int32_t>(S);
     return g;
 }
@@ -232,7 +242,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
 void build_incidence(Ctx &cx, Level &L);
 void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key);
 void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0);
-void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain);
-void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain);
+void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int32_t *go);
+void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go);
 
 }  // namespace bp

@@ -48,6 +48,19 @@ struct LevelInfo {
     int32_t pad[6];
 };
 
+// Per-list selection state (device arrays of 2S unless noted).
+struct SelState {
+    uint32_t *hist;   // [2S * 4096], zero between passes
+    int32_t *tot;     // eligible nodes
+    int32_t *gmax, *gmin;
+    int32_t *rsel;    // r, the number to choose (0 = none)
+    int32_t *rem;     // remaining inside the current prefix
+    int32_t *gpass;   // digits over u for this list
+    uint32_t *upre, *uthr, *lpre, *lthr;
+    uint8_t *done;
+    int32_t *ctl;     // [4]: [0] lists still open, [1] ticket
+};
+
 // Per-segment bisection state (device arrays; 2S entries where per side).
 struct Segs {
     int32_t S = 0;
@@ -66,14 +79,11 @@ struct Segs {
     uint8_t *done;
     int32_t *stuck;           // balance stopped over the bound (any level)
     int32_t *root_levels;     // coarsening steps
-    // radix-select state, per list (2S lists: segment x side)
-    uint32_t *hist;           // [2S * 256]
-    uint64_t *prefix, *thr;
-    int32_t *rem, *rsel;
-    uint8_t *ldone;
     int32_t *ccount;          // balance candidates per segment
     uint64_t *cand;           // [S * cand_stride]
     int32_t cand_stride = 0;
+    int32_t *go;              // [4] round counters (current, last, rounds run)
+    SelState st;              // selection state of the 2S lists
 };
 
 }  // namespace bp

@@ -7,9 +7,10 @@
 // wavefront ballots.  Node offsets are binary searches into the sorted keys.
 //
 // With it, the per-node steps - the 64-bit minimum of Algorithm 1 and the gain
-// sum of Algorithm 4 - are gathers over a node's own hyperedges with no
-// atomics, so a node contained in very many hyperedges (a heavy coarse node)
-// is summed by one workgroup instead of receiving that many atomic updates.
+// sum of Algorithm 4 (uncoarsen.hpp) - are gathers over a node's own
+// hyperedges with no atomics, so a node contained in very many hyperedges (a
+// heavy coarse node) is reduced by one workgroup instead of receiving that
+// many atomic updates.
 #pragma once
 #include "level.hpp"
 #include "scan.hpp"
@@ -170,66 +171,6 @@ __global__ __launch_bounds__(kBlock) void k_match_nodes(int32_t count, const int
         }
     m = group_min<S>(m, lds);
     if (lane == 0) key[v] = m;
-}
-
-// ---- Algorithm 4, split into a hyperedge pass and a node pass ---------------------
-
-// Per hyperedge, what a pin on side 0 / side 1 gains from it.
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_hedge_contrib(int32_t count, const int32_t *list,
-                                                          const int32_t *off, const int32_t *pins,
-                                                          const int32_t *hw, const int32_t *hseg,
-                                                          const uint8_t *gmask,
-                                                          const uint8_t *side, int2 *cc)
-{
-    __shared__ int32_t lds[16];
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
-    if (e < 0) return;
-    int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
-    if (!gmask[hseg[e]]) return;
-    int32_t n1 = 0;
-    if (S == SMALL) {
-#pragma unroll
-        for (int i = 0; i < kSmallMax; i++)
-            if (i < d) n1 += side[pins[b + i]];
-    } else {
-        for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
-        n1 = group_sum<S>(n1, lds);
-    }
-    if (lane == 0) {
-        int32_t w = hw[e], n0 = d - n1;
-        int2 c;
-        c.x = n0 == 1 ? w : (n0 == d ? -w : 0);
-        c.y = n1 == 1 ? w : (n1 == d ? -w : 0);
-        cc[e] = c;
-    }
-}
-
-template <int S>
-__global__ __launch_bounds__(kBlock) void k_node_gain(int32_t count, const int32_t *dcount,
-                                                      const int32_t *list,
-                                                      const int32_t *noff, const int32_t *inc,
-                                                      const int32_t *nseg, const uint8_t *gmask,
-                                                      const uint8_t *side, const int2 *cc,
-                                                      int32_t *gain)
-{
-    __shared__ int32_t lds[16];
-    int lane, stride;
-    int32_t v = sched_node<S>(count, dcount, list, lane, stride);
-    if (v < 0) return;
-    int32_t b = noff[v], d = noff[v + 1] - b;
-    if (S == SMALL && d > kNodeSmallMax) return;
-    if (!gmask[nseg[v]]) return;
-    int sd = side[v];
-    int32_t g = 0;
-    for (int i = lane; i < d; i += stride) {
-        int2 c = cc[inc[b + i]];
-        g += sd ? c.y : c.x;
-    }
-    g = group_sum<S>(g, lds);
-    if (lane == 0) gain[v] = g;
 }
 
 }  // namespace bp

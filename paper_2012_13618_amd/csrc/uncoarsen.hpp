@@ -1,0 +1,577 @@
+// Uncoarsening kernels with few launches per round (Algorithms 3-5).
+//
+// Gains (Algorithm 4) take two launches: a hyperedge pass computing what a pin
+// on each side gains from its hyperedge (+w when alone on its side, -w when
+// the hyperedge is uncut), and a node pass summing that over the node's
+// hyperedges.  Each launch covers all degree buckets: virtual blocks
+// [0, ns) take degree <= 8 (hyperedges) / <= 32 (nodes) one per thread, the
+// next ones one listed item per wavefront, the last ones one per workgroup.
+// The node pass also records, per list (one side of one segment), how many
+// nodes are eligible and their largest and smallest gain.
+//
+// Selection of the first r nodes in (gain desc, id asc) order per list is an
+// exact radix select over the pair (u, lid), u = max gain - gain (so ascending
+// u = descending gain) and lid = node id within its segment: 12-bit digits,
+// first over the significant bits of u (1 digit when the list's gains span
+// < 4096 values), then over the bits of lid - each list follows its own digit
+// schedule and stops as soon as the remaining count equals a bin's count.
+// Each pass is one launch: blocks build their histograms and the workgroup
+// that finishes last (atomic ticket) picks the digit of every list.
+#pragma once
+#include "level.hpp"
+#include "refine.hpp"
+#include "transpose.hpp"
+
+namespace bp {
+
+constexpr int kDigit = 12;
+constexpr int kBins = 1 << kDigit;        // 4096
+constexpr int kSelNodes = 1024;           // nodes per workgroup in histogram passes
+constexpr int kFusedPickLists = 8;        // above: separate pick launch, one workgroup per list
+
+__device__ __forceinline__ int bitlen_u32(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
+
+// ---- gains -------------------------------------------------------------------------
+
+template <int S>
+__device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int stride, const int32_t *off,
+                                                  const int32_t *pins, const int32_t *hw,
+                                                  const int32_t *hseg, const uint8_t *gmask,
+                                                  const uint8_t *side, int2 *cc, int32_t *lds)
+{
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (S == SMALL && d > kSmallMax) return;
+    if (!gmask[hseg[e]]) return;
+    int32_t n1 = 0;
+    if (S == SMALL) {
+#pragma unroll
+        for (int i = 0; i < kSmallMax; i++)
+            if (i < d) n1 += side[pins[b + i]];
+    } else {
+        for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
+        n1 = group_sum<S>(n1, lds);
+    }
+    if (lane == 0) {
+        int32_t w = hw[e], n0 = d - n1;
+        int2 c;
+        c.x = n0 == 1 ? w : (n0 == d ? -w : 0);
+        c.y = n1 == 1 ? w : (n1 == d ? -w : 0);
+        cc[e] = c;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t *lmid, int32_t nmid,
+                                                        const int32_t *lbig, int32_t nbig,
+                                                        const int32_t *off, const int32_t *pins,
+                                                        const int32_t *hw, const int32_t *hseg,
+                                                        const uint8_t *gmask, const uint8_t *side,
+                                                        int2 *cc, const int32_t *go)
+{
+    __shared__ int32_t lds[16];
+    if (go && *go == 0) return;
+    int64_t ns = ceil_div(E, kBlock), nw = ceil_div(nmid, kBlock / 64);
+    int64_t vb = blockIdx.x;
+    if (vb < ns) {
+        int64_t e = vb * kBlock + threadIdx.x;
+        if (e < E) hedge_contrib_one<SMALL>((int32_t)e, 0, 1, off, pins, hw, hseg, gmask, side, cc, lds);
+    } else if (vb < ns + nw) {
+        int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6);
+        if (i < nmid)
+            hedge_contrib_one<WAVE>(lmid[i], threadIdx.x & 63, 64, off, pins, hw, hseg, gmask, side, cc, lds);
+    } else if (vb - ns - nw < nbig) {
+        hedge_contrib_one<BLOCK>(lbig[vb - ns - nw], threadIdx.x, blockDim.x, off, pins, hw, hseg, gmask,
+                                 side, cc, lds);
+    }
+}
+
+// eligibility of a node for its list under the segment's selection mode
+__device__ __forceinline__ bool sel_list(int32_t s, int sd, int32_t g, const uint8_t *mode)
+{
+    uint8_t md = mode[s];
+    if (!((md >> sd) & 1)) return false;
+    return !((md & kGainNonNeg) && g < 0);
+}
+
+template <int S>
+__device__ __forceinline__ void node_gain_one(int32_t v, int lane, int stride, const int32_t *noff,
+                                              const int32_t *inc, const int32_t *nseg,
+                                              const uint8_t *gmask, const uint8_t *side,
+                                              const int2 *cc, int32_t *gain, int32_t *lds,
+                                              const uint8_t *mode, int32_t *tot, int32_t *gmax,
+                                              int32_t *gmin, bool stats)
+{
+    int32_t b = noff[v], d = noff[v + 1] - b;
+    if (S == SMALL && d > kNodeSmallMax) return;
+    int32_t s = nseg[v];
+    if (!gmask[s]) return;
+    int sd = side[v];
+    int32_t g = 0;
+    for (int i = lane; i < d; i += stride) {
+        int2 c = cc[inc[b + i]];
+        g += sd ? c.y : c.x;
+    }
+    g = group_sum<S>(g, lds);
+    if (lane == 0) {
+        gain[v] = g;
+        if (stats && sel_list(s, sd, g, mode)) {
+            int32_t c = 2 * s + sd;
+            atomicAdd(&tot[c], 1);
+            atomicMax(&gmax[c], g);
+            atomicMin(&gmin[c], g);
+        }
+    }
+}
+
+// Node pass.  Besides gain[v], per-list counts and gain extremes for the
+// selection that follows (block-aggregated when a block is in one segment).
+__global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t *lnmid,
+                                                       const int32_t *lnbig, const int32_t *ncount,
+                                                       const int32_t *noff, const int32_t *inc,
+                                                       const int32_t *nseg, const uint8_t *gmask,
+                                                       const uint8_t *side, const int2 *cc,
+                                                       int32_t *gain, const uint8_t *mode,
+                                                       int32_t *tot, int32_t *gmax, int32_t *gmin,
+                                                       const int32_t *go)
+{
+    __shared__ int32_t lds[16];
+    __shared__ int32_t agg[6];
+    if (go && *go == 0) return;
+    bool stats = tot != nullptr;
+    int32_t cm = ncount[0], cb = ncount[1];
+    int64_t ns = ceil_div(N, kBlock), nw = ceil_div(cm, kBlock / 64);
+    int64_t vb = blockIdx.x;
+    if (vb < ns) {
+        int64_t v = vb * kBlock + threadIdx.x;
+        int64_t vf = vb * kBlock, vl = vf + kBlock - 1 < N ? vf + kBlock - 1 : N - 1;
+        bool one = nseg[vf] == nseg[vl];
+        int32_t s0 = nseg[vf];
+        if (threadIdx.x < 2) {
+            agg[3 * threadIdx.x] = 0;
+            agg[3 * threadIdx.x + 1] = INT32_MIN;
+            agg[3 * threadIdx.x + 2] = INT32_MAX;
+        }
+        __syncthreads();
+        if (v < N) {
+            int32_t b = noff[v], d = noff[v + 1] - b;
+            int32_t s = nseg[v];
+            if (d <= kNodeSmallMax && gmask[s]) {
+                int sd = side[v];
+                int32_t g = 0;
+                for (int i = 0; i < d; i++) {
+                    int2 c = cc[inc[b + i]];
+                    g += sd ? c.y : c.x;
+                }
+                gain[v] = g;
+                if (stats && sel_list(s, sd, g, mode)) {
+                    if (one) {
+                        atomicAdd(&agg[3 * sd], 1);
+                        atomicMax(&agg[3 * sd + 1], g);
+                        atomicMin(&agg[3 * sd + 2], g);
+                    } else {
+                        int32_t c = 2 * s + sd;
+                        atomicAdd(&tot[c], 1);
+                        atomicMax(&gmax[c], g);
+                        atomicMin(&gmin[c], g);
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (stats && one && threadIdx.x < 2 && agg[3 * threadIdx.x] > 0) {
+            int32_t c = 2 * s0 + threadIdx.x;
+            atomicAdd(&tot[c], agg[3 * threadIdx.x]);
+            atomicMax(&gmax[c], agg[3 * threadIdx.x + 1]);
+            atomicMin(&gmin[c], agg[3 * threadIdx.x + 2]);
+        }
+    } else if (vb < ns + nw) {
+        int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6);
+        if (i < cm)
+            node_gain_one<WAVE>(lnmid[i], threadIdx.x & 63, 64, noff, inc, nseg, gmask, side, cc, gain,
+                                lds, mode, tot, gmax, gmin, stats);
+    } else if (vb - ns - nw < cb) {
+        node_gain_one<BLOCK>(lnbig[vb - ns - nw], threadIdx.x, blockDim.x, noff, inc, nseg, gmask, side,
+                             cc, gain, lds, mode, tot, gmax, gmin, stats);
+    }
+}
+
+// ---- radix select ----------------------------------------------------------------------
+
+struct SelView {
+    const int32_t *gain, *nseg, *nbase;
+    const uint8_t *side, *mode;
+    const int32_t *m;
+};
+
+// The digit of list c's element (u, lid) at global pass p, or -1 when the
+// element does not match the list's current prefix.  ph = digit range.
+__device__ __forceinline__ int sel_digit(const SelState &st, int32_t c, int p, int idbits,
+                                         uint32_t u, uint32_t lid)
+{
+    int gp = st.gpass[c];
+    int ubits = gp * kDigit;  // u is handled as a gp*12-bit number
+    if (p < gp) {
+        int hi = ubits - kDigit * p, lo = hi - kDigit;
+        if (hi < 32 && p > 0 && ((u ^ st.upre[c]) >> hi) != 0) return -1;
+        return (int)((u >> lo) & (kBins - 1));
+    }
+    if (u != st.upre[c]) return -1;
+    int q = p - gp;
+    int ipass = (idbits + kDigit - 1) / kDigit;
+    if (q >= ipass) return -1;
+    int hi = idbits - kDigit * q, lo = hi - kDigit > 0 ? hi - kDigit : 0;
+    if (q > 0 && hi < 32 && ((lid ^ st.lpre[c]) >> hi) != 0) return -1;
+    return (int)((lid >> lo) & ((1u << (hi - lo)) - 1u));
+}
+
+// Pick of list c after pass p: the digit holding the rem-th element.  One
+// workgroup.  Clears the bins it read.
+__device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, const uint8_t *mode,
+                              const int32_t *m, int64_t *lds)
+{
+    __shared__ int sbin;
+    __shared__ int32_t sbefore, sin_;
+    uint32_t *hc = st.hist + (int64_t)c * kBins;
+    if (p == 0) {
+        // the number to choose: Algorithm 5 takes min(|L0|, |L1|) from both
+        // lists, Algorithm 3 and the balance step at most ceil(sqrt n)
+        if (threadIdx.x == 0) {
+            int32_t s = c >> 1, sd = c & 1;
+            uint8_t md = mode[s];
+            int64_t r = 0;
+            if ((md >> sd) & 1) {
+                int64_t t = st.tot[c];
+                if (md & kMinPair) {
+                    int64_t o = st.tot[c ^ 1];
+                    r = t < o ? t : o;
+                } else {
+                    r = t < (int64_t)m[s] ? t : (int64_t)m[s];
+                }
+            }
+            st.rsel[c] = (int32_t)r;
+            st.rem[c] = (int32_t)r;
+            st.upre[c] = 0;
+            st.lpre[c] = 0;
+            uint32_t range = r > 0 ? (uint32_t)((int64_t)st.gmax[c] - st.gmin[c]) : 0u;
+            int ub = bitlen_u32(range);
+            st.gpass[c] = (ub + kDigit - 1) / kDigit;
+            st.done[c] = r == 0;
+            st.uthr[c] = 0;
+            st.lthr[c] = 0;
+            if (r == 0) atomicSub(&st.ctl[0], 1);
+        }
+        __syncthreads();
+    }
+    int per = kBins / kBlock;
+    if (st.done[c]) {
+        // nothing to choose: still clear what pass 0 counted for this list
+        if (p == 0)
+            for (int j = 0; j < per; j++) hc[threadIdx.x * per + j] = 0;
+        __syncthreads();
+        return;
+    }
+    int32_t r = st.rem[c];
+    int64_t loc = 0;
+    for (int j = 0; j < per; j++) loc += hc[threadIdx.x * per + j];
+    int64_t tot;
+    int64_t ex = block_excl_scan(loc, lds, &tot);
+    if (threadIdx.x == 0) sbin = -1;
+    __syncthreads();
+    if (ex < r && r <= ex + loc) {
+        int64_t acc = ex;
+        for (int j = 0; j < per; j++) {
+            int64_t x = hc[threadIdx.x * per + j];
+            if (acc + x >= r) {
+                sbin = threadIdx.x * per + j;
+                sbefore = (int32_t)acc;
+                sin_ = (int32_t)x;
+                break;
+            }
+            acc += x;
+        }
+    }
+    __syncthreads();
+    for (int j = 0; j < per; j++) hc[threadIdx.x * per + j] = 0;
+    if (threadIdx.x == 0 && sbin >= 0) {
+        int gp = st.gpass[c];
+        int32_t left = r - sbefore;
+        bool all = left == sin_;
+        st.rem[c] = left;
+        bool fin = false;
+        if (p < gp) {
+            int hi = gp * kDigit - kDigit * p, lo = hi - kDigit;
+            uint32_t pre = st.upre[c] | ((uint32_t)sbin << lo);
+            st.upre[c] = pre;
+            if (all) {
+                st.uthr[c] = pre | (lo ? ((1u << lo) - 1u) : 0u);
+                st.lthr[c] = 0xffffffffu;
+                fin = true;
+            } else if (lo == 0 && idbits == 0) {
+                st.uthr[c] = pre;
+                st.lthr[c] = 0xffffffffu;
+                fin = true;
+            }
+        } else {
+            int q = p - gp;
+            int hi = idbits - kDigit * q, lo = hi - kDigit > 0 ? hi - kDigit : 0;
+            uint32_t pre = st.lpre[c] | ((uint32_t)sbin << lo);
+            st.lpre[c] = pre;
+            if (all || lo == 0) {
+                st.uthr[c] = st.upre[c];
+                st.lthr[c] = pre | (lo ? ((1u << lo) - 1u) : 0u);
+                fin = true;
+            }
+        }
+        if (fin) {
+            st.done[c] = 1;
+            atomicSub(&st.ctl[0], 1);
+        }
+    }
+    __syncthreads();
+}
+
+// Histogram of global pass p; the last workgroup to finish does the picks
+// when there are few lists.
+__global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_t nlists, int idbits,
+                                                        SelView sv, SelState st, int fused,
+                                                        const int32_t *go)
+{
+    __shared__ uint32_t h[2 * kBins];
+    __shared__ int64_t lds[16];
+    __shared__ int last;
+    if (go && *go == 0) return;
+    if (p > 0 && st.ctl[0] <= 0) return;
+    int64_t v0 = (int64_t)blockIdx.x * kSelNodes;
+    if (v0 < N) {
+        int64_t v1 = v0 + kSelNodes < N ? v0 + kSelNodes : N;
+        int32_t cbase = 2 * sv.nseg[v0];
+        bool use_lds = 2 * sv.nseg[v1 - 1] + 1 - cbase < 2;
+        if (use_lds) {
+            for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) h[i] = 0;
+            __syncthreads();
+        }
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+            int32_t s = sv.nseg[v];
+            int sd = sv.side[v];
+            int32_t g = sv.gain[v];
+            if (!sel_list(s, sd, g, sv.mode)) continue;
+            int32_t c = 2 * s + sd;
+            if (p > 0 && st.done[c]) continue;
+            // pass 0 runs before the pick has set the schedule: u digit 0 of
+            // the span computed from the node pass's extremes
+            uint32_t u = (uint32_t)((int64_t)st.gmax[c] - g);
+            uint32_t lid = (uint32_t)(v - sv.nbase[s]);
+            int dig;
+            if (p == 0) {
+                int ub = bitlen_u32((uint32_t)((int64_t)st.gmax[c] - st.gmin[c]));
+                int gp = (ub + kDigit - 1) / kDigit;
+                if (gp > 0) {
+                    dig = (int)((u >> (gp * kDigit - kDigit)) & (kBins - 1));
+                } else {
+                    // every gain equal: the first digit is over the id
+                    int hi = idbits, lo = hi - kDigit > 0 ? hi - kDigit : 0;
+                    dig = (int)((lid >> lo) & ((1u << (hi - lo)) - 1u));
+                }
+            } else {
+                dig = sel_digit(st, c, p, idbits, u, lid);
+                if (dig < 0) continue;
+            }
+            if (use_lds) atomicAdd(&h[(c - cbase) * kBins + dig], 1u);
+            else atomicAdd(&st.hist[(int64_t)c * kBins + dig], 1u);
+        }
+        if (use_lds) {
+            __syncthreads();
+            for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) {
+                uint32_t x = h[i];
+                if (x) atomicAdd(&st.hist[(int64_t)(cbase + i / kBins) * kBins + (i % kBins)], x);
+            }
+        }
+    }
+    if (!fused) return;
+    // ticket: the last workgroup sees every histogram
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int t = atomicAdd(&st.ctl[1], 1);
+        last = t == (int)gridDim.x - 1;
+        if (last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+    if (!last) return;
+    for (int32_t c = 0; c < nlists; c++) sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds);
+    if (threadIdx.x == 0) st.ctl[1] = 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_select_pick(int32_t nlists, int p, int idbits, SelView sv,
+                                                        SelState st, const int32_t *go)
+{
+    __shared__ int64_t lds[16];
+    if (go && *go == 0) return;
+    if (p > 0 && st.ctl[0] <= 0) return;
+    int32_t c = blockIdx.x;
+    if (c >= nlists) return;
+    sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds);
+}
+
+__device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const SelState &st)
+{
+    int32_t s = sv.nseg[v];
+    int sd = sv.side[v];
+    int32_t g = sv.gain[v];
+    if (!sel_list(s, sd, g, sv.mode)) return false;
+    int32_t c = 2 * s + sd;
+    if (st.rsel[c] <= 0) return false;
+    uint32_t u = (uint32_t)((int64_t)st.gmax[c] - g);
+    if (u != st.uthr[c]) return u < st.uthr[c];
+    return (uint32_t)(v - sv.nbase[s]) <= st.lthr[c];
+}
+
+// ---- moves ---------------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_flip(int32_t N, SelView sv, SelState st, uint8_t *side,
+                                                 const int32_t *nw, unsigned long long *segw,
+                                                 const int32_t *go)
+{
+    __shared__ int64_t lds[16];
+    if (go && *go == 0) return;
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t vf = (int64_t)blockIdx.x * blockDim.x;
+    int64_t vl = vf + blockDim.x - 1 < N ? vf + blockDim.x - 1 : N - 1;
+    bool one = sv.nseg[vf] == sv.nseg[vl];
+    int64_t d01 = 0;
+    if (v < N && sel_chosen(v, sv, st)) {
+        int32_t sd = side[v];
+        int64_t w = nw[v];
+        side[v] = (uint8_t)(1 - sd);
+        if (one) {
+            d01 += sd ? -w : w;
+        } else {
+            int32_t s = sv.nseg[v];
+            atomicAdd(&segw[2 * s + sd], (unsigned long long)(-w));
+            atomicAdd(&segw[2 * s + 1 - sd], (unsigned long long)w);
+        }
+    }
+    if (one) {
+        d01 = block_sum(d01, lds);
+        if (threadIdx.x == 0 && d01 != 0) {
+            int32_t s = sv.nseg[vf];
+            atomicAdd(&segw[2 * s], (unsigned long long)(-d01));
+            atomicAdd(&segw[2 * s + 1], (unsigned long long)d01);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gather(int32_t N, SelView sv, SelState st, int32_t *ccount,
+                                                   uint64_t *cand, int32_t stride, const int32_t *go)
+{
+    if (go && *go == 0) return;
+    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= N || !sel_chosen(v, sv, st)) return;
+    int32_t s = sv.nseg[v];
+    int32_t at = atomicAdd(&ccount[s], 1);
+    cand[(int64_t)s * stride + at] = gain_order_key(sv.gain[v], (uint32_t)v);
+}
+
+// ---- per-round modes: also reset the selection state of the lists --------------------------
+
+__device__ __forceinline__ void reset_lists(SelState st, int32_t s)
+{
+    for (int sd = 0; sd < 2; sd++) {
+        int32_t c = 2 * s + sd;
+        st.tot[c] = 0;
+        st.gmax[c] = INT32_MIN;
+        st.gmin[c] = INT32_MAX;
+        st.done[c] = 0;
+    }
+}
+
+// Algorithm 3 loop test per segment: P0 below its share and P1 non-empty.
+__global__ void k_round_initial(int32_t S, int32_t j, const int32_t *nbase, const int32_t *coarsest,
+                                const int32_t *k0, const int32_t *k1, const int64_t *W,
+                                const unsigned long long *segw, int32_t *cnt1, int first,
+                                uint8_t *mode, uint8_t *gmask, int32_t *m, SelState st, int32_t *go)
+{
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) st.ctl[0] = 2 * S;
+    if (s >= S) return;
+    if (go[1] == 0 && !first) {  // the previous round found nothing to do
+        mode[s] = 0;
+        gmask[s] = 0;
+        return;
+    }
+    uint8_t md = 0;
+    if (coarsest[s] == j) {
+        int32_t n = nbase[s + 1] - nbase[s];
+        if (first) cnt1[s] = n;
+        else cnt1[s] -= st.rsel[2 * s + 1];
+        int64_t ks = (int64_t)k0[s] + k1[s];
+        bool run = (int64_t)segw[2 * s] * ks < W[s] * (int64_t)k0[s] && cnt1[s] > 0;
+        if (run) {
+            md = kList1;
+            m[s] = (int32_t)ceil_sqrt_i64(n);
+            atomicAdd(&go[0], 1);
+        }
+    }
+    mode[s] = md;
+    gmask[s] = md ? 1 : 0;
+    reset_lists(st, s);
+    st.rsel[2 * s] = 0;
+    st.rsel[2 * s + 1] = 0;
+}
+
+__global__ void k_round_refine(int32_t S, int32_t j, const int32_t *coarsest, uint8_t *mode,
+                               uint8_t *gmask, uint8_t *done, SelState st, int32_t *go)
+{
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) {
+        st.ctl[0] = 2 * S;
+        go[0] = 1;
+    }
+    if (s >= S) return;
+    bool present = coarsest[s] >= j;
+    mode[s] = present ? (kList0 | kList1 | kGainNonNeg | kMinPair) : 0;
+    gmask[s] = present ? 1 : 0;
+    done[s] = present ? 0 : 1;
+    reset_lists(st, s);
+}
+
+// Balance test per segment: the side over its bound, the excess, the room.
+__global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned long long *segw,
+                                const int64_t *max0, const int64_t *max1, uint8_t *done,
+                                uint8_t *mode, uint8_t *gmask, int32_t *m, int64_t *need,
+                                int64_t *room, int32_t *ccount, SelState st, int32_t *go)
+{
+    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s == 0) st.ctl[0] = 2 * S;
+    if (s >= S) return;
+    uint8_t md = 0;
+    ccount[s] = 0;
+    if (!done[s]) {
+        int64_t w0 = (int64_t)segw[2 * s], w1 = (int64_t)segw[2 * s + 1];
+        int h = -1;
+        if (w0 > max0[s]) h = 0;
+        else if (w1 > max1[s]) h = 1;
+        if (h < 0) {
+            done[s] = 1;
+        } else {
+            md = h ? kList1 : kList0;
+            need[s] = h ? w1 - max1[s] : w0 - max0[s];
+            room[s] = h ? max0[s] - w0 : max1[s] - w1;
+            m[s] = (int32_t)ceil_sqrt_i64(nbase[s + 1] - nbase[s]);
+            atomicAdd(&go[0], 1);
+        }
+    }
+    mode[s] = md;
+    gmask[s] = md ? 1 : 0;
+    reset_lists(st, s);
+}
+
+// Rotates the round counters: go[1] = this round's count, go[0] = 0 for the
+// next round's test; go[2] accumulates rounds run.
+__global__ void k_round_end(int32_t *go)
+{
+    go[1] = go[0];
+    if (go[0]) go[2] += 1;
+    go[0] = 0;
+}
+
+}  // namespace bp
