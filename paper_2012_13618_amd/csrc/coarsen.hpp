@@ -209,8 +209,76 @@ __global__ __launch_bounds__(kBlock) void k_qbuild_small(int32_t E, const int32_
     fp[e] = fp_finish(sum, len);
 }
 
-// Degree 9..256: each wavefront sorts its hyperedge's parents in a 256-entry
-// LDS slice.  Waves without a hyperedge sort padding so barriers line up.
+// Ascending bitonic sort of 64*R keys held R per lane (key i = lane*R + t),
+// entirely in registers: steps across lanes use shuffles, steps inside a lane
+// are plain compare-exchanges.
+template <int R> __device__ __forceinline__ void wave_sort_regs(int32_t (&x)[R])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 2; k <= 64 * R; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j >= R) {
+                int lj = j / R;
+#pragma unroll
+                for (int t = 0; t < R; t++) {
+                    int i = lane * R + t;
+                    int32_t y = __shfl_xor(x[t], lj, 64);
+                    bool up = (i & k) == 0, lower = (i & j) == 0;
+                    int32_t mn = x[t] < y ? x[t] : y, mx = x[t] < y ? y : x[t];
+                    x[t] = (lower == up) ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < R; t++) {
+                    int p = t ^ j;
+                    if (p > t) {
+                        int i = lane * R + t;
+                        bool up = (i & k) == 0;
+                        int32_t a = x[t], b = x[p];
+                        bool sw = (a > b) == up;
+                        x[t] = sw ? b : a;
+                        x[p] = sw ? a : b;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Distinct keys of a sorted register tile (first d keys valid) written to
+// dst in order; returns the count and the fingerprint sum.
+template <int R>
+__device__ __forceinline__ int32_t wave_unique_emit(const int32_t (&x)[R], int32_t d, int32_t *dst,
+                                                    uint64_t *sum_out)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t prev_last = __shfl_up(x[R - 1], 1, 64);
+    int flags = 0, cnt = 0;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int t = 0; t < R; t++) {
+        int i = lane * R + t;
+        int32_t before = t == 0 ? prev_last : x[t > 0 ? t - 1 : 0];
+        bool first = i < d && (i == 0 || x[t] != before);
+        if (first) {
+            flags |= 1 << t;
+            cnt++;
+            sum += fp_term(x[t], 0);
+        }
+    }
+    int32_t incl = wave_incl_scan(cnt);
+    int32_t len = __shfl(incl, 63, 64);
+    int32_t pos = incl - cnt;
+#pragma unroll
+    for (int t = 0; t < R; t++)
+        if (flags & (1 << t)) dst[pos++] = x[t];
+    *sum_out = wave_sum(sum);
+    return len;
+}
+
+// Degree 9..256: one wavefront per hyperedge, parents sorted in registers.
 __global__ __launch_bounds__(kBlock) void k_qbuild_wave(int32_t count, const int32_t *list,
                                                         const int32_t *off, const int32_t *pins,
                                                         const int32_t *hseg,
@@ -218,43 +286,34 @@ __global__ __launch_bounds__(kBlock) void k_qbuild_wave(int32_t count, const int
                                                         const int32_t *parent, int32_t *qpins,
                                                         int32_t *qlen, uint64_t *fp)
 {
-    __shared__ int32_t buf[kBlock / kWave][kMidMax];
-    int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int64_t gw_ = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    int32_t e = gw_ < count ? list[gw_] : -1;
-    int32_t b = 0, d = 0;
-    bool act = false;
-    if (e >= 0) {
-        b = off[e];
-        d = off[e + 1] - b;
-        act = sact[hseg[e]] != 0;
+    int lane = threadIdx.x & 63;
+    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    if (w >= count) return;
+    int32_t e = list[w];
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (!sact[hseg[e]]) {
+        if (lane == 0) qlen[e] = 0;
+        return;
     }
-    int32_t *a = buf[w];
-    for (int i = lane; i < kMidMax; i += 64) a[i] = (act && i < d) ? parent[pins[b + i]] : INT32_MAX;
-    __syncthreads();
-    wave_bitonic_sort(a, kMidMax);
-    // each lane owns 4 consecutive sorted entries
-    int32_t flags = 0, cntl = 0;
-    uint64_t sum = 0;
+    int32_t len;
+    uint64_t sum;
+    if (d <= 64) {
+        int32_t x[1];
+        x[0] = lane < d ? parent[pins[b + lane]] : INT32_MAX;
+        wave_sort_regs<1>(x);
+        len = wave_unique_emit<1>(x, d, qpins + b, &sum);
+    } else {
+        int32_t x[4];
 #pragma unroll
-    for (int j = 0; j < 4; j++) {
-        int i = lane * 4 + j;
-        bool first = act && i < d && (i == 0 || a[i] != a[i - 1]);
-        if (first) {
-            flags |= 1 << j;
-            cntl++;
-            sum += fp_term(a[i], 0);
+        for (int t = 0; t < 4; t++) {
+            int i = lane * 4 + t;
+            x[t] = i < d ? parent[pins[b + i]] : INT32_MAX;
         }
+        wave_sort_regs<4>(x);
+        len = wave_unique_emit<4>(x, d, qpins + b, &sum);
     }
-    int32_t incl = wave_incl_scan(cntl);
-    int32_t len = __shfl(incl, 63, 64);
-    sum = wave_sum(sum);
-    int32_t pos = incl - cntl;
-#pragma unroll
-    for (int j = 0; j < 4; j++)
-        if (flags & (1 << j)) qpins[b + pos++] = a[lane * 4 + j];
-    if (e >= 0 && lane == 0) {
-        qlen[e] = (act && len >= 2) ? len : 0;
+    if (lane == 0) {
+        qlen[e] = len >= 2 ? len : 0;
         fp[e] = fp_finish(sum, len);
     }
 }

@@ -12,6 +12,9 @@ static void check_lists(const Level &L)
 {
     if ((L.nmid > 0 && !L.lmid) || (L.nbig > 0 && !L.lbig) || (L.nhuge > 0 && !L.lhuge))
         throw Error(BP_ERR_DEVICE, "internal: hyperedge schedule lists missing");
+    if (L.noff && (!L.ncount || !L.chunk_node || !L.chunk_beg || !L.chunk_big || !L.big_chunks ||
+                   !L.big_done))
+        throw Error(BP_ERR_DEVICE, "internal: node schedule lists missing");
 }
 
 // ---- one coarsening step ------------------------------------------------------
@@ -259,10 +262,18 @@ void build_incidence(Ctx &cx, Level &L)
     L.nbig_bound = std::min<int64_t>(N, P / (kNodeMidMax + 1)) + 1;
     L.lnmid = ar.get<int32_t>(L.nmid_bound);
     L.lnbig = ar.get<int32_t>(L.nbig_bound);
-    L.ncount = ar.get<int32_t>(2);
-    fill(lc, L.ncount, 2, 0);
+    L.ncount = ar.get<int32_t>(4);
+    fill(lc, L.ncount, 4, 0);
     launch(lc, "incidence", 8.0 * N, k_classify_nodes, ceil_div(N, kBlock), kBlock, 0, N,
            (const int32_t *)L.noff, L.lnmid, L.lnbig, L.ncount);
+    L.nchunk_bound = (int64_t)P / kNodeChunk + L.nbig_bound + 1;
+    L.chunk_node = ar.get<int32_t>(L.nchunk_bound);
+    L.chunk_beg = ar.get<int32_t>(L.nchunk_bound);
+    L.chunk_big = ar.get<int32_t>(L.nchunk_bound);
+    L.big_chunks = ar.get<int32_t>(L.nbig_bound);
+    L.big_done = ar.get<int32_t>(L.nbig_bound);
+    launch(lc, "incidence", 0.0, k_big_chunks, 1, kBlock, 0, (const int32_t *)L.lnbig,
+           (const int32_t *)L.noff, L.ncount, L.chunk_node, L.chunk_beg, L.chunk_big, L.big_chunks);
     L.cc = ar.get<int2>(E);
 }
 
@@ -281,9 +292,10 @@ void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key)
     launch(lc, "match_wave", 0.0, k_match_nodes<WAVE>, sched_grid<WAVE>(L.nmid_bound), kBlock, 0, L.N,
            (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
            (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
-    launch(lc, "match_block", 0.0, k_match_nodes<BLOCK>, sched_grid<BLOCK>(L.nbig_bound), kBlock, 0,
-           L.N, (const int32_t *)(L.ncount + 1), (const int32_t *)L.lnbig, (const int32_t *)L.noff,
-           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
+    launch(lc, "match_chunks", 0.0, k_match_chunks, L.nchunk_bound, kBlock, 0, (const int32_t *)L.ncount,
+           (const int32_t *)L.chunk_node, (const int32_t *)L.chunk_beg, (const int32_t *)L.noff,
+           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey,
+           (unsigned long long *)key);
 }
 
 // ---- gains and selection -----------------------------------------------------------
@@ -295,19 +307,23 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int
     LaunchCtx &lc = cx.lc;
     check_lists(L);
     cx.pins_refined += L.P;
-    int64_t hv = ceil_div(L.E, kBlock) + ceil_div(L.nmid, kBlock / 64) + L.nbig;
+    int64_t hv = std::max<int64_t>(ceil_div(L.E, kBlock) + ceil_div(L.nmid, kBlock / 64) + L.nbig,
+                                   ceil_div(L.nbig_bound, kBlock));
     double hb = 8.0 * L.E + 4.0 * L.E + 4.0 * L.P + 1.0 * L.P + 8.0 * L.E;
     launch(lc, "gain_hedges", hb, k_gain_hedges, hv, kBlock, 0, L.E, (const int32_t *)L.lmid, L.nmid,
            (const int32_t *)L.lbig, L.nbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, L.cc, go);
-    int64_t nv = ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64) + L.nbig_bound;
+           (const uint8_t *)L.side, L.cc, go, (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gain,
+           L.big_done);
+    int64_t nv = ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64) + L.nchunk_bound;
     double nb = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 1.0 * L.N + 4.0 * L.N;
     launch(lc, "gain_nodes", nb, k_gain_nodes, nv, kBlock, 0, L.N, (const int32_t *)L.lnmid,
            (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)L.noff,
            (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
            (const uint8_t *)L.side, (const int2 *)L.cc, gain, (const uint8_t *)sg.mode,
-           stats ? sg.st.tot : nullptr, sg.st.gmax, sg.st.gmin, go);
+           stats ? sg.st.tot : nullptr, sg.st.gmax, sg.st.gmin, go, (const int32_t *)L.chunk_node,
+           (const int32_t *)L.chunk_beg, (const int32_t *)L.chunk_big, (const int32_t *)L.big_chunks,
+           L.big_done);
 }
 
 static int id_bits(const Level &L)

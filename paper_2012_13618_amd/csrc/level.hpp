@@ -32,8 +32,12 @@ struct Level {
     int32_t *noff = nullptr;    // [N+1]
     int32_t *inc = nullptr;     // [P]
     int32_t *lnmid = nullptr, *lnbig = nullptr;  // node buckets (degree > 32, > 2048)
-    int32_t *ncount = nullptr;  // device: [0] = |lnmid|, [1] = |lnbig|
+    int32_t *ncount = nullptr;  // device: [0] = |lnmid|, [1] = |lnbig|, [2] = chunks of big nodes
     int64_t nmid_bound = 0, nbig_bound = 0;      // grid bounds for the node buckets
+    // big nodes (degree > 2048) are reduced in chunks of 4096 incidences
+    int32_t *chunk_node = nullptr, *chunk_beg = nullptr, *chunk_big = nullptr;
+    int32_t *big_chunks = nullptr, *big_done = nullptr;  // per big node
+    int64_t nchunk_bound = 0;
     int2 *cc = nullptr;         // [E] per-hyperedge gain contributions (scratch)
 };
 

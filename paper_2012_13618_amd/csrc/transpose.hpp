@@ -20,7 +20,8 @@ namespace bp {
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kBlock * kRsItems;   // 4096 pairs per tile
 constexpr int kNodeSmallMax = 32;            // node degree: one thread
-constexpr int kNodeMidMax = 2048;            // one wavefront; above: one workgroup
+constexpr int kNodeMidMax = 2048;            // one wavefront; above: chunks
+constexpr int kNodeChunk = 4096;             // incidences per workgroup for big nodes
 
 __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, int64_t n, int shift,
                                                     uint32_t *counts, int64_t ntiles)
@@ -128,7 +129,60 @@ __global__ __launch_bounds__(kBlock) void k_classify_nodes(int32_t N, const int3
     wave_append(d > kNodeMidMax, (int32_t)v, lbig, &counters[1]);
 }
 
+// Chunk table of the big nodes: one workgroup walks them in tiles of 256 and
+// places each node's chunks after a prefix sum of the chunk counts.
+__global__ __launch_bounds__(kBlock) void k_big_chunks(const int32_t *lnbig, const int32_t *noff,
+                                                       int32_t *ncount, int32_t *chunk_node,
+                                                       int32_t *chunk_beg, int32_t *chunk_big,
+                                                       int32_t *big_chunks)
+{
+    __shared__ int32_t lds[16];
+    int32_t cb = ncount[1], q0 = 0;
+    for (int32_t t = 0; t < cb; t += kBlock) {
+        int32_t i = t + threadIdx.x;
+        int32_t v = 0, b = 0, n = 0;
+        if (i < cb) {
+            v = lnbig[i];
+            b = noff[v];
+            n = (int32_t)ceil_div(noff[v + 1] - b, kNodeChunk);
+            big_chunks[i] = n;
+        }
+        int32_t tot;
+        int32_t q = q0 + block_excl_scan(n, lds, &tot);
+        for (int32_t j = 0; j < n; j++) {
+            chunk_node[q + j] = v;
+            chunk_beg[q + j] = b + j * kNodeChunk;
+            chunk_big[q + j] = i;
+        }
+        q0 += tot;
+    }
+    if (threadIdx.x == 0) ncount[2] = q0;
+}
+
 // ---- Algorithm 1, node side ------------------------------------------------------
+
+// Big nodes: each workgroup takes one chunk and folds its minimum in with a
+// 64-bit atomicMin (key[] starts at the no-hyperedge value).
+__global__ __launch_bounds__(kBlock) void k_match_chunks(const int32_t *ncount, const int32_t *chunk_node,
+                                                         const int32_t *chunk_beg, const int32_t *noff,
+                                                         const int32_t *inc, const int32_t *nseg,
+                                                         const uint8_t *sact, const uint64_t *hkey,
+                                                         unsigned long long *key)
+{
+    __shared__ unsigned long long lds[16];
+    int32_t q = blockIdx.x;
+    if (q >= ncount[2]) return;
+    int32_t v = chunk_node[q];
+    if (!sact[nseg[v]]) return;
+    int32_t b = chunk_beg[q], e = min(b + kNodeChunk, noff[v + 1]);
+    unsigned long long m = kNoKey;
+    for (int32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+        unsigned long long k = hkey[inc[i]];
+        m = k < m ? k : m;
+    }
+    m = block_min(m, lds);
+    if (threadIdx.x == 0 && m != kNoKey) atomicMin(&key[v], m);
+}
 
 __global__ __launch_bounds__(kBlock) void k_hedge_keys(int32_t E, const int32_t *off,
                                                        const int32_t *hw, const int32_t *hseg,
@@ -162,7 +216,10 @@ __global__ __launch_bounds__(kBlock) void k_match_nodes(int32_t count, const int
     int32_t v = sched_node<S>(count, dcount, list, lane, stride);
     if (v < 0) return;
     int32_t b = noff[v], d = noff[v + 1] - b;
-    if (S == SMALL && d > kNodeSmallMax) return;
+    if (S == SMALL && d > kNodeSmallMax) {
+        if (d > kNodeMidMax) key[v] = kNoKey;  // start value of the chunked minimum
+        return;
+    }
     unsigned long long m = kNoKey;
     if (sact[nseg[v]])
         for (int i = lane; i < d; i += stride) {

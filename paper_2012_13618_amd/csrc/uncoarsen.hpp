@@ -65,10 +65,18 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
                                                         const int32_t *off, const int32_t *pins,
                                                         const int32_t *hw, const int32_t *hseg,
                                                         const uint8_t *gmask, const uint8_t *side,
-                                                        int2 *cc, const int32_t *go)
+                                                        int2 *cc, const int32_t *go,
+                                                        const int32_t *lnbig, const int32_t *ncount,
+                                                        int32_t *gain, int32_t *big_done)
 {
     __shared__ int32_t lds[16];
     if (go && *go == 0) return;
+    // big nodes are summed chunk by chunk in the node pass: start them at 0
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < ncount[1]) {
+        gain[lnbig[t]] = 0;
+        big_done[t] = 0;
+    }
     int64_t ns = ceil_div(E, kBlock), nw = ceil_div(nmid, kBlock / 64);
     int64_t vb = blockIdx.x;
     if (vb < ns) {
@@ -131,13 +139,16 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
                                                        const uint8_t *side, const int2 *cc,
                                                        int32_t *gain, const uint8_t *mode,
                                                        int32_t *tot, int32_t *gmax, int32_t *gmin,
-                                                       const int32_t *go)
+                                                       const int32_t *go, const int32_t *chunk_node,
+                                                       const int32_t *chunk_beg,
+                                                       const int32_t *chunk_big,
+                                                       const int32_t *big_chunks, int32_t *big_done)
 {
     __shared__ int32_t lds[16];
     __shared__ int32_t agg[6];
     if (go && *go == 0) return;
     bool stats = tot != nullptr;
-    int32_t cm = ncount[0], cb = ncount[1];
+    int32_t cm = ncount[0], ck = ncount[2];
     int64_t ns = ceil_div(N, kBlock), nw = ceil_div(cm, kBlock / 64);
     int64_t vb = blockIdx.x;
     if (vb < ns) {
@@ -188,9 +199,36 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
         if (i < cm)
             node_gain_one<WAVE>(lnmid[i], threadIdx.x & 63, 64, noff, inc, nseg, gmask, side, cc, gain,
                                 lds, mode, tot, gmax, gmin, stats);
-    } else if (vb - ns - nw < cb) {
-        node_gain_one<BLOCK>(lnbig[vb - ns - nw], threadIdx.x, blockDim.x, noff, inc, nseg, gmask, side,
-                             cc, gain, lds, mode, tot, gmax, gmin, stats);
+    } else if (vb - ns - nw < ck) {
+        // one chunk of a big node: partial sum, then the last chunk of the
+        // node records its statistics
+        int32_t q = (int32_t)(vb - ns - nw);
+        int32_t v = chunk_node[q];
+        int32_t s = nseg[v];
+        if (!gmask[s]) return;
+        int sd = side[v];
+        int32_t b = chunk_beg[q], e = min(b + kNodeChunk, noff[v + 1]);
+        int32_t g = 0;
+        for (int32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
+            int2 c = cc[inc[i]];
+            g += sd ? c.y : c.x;
+        }
+        g = block_sum(g, lds);
+        if (threadIdx.x == 0) {
+            atomicAdd(&gain[v], g);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            int32_t bi = chunk_big[q];
+            if (atomicAdd(&big_done[bi], 1) == big_chunks[bi] - 1) {
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                int32_t gv = __hip_atomic_load(&gain[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (stats && sel_list(s, sd, gv, mode)) {
+                    int32_t c = 2 * s + sd;
+                    atomicAdd(&tot[c], 1);
+                    atomicMax(&gmax[c], gv);
+                    atomicMin(&gmin[c], gv);
+                }
+            }
+        }
     }
 }
 
