@@ -149,6 +149,40 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
                               bp_report *report, void *stream);
 
 /*
+ * Batched form: n independent hypergraphs partitioned in ONE device run.  All
+ * graphs are segments of the same levels (the nested scheme of Algorithm 6
+ * with every graph as a root bisection), so the launch sequence and the
+ * host-device round trips are shared by the whole batch.
+ * graphs, k, eps: host arrays of n entries, each as for bp_partition (host
+ * pointers inside graphs[g]).  part_out: host array of n host pointers,
+ * part_out[g] receives int32[graphs[g].num_nodes] (may be NULL for a graph
+ * without nodes).  cut_out (nullable): host int64[n].  reports (nullable):
+ * host bp_report[n]; cut, max_part_weight, part_weight_limit and balanced are
+ * the graph's own, the counters (tree_levels ... kernel_launches) are those of
+ * the whole batch run.
+ * Every graph gets exactly the partition and cut bp_partition gives it alone.
+ * Returns BP_WARN_IMBALANCED if any graph's result is imbalanced; on an
+ * invalid graph returns its error and bp_last_error() names the graph index.
+ * n = 0 is valid; n <= 65535, and the batch's node, hyperedge and pin totals
+ * must each stay below 2^31.
+ */
+bp_status bp_partition_batch(int32_t n, const bp_hypergraph *graphs, const int32_t *k, const double *eps,
+                             const bp_params *params, int32_t *const *part_out, int64_t *cut_out,
+                             bp_report *reports);
+
+/*
+ * Same for graphs already in device memory: the structs and the k, eps,
+ * d_part_out and output arrays are host memory; the arrays inside graphs[g]
+ * and the d_part_out[g] buffers are device memory.  Validation as in
+ * bp_partition_device (repeated pins are not detected).  Ordered on stream;
+ * outputs are complete on return.
+ */
+bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, const int32_t *k,
+                                    const double *eps, const bp_params *params,
+                                    int32_t *const *d_part_out, int64_t *cut_out, bp_report *reports,
+                                    void *stream);
+
+/*
  * Connectivity-1 cut and heaviest part of a given partition (problem
  * statement, Section 1.1), computed on the device.  Host pointers; part[v] in
  * [0, k).  cut and max_part_weight are host outputs (nullable).

@@ -28,7 +28,8 @@ EXPORTS = [
     "bp_default_params", "bp_status_string", "bp_last_error", "bp_partition",
     "bp_partition_device", "bp_compute_cut", "bp_compute_cut_device", "bp_step_match",
     "bp_step_coarsen", "bp_step_gains", "bp_step_initial", "bp_step_refine", "bp_step_bisect",
-    "bp_profile_enable", "bp_profile_reset", "bp_profile_read",
+    "bp_profile_enable", "bp_profile_reset", "bp_profile_read", "bp_partition_batch",
+    "bp_partition_batch_device",
 ]
 
 
@@ -94,6 +95,8 @@ def lib():
         L.bp_step_initial.argtypes = [P, i32, i32, P, P]
         L.bp_step_refine.argtypes = [P, i32, i64, i64, P, P, P]
         L.bp_step_bisect.argtypes = [P, i32, i32, u64, P, P, P, P]
+        L.bp_partition_batch.argtypes = [i32, P, P, P, P, P, P, P]
+        L.bp_partition_batch_device.argtypes = [i32, P, P, P, P, P, P, P, P]
         L.bp_profile_enable.argtypes = [i32]
         L.bp_profile_enable.restype = None
         L.bp_profile_reset.argtypes = []
@@ -151,6 +154,34 @@ def partition_hg(h, k=None, eps=None, prm: Params | None = None):
     k = h.meta.get("k", 2) if k is None else k
     eps = h.meta.get("eps", 0.05) if eps is None else eps
     return partition(h.num_nodes, h.offsets, h.pins, k, eps, h.node_w, h.hedge_w, prm)
+
+
+def _batch_arrays(n, ks, epss):
+    ks = np.ascontiguousarray(ks, dtype=np.int32)
+    epss = np.ascontiguousarray(epss, dtype=np.float64)
+    if len(ks) != n or len(epss) != n:
+        raise ValueError("k and eps need one entry per graph")
+    return ks, epss
+
+
+def partition_batch(graphs, ks, epss, prm: Params | None = None):
+    """Batched form over host hypergraphs (objects with num_nodes, offsets, pins,
+    node_w, hedge_w): returns (list of parts, list of cuts, status, list of reports)."""
+    n = len(graphs)
+    keep = []
+    hgs = (Hypergraph * max(n, 1))()
+    for i, h in enumerate(graphs):
+        hgs[i] = _host_hg(h.num_nodes, h.offsets, h.pins, h.node_w, h.hedge_w, keep)
+    ks, epss = _batch_arrays(n, ks, epss)
+    parts = [np.empty(max(h.num_nodes, 1), np.int32) for h in graphs]
+    outs = (ctypes.c_void_p * max(n, 1))(*[p.ctypes.data for p in parts])
+    cuts = np.zeros(max(n, 1), np.int64)
+    reps = (Report * max(n, 1))()
+    st = _check(lib().bp_partition_batch(n, hgs, ks.ctypes.data, epss.ctypes.data,
+                                         None if prm is None else ctypes.byref(prm), outs,
+                                         cuts.ctypes.data, reps))
+    return ([p[:h.num_nodes] for p, h in zip(parts, graphs)], [int(c) for c in cuts[:n]], st,
+            [reps[i] for i in range(n)])
 
 
 def compute_cut(n, off, pins, part, k, nw=None, hw=None):
@@ -212,6 +243,27 @@ def partition_device(dh: DeviceHypergraph, k, eps, prm: Params | None = None, pa
                                           part_out.data_ptr(), ctypes.byref(cut),
                                           ctypes.byref(rep), _stream()))
     return part_out[:dh.num_nodes], int(cut.value), st, rep
+
+
+def partition_batch_device(dhs, ks, epss, prm: Params | None = None, parts_out=None):
+    """Batched form over DeviceHypergraphs: returns (list of part tensors, list of
+    cuts, status, list of reports)."""
+    import torch
+    n = len(dhs)
+    hgs = (Hypergraph * max(n, 1))()
+    for i, d in enumerate(dhs):
+        hgs[i] = d.struct()
+    ks, epss = _batch_arrays(n, ks, epss)
+    if parts_out is None:
+        parts_out = [torch.empty(max(d.num_nodes, 1), dtype=torch.int32, device="cuda") for d in dhs]
+    outs = (ctypes.c_void_p * max(n, 1))(*[p.data_ptr() for p in parts_out])
+    cuts = np.zeros(max(n, 1), np.int64)
+    reps = (Report * max(n, 1))()
+    st = _check(lib().bp_partition_batch_device(n, hgs, ks.ctypes.data, epss.ctypes.data,
+                                                None if prm is None else ctypes.byref(prm), outs,
+                                                cuts.ctypes.data, reps, _stream()))
+    return ([p[:d.num_nodes] for p, d in zip(parts_out, dhs)], [int(c) for c in cuts[:n]], st,
+            [reps[i] for i in range(n)])
 
 
 def compute_cut_device(dh: DeviceHypergraph, part, k):

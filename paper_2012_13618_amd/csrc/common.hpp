@@ -124,6 +124,27 @@ struct LaunchCtx {
 };
 
 template <typename K, typename... Args>
+inline void launch3(LaunchCtx &lc, const char *name, double bytes, K kernel, dim3 grid, int block,
+                    size_t lds, Args... args)
+{
+    if (grid.x == 0 || grid.y == 0 || grid.z == 0) return;
+    hipEvent_t a = nullptr, b = nullptr;
+    if (lc.prof) {
+        a = lc.ev();
+        b = lc.ev();
+        BP_HIP(hipEventRecord(a, lc.stream));
+    }
+    hipLaunchKernelGGL(kernel, grid, dim3(block), lds, lc.stream, args...);
+    BP_HIP(hipGetLastError());
+    lc.launches++;
+    if (lc.prof) {
+        BP_HIP(hipEventRecord(b, lc.stream));
+        lc.pending.push_back({name, bytes, a, b});
+        if (lc.pending.size() > 4096) lc.flush();
+    }
+}
+
+template <typename K, typename... Args>
 inline void launch(LaunchCtx &lc, const char *name, double bytes, K kernel, int64_t grid,
                    int block, size_t lds, Args... args)
 {

@@ -2,6 +2,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
 
 #include "engine.hpp"
 
@@ -516,11 +519,12 @@ struct TreeLevel {
     Level L;
     Segs sg;
     int32_t *ksub;  // [S]
+    uint64_t *F;    // [S] per-bisection factor
     int32_t *orig;  // [N] input node id
     int32_t active0;
 };
 
-static void seg_setup(Ctx &cx, TreeLevel &t, uint64_t F, const int32_t *k0_fixed = nullptr)
+static void seg_setup(Ctx &cx, TreeLevel &t, const int32_t *k0_fixed = nullptr)
 {
     LaunchCtx &lc = cx.lc;
     Level &L = t.L;
@@ -528,7 +532,8 @@ static void seg_setup(Ctx &cx, TreeLevel &t, uint64_t F, const int32_t *k0_fixed
     launch(lc, "seg_setup", 8.0 * L.N, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)t.sg.W);
     launch(lc, "seg_setup", 0.0, k_seg_setup, ceil_div(L.S, kBlock), kBlock, 0, L.S,
-           (const int32_t *)t.ksub, k0_fixed, (const int64_t *)t.sg.W, F, (const int32_t *)L.nbase,
+           (const int32_t *)t.ksub, k0_fixed, (const int64_t *)t.sg.W, (const uint64_t *)t.F,
+           (const int32_t *)L.nbase,
            (const int32_t *)L.hbase, cx.prm.max_levels, cx.prm.min_coarse_nodes, t.sg.k0, t.sg.k1,
            t.sg.max0, t.sg.max1, t.sg.active, t.sg.coarsest, t.sg.stuck, cx.info_d);
 }
@@ -582,10 +587,11 @@ static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
     ct.pbase = ar.get<int32_t>(2 * S + 1);
     ct.k = ar.get<int32_t>(2 * S);
     ct.lo = ar.get<int32_t>(2 * S);
+    ct.F = ar.get<uint64_t>(2 * S);
     cx.clear_info();
     launch(lc, "extract", 0.0, k_child_table, 1, 1, 0, S, N, E, (const int32_t *)L.nbase,
            (const int32_t *)L.hbase, (const int32_t *)t.sg.k0, (const int32_t *)t.sg.k1,
-           (const int32_t *)t.sg.lo, (const uint64_t *)nscan, (const uint64_t *)hs0,
+           (const int32_t *)t.sg.lo, (const uint64_t *)t.F, (const uint64_t *)nscan, (const uint64_t *)hs0,
            (const uint64_t *)hs1, (const uint64_t *)tots, (const uint64_t *)(tots + 1),
            (const uint64_t *)(tots + 2), ct, cx.info_d);
     LevelInfo inf = cx.readback();
@@ -628,18 +634,19 @@ static bool extract(Ctx &cx, TreeLevel &t, int32_t *d_part, TreeLevel &nx)
     c.nbase = ct.nbase;
     c.hbase = ct.hbase;
     nx.ksub = ct.k;
+    nx.F = ct.F;
     nx.sg = alloc_segs(ar, C);
     BP_HIP(hipMemcpyAsync(nx.sg.lo, ct.lo, sizeof(int32_t) * C, hipMemcpyDeviceToDevice, lc.stream));
     return true;
 }
 
-static void prepare_tree_level(Ctx &cx, TreeLevel &t, uint64_t F)
+static void prepare_tree_level(Ctx &cx, TreeLevel &t)
 {
     int32_t *ctr = cx.ar->get<int32_t>(8);
     fill(cx.lc, ctr, 8, 0);
     classify(cx, t.L, ctr);
     cx.clear_info();
-    seg_setup(cx, t, F);
+    seg_setup(cx, t);
     // fold the schedule counts into the same readback
     BP_HIP(hipMemcpyAsync(&cx.info_d->nmid, ctr + 1, 3 * sizeof(int32_t), hipMemcpyDeviceToDevice,
                           cx.lc.stream));
@@ -726,6 +733,17 @@ static int64_t validate_device(Ctx &cx, const Input &in)
     return sn;
 }
 
+// The balance limit of the problem statement, max(ceil(W/k), floor((1+eps) W / k)),
+// with (1+eps) in 32.32 fixed point.
+int64_t part_limit(int64_t W, int32_t k, double eps)
+{
+    uint64_t F0 = (uint64_t)std::floor(std::ldexp(1.0 + eps, 32));
+    unsigned __int128 a = (unsigned __int128)(uint64_t)W * F0;
+    int64_t lim_f = (int64_t)(a / ((unsigned __int128)(uint64_t)k << 32));
+    int64_t lim_c = (W + k - 1) / k;
+    return std::max(lim_f, lim_c);
+}
+
 bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int32_t *d_part,
                            int64_t *cut_out, bp_report *rep)
 {
@@ -743,11 +761,13 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         t.sg = alloc_segs(*cx.ar, 1);
         t.ksub = cx.ar->get<int32_t>(1);
         launch(lc, "seg_setup", 4.0, k_set_i32, 1, 1, 0, t.ksub, k);
+        t.F = cx.ar->get<uint64_t>(1);
+        fill(lc, t.F, 1, F);
         fill(lc, t.sg.lo, 1, 0);
         t.orig = cx.ar->get<int32_t>(in.N);
         launch(lc, "seg_setup", 4.0 * in.N, k_iota, std::min<int64_t>(ceil_div(in.N, kBlock), 4096), kBlock,
                0, (int64_t)in.N, t.orig);
-        prepare_tree_level(cx, t, F);
+        prepare_tree_level(cx, t);
         root = t.L;  // keep the schedule lists for the final cut
         for (;;) {
             tree_levels++;
@@ -755,7 +775,7 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
             bisect_all(cx, t.L, t.sg, t.active0);
             TreeLevel nx;
             if (!extract(cx, t, d_part, nx)) break;
-            prepare_tree_level(cx, nx, F);
+            prepare_tree_level(cx, nx);
             t = nx;
         }
     }
@@ -765,11 +785,7 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         cr.maxw = W;
     }
     if (cut_out) *cut_out = cr.cut;
-    uint64_t F0 = (uint64_t)std::floor(std::ldexp(1.0 + eps, 32));
-    unsigned __int128 a = (unsigned __int128)(uint64_t)W * F0;
-    int64_t lim_f = (int64_t)(a / ((unsigned __int128)(uint64_t)k << 32));
-    int64_t lim_c = (W + k - 1) / k;
-    int64_t limit = std::max(lim_f, lim_c);
+    int64_t limit = part_limit(W, k, eps);
     bool balanced = cr.maxw <= limit;
     if (rep) {
         rep->cut = cr.cut;
@@ -785,6 +801,233 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         rep->kernel_launches = lc.launches;
     }
     return balanced ? BP_OK : BP_WARN_IMBALANCED;
+}
+
+// ---- batches of independent graphs ----------------------------------------------------
+//
+// Graph g of the batch is segment g of the first tree level (graphs that need
+// no bisection - k = 1 or no node - are placed after the others and only
+// copied).  Every later step is the segmented k-way loop above, so each graph
+// gets the partition it gets alone.
+
+template <typename T> static T *upload_vec(Ctx &cx, const std::vector<T> &v)
+{
+    T *p = cx.ar->get<T>((int64_t)std::max<size_t>(v.size(), 1));
+    if (!v.empty())
+        BP_HIP(hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, cx.lc.stream));
+    return p;
+}
+
+std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
+                                      const std::vector<int32_t *> &d_out, int32_t *tree_levels)
+{
+    Arena &ar = *cx.ar;
+    LaunchCtx &lc = cx.lc;
+    const int32_t n = (int32_t)it.size();
+    std::vector<BatchOut> res(n);
+    if (tree_levels) *tree_levels = 0;
+    if (n == 0) return res;
+    if (n > 65535) throw Error(BP_ERR_INVALID_ARG, "batch of more than 65535 graphs");
+    std::vector<int32_t> order;
+    for (int32_t g = 0; g < n; g++)
+        if (it[g].k >= 2 && it[g].N > 0) order.push_back(g);
+    const int32_t S = (int32_t)order.size();
+    for (int32_t g = 0; g < n; g++)
+        if (!(it[g].k >= 2 && it[g].N > 0)) order.push_back(g);
+
+    // sizes, then the concatenation (with the same checks as a single input)
+    std::vector<GraphDesc> d(n);
+    for (int32_t i = 0; i < n; i++) {
+        const BatchItem &x = it[order[i]];
+        d[i] = GraphDesc{x.off, x.pins, x.nw, x.hw, x.N, x.E, 0, 0, 0};
+    }
+    GraphDesc *dd = upload_vec(cx, d);
+    GraphCheck *chk = ar.get<GraphCheck>(n);
+    launch(lc, "batch", 0.0, k_batch_sizes, ceil_div(n, kBlock), kBlock, 0, n, (const GraphDesc *)dd, chk);
+    std::vector<GraphCheck> ch(n);
+    BP_HIP(hipMemcpyAsync(ch.data(), chk, sizeof(GraphCheck) * n, hipMemcpyDeviceToHost, lc.stream));
+    lc.sync();
+    int64_t nb = 0, eb = 0, pb = 0, work = 1;
+    for (int32_t i = 0; i < n; i++) {
+        if (ch[i].bad_offsets)
+            throw Error(BP_ERR_INVALID_CSR, "graph " + std::to_string(order[i]) + ": invalid CSR offsets");
+        d[i].nbase = nb;
+        d[i].ebase = eb;
+        d[i].pbase = pb;
+        nb += d[i].N;
+        eb += d[i].E;
+        pb += ch[i].P;
+        work = std::max({work, (int64_t)d[i].N, (int64_t)d[i].E, ch[i].P});
+    }
+    if (nb >= INT32_MAX || eb >= INT32_MAX || pb >= INT32_MAX)
+        throw Error(BP_ERR_INVALID_ARG, "batch too large: nodes, hyperedges and pins must each total < 2^31");
+    BP_HIP(hipMemcpyAsync(dd, d.data(), sizeof(GraphDesc) * n, hipMemcpyHostToDevice, lc.stream));
+    int32_t *off = ar.get<int32_t>(eb + 1), *pins = ar.get<int32_t>(std::max<int64_t>(pb, 1));
+    int32_t *nw = ar.get<int32_t>(std::max<int64_t>(nb, 1)), *hw = ar.get<int32_t>(std::max<int64_t>(eb, 1));
+    int32_t *nseg = ar.get<int32_t>(std::max<int64_t>(nb, 1)), *eseg = ar.get<int32_t>(std::max<int64_t>(eb, 1));
+    unsigned gx = (unsigned)std::min<int64_t>(ceil_div(work, kBlock), 64);
+    launch3(lc, "batch", 4.0 * (2 * pb + 4 * eb + 3 * nb), k_batch_gather, dim3(gx, (unsigned)n), kBlock, 0,
+            (const GraphDesc *)dd, chk, off, pins, nw, hw, nseg, eseg);
+    launch(lc, "batch", 4.0, k_set_i32, 1, 1, 0, off + eb, (int32_t)pb);
+    BP_HIP(hipMemcpyAsync(ch.data(), chk, sizeof(GraphCheck) * n, hipMemcpyDeviceToHost, lc.stream));
+    lc.sync();
+    std::vector<int64_t> W(n);
+    for (int32_t i = 0; i < n; i++) {
+        std::string gname = "graph " + std::to_string(order[i]) + ": ";
+        if (ch[i].bad_offsets) throw Error(BP_ERR_INVALID_CSR, gname + "hedge offsets not monotone");
+        if (ch[i].bad_pins) throw Error(BP_ERR_INVALID_CSR, gname + "pin out of range");
+        if (ch[i].bad_weights) throw Error(BP_ERR_WEIGHT_OVERFLOW, gname + "negative weight");
+        if (ch[i].sum_nw >= (1ull << 31) || ch[i].sum_hw >= (1ull << 31))
+            throw Error(BP_ERR_WEIGHT_OVERFLOW, gname + "weight sum >= 2^31");
+        W[i] = (int64_t)ch[i].sum_nw;
+    }
+    const int64_t Neng = S < n ? d[S].nbase : nb, Eeng = S < n ? d[S].ebase : eb;
+    int32_t *part = ar.get<int32_t>(std::max<int64_t>(nb, 1));
+    if (nb > Neng) fill(lc, part + Neng, nb - Neng, 0);
+    for (int32_t i = S; i < n; i++) {
+        const BatchItem &x = it[order[i]];
+        BatchOut &r = res[order[i]];
+        r.cut = 0;
+        r.maxw = W[i];
+        r.limit = part_limit(W[i], x.k, x.eps);
+        r.balanced = r.maxw <= r.limit;
+    }
+
+    if (S > 0) {
+        // level 0: hyperedges of >= 2 pins, per segment, in input order
+        Level L;
+        L.S = S;
+        L.N = (int32_t)Neng;
+        uint64_t *kept = ar.get<uint64_t>(std::max<int64_t>(Eeng, 1));
+        int32_t *dst = ar.get<int32_t>(std::max<int64_t>(Eeng, 1));
+        L.off = ar.get<int32_t>(Eeng + 1);
+        L.hw = ar.get<int32_t>(std::max<int64_t>(Eeng, 1));
+        L.hseg = ar.get<int32_t>(std::max<int64_t>(Eeng, 1));
+        uint64_t *tot = ar.get<uint64_t>(1);
+        {
+            int32_t *loff = L.off, *lhw = L.hw, *lhseg = L.hseg;
+            const int32_t *coff = off, *chw = hw, *ceseg = eseg;
+            scan<uint64_t>(
+                lc, ar, "normalize_scan", Eeng,
+                [=] __device__(int64_t e) -> uint64_t {
+                    int32_t dg = coff[e + 1] - coff[e];
+                    return dg >= 2 ? ((1ull << 32) | (uint32_t)dg) : 0ull;
+                },
+                [=] __device__(int64_t e, uint64_t ex, uint64_t val) {
+                    kept[e] = ex;
+                    if (!val) return;
+                    int32_t id = (int32_t)(ex >> 32);
+                    loff[id] = (int32_t)ex;
+                    lhw[id] = chw[e];
+                    lhseg[id] = ceseg[e];
+                    dst[e] = (int32_t)ex;
+                },
+                tot);
+        }
+        BP_HIP(hipMemcpyAsync(cx.info_h, tot, sizeof(uint64_t), hipMemcpyDeviceToHost, lc.stream));
+        lc.sync();
+        uint64_t tv = *(uint64_t *)cx.info_h;
+        L.E = (int32_t)(tv >> 32);
+        L.P = (int32_t)(tv & 0xffffffffu);
+        L.pins = ar.get<int32_t>(std::max<int32_t>(L.P, 1));
+        launch(lc, "normalize_copy", 8.0 * L.P, k_norm_copy, ceil_div(Eeng, kBlock), kBlock, 0, (int32_t)Eeng,
+               (const int32_t *)off, (const int32_t *)pins, (const int32_t *)dst, L.pins);
+        launch(lc, "normalize", 4.0, k_set_i32, 1, 1, 0, L.off + L.E, L.P);
+        L.nw = nw;
+        L.nseg = nseg;
+        std::vector<int32_t> nbh(S + 1);
+        std::vector<int64_t> ebh(S + 1);
+        for (int32_t i = 0; i <= S; i++) {
+            nbh[i] = (int32_t)(i < n ? d[i].nbase : nb);
+            ebh[i] = i < n ? d[i].ebase : eb;
+        }
+        L.nbase = upload_vec(cx, nbh);
+        int64_t *ebd = upload_vec(cx, ebh);
+        L.hbase = ar.get<int32_t>(S + 1);
+        int32_t *pbk = ar.get<int32_t>(S + 1);
+        launch(lc, "normalize", 0.0, k_batch_hbase, ceil_div(S + 1, kBlock), kBlock, 0, S,
+               (const int64_t *)ebd, Eeng, (const uint64_t *)kept, (const uint64_t *)tot, L.hbase, pbk);
+
+        // first tree level: one segment per graph, its own k and factor
+        std::vector<int32_t> kh(S), kb(S + 1, 0);
+        std::vector<uint64_t> fh(S);
+        int32_t kmax = 1;
+        for (int32_t i = 0; i < S; i++) {
+            const BatchItem &x = it[order[i]];
+            kh[i] = x.k;
+            fh[i] = eps_factor(x.k, x.eps);
+            kb[i + 1] = kb[i] + x.k;
+            kmax = std::max(kmax, x.k);
+        }
+        TreeLevel t;
+        t.L = L;
+        t.sg = alloc_segs(ar, S);
+        t.ksub = upload_vec(cx, kh);
+        t.F = upload_vec(cx, fh);
+        fill(lc, t.sg.lo, S, 0);
+        t.orig = ar.get<int32_t>(Neng);
+        launch(lc, "seg_setup", 4.0 * Neng, k_iota, std::min<int64_t>(ceil_div(Neng, kBlock), 4096), kBlock, 0,
+               Neng, t.orig);
+        prepare_tree_level(cx, t);
+        Level root = t.L;
+        int32_t tl = 0;
+        for (;;) {
+            tl++;
+            cx.bisections += t.L.S;
+            bisect_all(cx, t.L, t.sg, t.active0);
+            TreeLevel nx;
+            if (!extract(cx, t, part, nx)) break;
+            prepare_tree_level(cx, nx);
+            t = nx;
+        }
+        if (tree_levels) *tree_levels = tl;
+
+        // per-graph cut (connectivity - 1) and heaviest part
+        int32_t *kbd = upload_vec(cx, kb);
+        unsigned long long *acc = ar.get<unsigned long long>(2 * S);
+        unsigned long long *pw = ar.get<unsigned long long>(kb[S]);
+        fill(lc, acc, 2 * S, 0ull);
+        fill(lc, pw, kb[S], 0ull);
+        check_lists(root);
+        launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, sched_grid<SMALL>(root.E), kBlock,
+               0, root.E, (const int32_t *)nullptr, (const int32_t *)root.off, (const int32_t *)root.pins,
+               (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
+        launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, sched_grid<WAVE>(root.nmid), kBlock, 0, root.nmid,
+               (const int32_t *)root.lmid, (const int32_t *)root.off, (const int32_t *)root.pins,
+               (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
+        launch(lc, "cut_block", 0.0, k_cut_seg<BLOCK>, sched_grid<BLOCK>(root.nbig), kBlock, 0, root.nbig,
+               (const int32_t *)root.lbig, (const int32_t *)root.off, (const int32_t *)root.pins,
+               (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
+        launch(lc, "part_weights", 8.0 * Neng, k_part_weights_seg, ceil_div(Neng, kBlock), kBlock, 0,
+               (int32_t)Neng, (const int32_t *)nseg, (const int32_t *)kbd, (const int32_t *)part,
+               (const int32_t *)nw, pw);
+        launch(lc, "cut", 0.0, k_seg_max, ceil_div(S, kBlock), kBlock, 0, S, (const int32_t *)kbd,
+               (const unsigned long long *)pw, acc + S);
+        std::vector<unsigned long long> accv(2 * S);
+        BP_HIP(hipMemcpyAsync(accv.data(), acc, sizeof(unsigned long long) * 2 * S, hipMemcpyDeviceToHost,
+                              lc.stream));
+        lc.sync();
+        for (int32_t i = 0; i < S; i++) {
+            const BatchItem &x = it[order[i]];
+            BatchOut &r = res[order[i]];
+            r.cut = (int64_t)accv[i];
+            r.maxw = (int64_t)accv[S + i];
+            r.limit = part_limit(W[i], x.k, x.eps);
+            r.balanced = r.maxw <= r.limit;
+        }
+    }
+
+    // part ids into every graph's own buffer
+    std::vector<int32_t *> outs(n);
+    int64_t maxn = 1;
+    for (int32_t i = 0; i < n; i++) {
+        outs[i] = d_out[order[i]];
+        maxn = std::max<int64_t>(maxn, d[i].N);
+    }
+    int32_t **outd = upload_vec(cx, outs);
+    launch3(lc, "batch", 8.0 * nb, k_batch_scatter, dim3((unsigned)std::min<int64_t>(ceil_div(maxn, kBlock), 64), (unsigned)n),
+            kBlock, 0, (const GraphDesc *)dd, (int32_t *const *)outd, (const int32_t *)part);
+    return res;
 }
 
 // ---- context pool -------------------------------------------------------------------
@@ -1026,6 +1269,120 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
     BP_GUARD_BEGIN
     CtxGuard g((hipStream_t)stream, params);
     return partition_device(g.cx, device_input(hg), k, eps, d_part_out, cut_out, report);
+    BP_GUARD_END
+}
+
+static void fill_batch_reports(const Ctx &cx, const std::vector<BatchOut> &res, int32_t tree_levels,
+                               int64_t *cut_out, bp_report *reports)
+{
+    for (size_t g = 0; g < res.size(); g++) {
+        if (cut_out) cut_out[g] = res[g].cut;
+        if (!reports) continue;
+        bp_report &r = reports[g];
+        r.cut = res[g].cut;
+        r.max_part_weight = res[g].maxw;
+        r.part_weight_limit = res[g].limit;
+        r.balanced = res[g].balanced;
+        r.tree_levels = tree_levels;
+        r.bisections = cx.bisections;
+        r.coarsen_levels = cx.first_levels < 0 ? 0 : cx.first_levels;
+        r.pins_coarsened = cx.pins_coarsened;
+        r.pins_refined = cx.pins_refined;
+        r.host_syncs = cx.lc.syncs;
+        r.kernel_launches = cx.lc.launches;
+    }
+}
+
+static bp_status batch_status(const std::vector<BatchOut> &res)
+{
+    for (auto &r : res)
+        if (!r.balanced) return BP_WARN_IMBALANCED;
+    return BP_OK;
+}
+
+static bp_status check_batch_args(int32_t n, const bp_hypergraph *graphs, const int32_t *k, const double *eps,
+                                  const void *outs, const bp_params *params)
+{
+    if (n < 0) return fail(BP_ERR_INVALID_ARG, "n < 0");
+    if (n > 0 && (!graphs || !k || !eps || !outs)) return fail(BP_ERR_INVALID_ARG, "NULL batch array");
+    bp_status st = check_params(params);
+    if (st != BP_OK) return st;
+    for (int32_t g = 0; g < n; g++)
+        if (k[g] < 1 || !(eps[g] >= 0.0) || std::isinf(eps[g]))
+            return fail(BP_ERR_INVALID_ARG, "graph " + std::to_string(g) + ": k < 1 or bad eps");
+    return BP_OK;
+}
+
+bp_status bp_partition_batch(int32_t n, const bp_hypergraph *graphs, const int32_t *k, const double *eps,
+                             const bp_params *params, int32_t *const *part_out, int64_t *cut_out,
+                             bp_report *reports)
+{
+    bp_status st = check_batch_args(n, graphs, k, eps, part_out, params);
+    if (st != BP_OK) return st;
+    for (int32_t g = 0; g < n; g++) {
+        if ((st = validate_host(&graphs[g])) != BP_OK)
+            return fail(st, "graph " + std::to_string(g) + ": " + g_last_error);
+        if (!part_out[g] && graphs[g].num_nodes > 0)
+            return fail(BP_ERR_INVALID_ARG, "graph " + std::to_string(g) + ": part_out is NULL");
+    }
+    if (n == 0) return BP_OK;
+    BP_GUARD_BEGIN
+    CtxGuard gd(nullptr, params);
+    Ctx &cx = gd.cx;
+    std::vector<BatchItem> items(n);
+    std::vector<int32_t *> outs(n);
+    std::vector<int64_t> obase(n + 1, 0);
+    for (int32_t g = 0; g < n; g++) obase[g + 1] = obase[g] + graphs[g].num_nodes;
+    int32_t *dpart = cx.ar->get<int32_t>(std::max<int64_t>(obase[n], 1));
+    for (int32_t g = 0; g < n; g++) {
+        Input in = upload(cx, &graphs[g]);
+        items[g] = BatchItem{in.N, in.E, in.off, in.pins, in.nw, in.hw, k[g], eps[g]};
+        outs[g] = dpart + obase[g];
+    }
+    int32_t tl = 0;
+    std::vector<BatchOut> res = partition_batch(cx, items, outs, &tl);
+    std::vector<int32_t> host((size_t)obase[n]);
+    if (obase[n] > 0)
+        BP_HIP(hipMemcpyAsync(host.data(), dpart, sizeof(int32_t) * (size_t)obase[n], hipMemcpyDeviceToHost,
+                              cx.lc.stream));
+    BP_HIP(hipStreamSynchronize(cx.lc.stream));
+    for (int32_t g = 0; g < n; g++)
+        if (graphs[g].num_nodes > 0)
+            std::memcpy(part_out[g], host.data() + obase[g], sizeof(int32_t) * (size_t)graphs[g].num_nodes);
+    fill_batch_reports(cx, res, tl, cut_out, reports);
+    return batch_status(res);
+    BP_GUARD_END
+}
+
+bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, const int32_t *k,
+                                    const double *eps, const bp_params *params,
+                                    int32_t *const *d_part_out, int64_t *cut_out, bp_report *reports,
+                                    void *stream)
+{
+    bp_status st = check_batch_args(n, graphs, k, eps, d_part_out, params);
+    if (st != BP_OK) return st;
+    for (int32_t g = 0; g < n; g++) {
+        if ((st = check_device_hg(&graphs[g])) != BP_OK)
+            return fail(st, "graph " + std::to_string(g) + ": " + g_last_error);
+        if (!d_part_out[g] && graphs[g].num_nodes > 0)
+            return fail(BP_ERR_INVALID_ARG, "graph " + std::to_string(g) + ": d_part_out is NULL");
+    }
+    if (n == 0) return BP_OK;
+    BP_GUARD_BEGIN
+    CtxGuard gd((hipStream_t)stream, params);
+    Ctx &cx = gd.cx;
+    std::vector<BatchItem> items(n);
+    std::vector<int32_t *> outs(n);
+    for (int32_t g = 0; g < n; g++) {
+        Input in = device_input(&graphs[g]);
+        items[g] = BatchItem{in.N, in.E, in.off, in.pins, in.nw, in.hw, k[g], eps[g]};
+        outs[g] = d_part_out[g];
+    }
+    int32_t tl = 0;
+    std::vector<BatchOut> res = partition_batch(cx, items, outs, &tl);
+    BP_HIP(hipStreamSynchronize(cx.lc.stream));
+    fill_batch_reports(cx, res, tl, cut_out, reports);
+    return batch_status(res);
     BP_GUARD_END
 }
 
@@ -1271,8 +1628,10 @@ bp_status bp_step_bisect(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint64
     fill(cx.lc, t.ksub, 1, k0 + k1);
     int32_t *k0_fixed = cx.ar->get<int32_t>(1);
     fill(cx.lc, k0_fixed, 1, k0);
+    t.F = cx.ar->get<uint64_t>(1);
+    fill(cx.lc, t.F, 1, F);
     cx.clear_info();
-    seg_setup(cx, t, F, k0_fixed);
+    seg_setup(cx, t, k0_fixed);
     LevelInfo inf = cx.readback();
     t.active0 = inf.active;
     bisect_all(cx, t.L, t.sg, t.active0);

@@ -1,5 +1,6 @@
 // Host driver of the device-resident multilevel bisection engine.
 #pragma once
+#include "batch.hpp"
 #include "coarsen.hpp"
 #include "kway.hpp"
 #include "refine.hpp"
@@ -65,9 +66,10 @@ __global__ __launch_bounds__(kBlock) void k_seg_total(int32_t N, const int32_t *
 }
 
 // Bisection split, side bounds and coarsening start state of every segment.
-// bound_s = max(ceil(W k_s / k_sub), floor(W k_s F / (k_sub 2^32))).
+// bound_s = max(ceil(W k_s / k_sub), floor(W k_s F / (k_sub 2^32))), with F the
+// per-bisection fixed-point factor of the graph the segment descends from.
 __global__ void k_seg_setup(int32_t S, const int32_t *ksub, const int32_t *k0_fixed,
-                            const int64_t *W, uint64_t F,
+                            const int64_t *W, const uint64_t *Fs,
                             const int32_t *nbase, const int32_t *hbase, int32_t max_levels,
                             int32_t min_nodes, int32_t *k0, int32_t *k1, int64_t *max0,
                             int64_t *max1, uint8_t *active, int32_t *coarsest, int32_t *stuck,
@@ -79,7 +81,7 @@ __global__ void k_seg_setup(int32_t S, const int32_t *ksub, const int32_t *k0_fi
     int32_t a = k0_fixed ? k0_fixed[s] : (ks + 1) / 2, b = ks - a;
     k0[s] = a;
     k1[s] = b;
-    uint64_t w = (uint64_t)W[s];
+    uint64_t w = (uint64_t)W[s], F = Fs[s];
     for (int sd = 0; sd < 2; sd++) {
         uint64_t kk = sd ? b : a;
         uint64_t prod = w * kk;  // < 2^62
@@ -236,6 +238,24 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     g.ccount = ar.get<int32_t>(S);
     return g;
 }
+
+// one graph of a batch (device arrays)
+struct BatchItem {
+    int32_t N = 0, E = 0;
+    const int32_t *off = nullptr, *pins = nullptr, *nw = nullptr, *hw = nullptr;
+    int32_t k = 1;
+    double eps = 0.0;
+};
+
+struct BatchOut {
+    int64_t cut = 0, maxw = 0, limit = 0;
+    int32_t balanced = 1;
+};
+
+std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
+                                      const std::vector<int32_t *> &d_out, int32_t *tree_levels);
+int64_t part_limit(int64_t W, int32_t k, double eps);
+uint64_t eps_factor(int32_t k, double eps);
 
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
                    Level &c);

@@ -125,11 +125,13 @@ struct ChildTable {
     int32_t *pbase;   // [C+1]
     int32_t *k;       // [C] parts of each child
     int32_t *lo;      // [C]
+    uint64_t *F;      // [C] per-bisection factor, inherited from the parent
 };
 
 __global__ void k_child_table(int32_t S, int32_t N, int32_t E, const int32_t *nbase,
                               const int32_t *hbase, const int32_t *k0, const int32_t *k1,
-                              const int32_t *lo, const uint64_t *nscan, const uint64_t *hscan0,
+                              const int32_t *lo, const uint64_t *F, const uint64_t *nscan,
+                              const uint64_t *hscan0,
                               const uint64_t *hscan1, const uint64_t *ntot, const uint64_t *htot0,
                               const uint64_t *htot1, ChildTable ct, LevelInfo *info)
 {
@@ -158,6 +160,7 @@ __global__ void k_child_table(int32_t S, int32_t N, int32_t E, const int32_t *nb
             ct.pbase[c] = pb;
             ct.k[c] = kk;
             ct.lo[c] = lo[s] + (sd ? k0[s] : 0);
+            ct.F[c] = F[s];
             nb += nn;
             hb += ne;
             pb += np;

@@ -74,3 +74,20 @@ def test_library_has_no_cpu_fallback():
         pytest.skip("a GPU is present")
     h = I.random_small(20, 15, 2, 4, 0)
     _expect(-5, lambda: bp.partition(h.num_nodes, h.offsets, h.pins, 2, 0.05))
+
+
+def test_batch_host_validation_errors():
+    a = I.random_small(30, 20, 2, 4, 1)
+    b = I.random_small(30, 20, 2, 4, 2)
+    bad = I.Hypergraph(b.num_nodes, b.offsets, b.pins.copy(), b.node_w, b.hedge_w)
+    bad.pins[0] = -1
+    with pytest.raises(bp.BipartError) as ei:
+        bp.partition_batch([a, bad], [2, 2], [0.05, 0.05])
+    assert ei.value.status == -2 and "graph 1" in str(ei.value)
+    _expect(-1, lambda: bp.partition_batch([a, b], [2, 0], [0.05, 0.05]))
+    _expect(-1, lambda: bp.partition_batch([a, b], [2, 2], [0.05, float("inf")]))
+    _expect(-3, lambda: bp.partition_batch(
+        [a, I.Hypergraph(30, b.offsets, b.pins, np.full(30, 2 ** 27, np.int32), b.hedge_w)],
+        [2, 2], [0.05, 0.05]))
+    with pytest.raises(ValueError):
+        bp.partition_batch([a, b], [2], [0.05, 0.05])
