@@ -48,6 +48,26 @@ def make_workload(name):
     return h, desc
 
 
+BATCH_DESC = ("batch of 256 netlist-shaped graphs: N log-uniform in [1e3, 2e5], E = 1.2 N, "
+              "degree power-law alpha=2.5 on [2,1000] with 80% local pins; k = 2 for even members, "
+              "4 for odd; eps = 0.05")
+
+
+def cpu_baseline_batch(hs, budget_s):
+    """The sequential oracle over members of the batch, in order, until the budget."""
+    import oracle
+    pins, runs, t0 = 0, 0, time.perf_counter()
+    for h in hs:
+        oracle.partition_hg(h)
+        pins += h.num_pins
+        runs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": pins / el, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": f"the first {runs} of the 256 members ({pins} pins), {el:.1f} s single-threaded"}
+
+
 def cpu_baseline(h, k, eps, budget_s):
     """The sequential oracle, single-threaded, on the same workload."""
     import oracle
@@ -63,6 +83,137 @@ def cpu_baseline(h, k, eps, budget_s):
                       f"{el:.1f} s single-threaded"}
 
 
+def profiled_step(step):
+    """One more step with per-launch hipEvent timing on the launching stream;
+    returns the roofline entry of the kernel with the largest share of time."""
+    import torch
+    import paper_2012_13618_amd as bp
+    bp.profile_reset()
+    bp.profile_enable(True)
+    step()
+    torch.cuda.synchronize()
+    bp.profile_enable(False)
+    stats = sorted(bp.profile_read(), key=lambda s: -s["total_ms"])
+    tot = sum(s["total_ms"] for s in stats)
+    log(f"kernel time (profiled step): {tot:.3f} ms over "
+        f"{sum(s['launches'] for s in stats)} launches")
+    for s in stats[:25]:
+        gbs = s["bytes"] / (s["total_ms"] * 1e6) if s["total_ms"] > 0 else 0
+        log(f"  {s['name']:<16} {s['launches']:6d} launches {s['total_ms']:8.3f} ms "
+            f"avg {1000 * s['total_ms'] / s['launches']:8.2f} us  {gbs:8.1f} GB/s")
+    dom = next((s for s in stats if s["bytes"] > 0), None)
+    if not dom:
+        return None
+    achieved = dom["bytes"] / (dom["total_ms"] * 1e6)
+    return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None, "avg_launch_us": round(1000 * dom["total_ms"] / dom["launches"], 3),
+            "launches_per_step": dom["launches"],
+            "share_of_kernel_time": round(dom["total_ms"] / tot, 4)}
+
+
+def bench_batch(args):
+    """One step = one bp_partition_batch_device call over the 256-graph batch."""
+    import torch
+    import paper_2012_13618_amd as bp
+    from paper_2012_13618_amd import inputs as I
+    hs = [I.batch_member(i) for i in range(256)]
+    ks = [h.meta["k"] for h in hs]
+    es = [h.meta["eps"] for h in hs]
+    pins = sum(h.num_pins for h in hs)
+    log(f"workload batch: 256 graphs, N={sum(h.num_nodes for h in hs)} P={pins}")
+    dev = [bp.DeviceHypergraph.from_host(h) for h in hs]
+    outs = [torch.empty(max(h.num_nodes, 1), dtype=torch.int32, device="cuda") for h in hs]
+    torch.cuda.synchronize()
+    run = lambda: bp.partition_batch_device(dev, ks, es, parts_out=outs)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, cuts, status, reps = run()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = el * 1000.0 / args.steps
+    value = pins * args.steps / el
+    log(f"{ms:.3f} ms/step  {value / 1e9:.3f} Gpins/s  total cut={sum(cuts)} "
+        f"status={bp.STATUS[status]} launches={reps[0].kernel_launches} syncs={reps[0].host_syncs}")
+    # the same graphs one call at a time, for comparison
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(256):
+        bp.partition_device(dev[i], ks[i], es[i], part_out=outs[i])
+    torch.cuda.synchronize()
+    seq_ms = (time.perf_counter() - t1) * 1000.0
+    log(f"one call per graph: {seq_ms:.3f} ms for the 256 graphs ({ms / seq_ms:.3f} of it batched)")
+    roofline = None if args.no_profile else profiled_step(run)
+    cpu = None if args.no_cpu_baseline else cpu_baseline_batch(hs, args.cpu_budget)
+    if cpu:
+        log(f"cpu oracle: {cpu['value'] / 1e6:.3f} Mpins/s ({cpu['sample']})")
+    line = {"metric": METRIC, "value": value, "unit": "pins/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": BATCH_DESC, "graphs": 256, "pins": pins, "parallelism": "1 GPU",
+                       "one_call_per_graph_ms": round(seq_ms, 3), "total_cut": sum(cuts)},
+            "roofline": roofline, "cpu_baseline": cpu}
+    print(json.dumps(line), flush=True)
+
+
+SERVE_DESC = ("served stream: open-loop Poisson arrivals; request pins log-uniform in [1e4, 2e6], "
+              "netlist-shaped, N = pins / (1.2 x 4.54), E = 1.2 N, k uniform in {2, 4, 16}, eps = 0.05")
+
+
+def bench_serve(args):
+    """Open-loop Poisson stream into the server; value = pins/s delivered over
+    the makespan; latency percentiles are submission to results on the host."""
+    import threading
+    import numpy as np
+    import paper_2012_13618_amd as bp
+    from paper_2012_13618_amd import inputs as I
+    R = args.requests
+    reqs = [I.serve_request(r) for r in range(R)]
+    arrivals = I.poisson_arrivals(R, args.rate)
+    pins = sum(h.num_pins for h in reqs)
+    log(f"workload serve: {R} requests, {pins} pins, rate {args.rate}/s")
+    with bp.Server(hbm_budget_bytes=args.budget_gib << 30, max_slots=args.slots) as srv:
+        for h in reqs[:args.warmup]:  # warm the worker's device memory
+            srv.wait(srv.submit(h))
+        tickets = [None] * R
+        t0 = time.perf_counter()
+
+        def feeder():
+            for i, h in enumerate(reqs):
+                d = t0 + arrivals[i] - time.perf_counter()
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(h)
+
+        th = threading.Thread(target=feeder)
+        th.start()
+        stats = []
+        for i in range(R):
+            while tickets[i] is None:
+                time.sleep(0.0005)
+            stats.append(srv.wait(tickets[i])[3])
+        th.join()
+        el = time.perf_counter() - t0
+    lat = np.array([s.latency_ms for s in stats])
+    bsz = np.array([s.batch_size for s in stats])
+    value = pins / el
+    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
+    log(f"makespan {el:.3f} s  {value / 1e6:.1f} Mpins/s  latency p50 {p50:.2f} ms p99 {p99:.2f} ms "
+        f"mean batch {bsz.mean():.2f} max {bsz.max()}")
+    line = {"metric": METRIC, "value": value, "unit": "pins/s", "n_gpus": 1, "steps": R,
+            "warmup": args.warmup, "ms_per_step": el * 1000.0 / R, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": SERVE_DESC, "requests": R, "pins": pins, "rate_per_s": args.rate,
+                       "parallelism": "1 GPU", "budget_gib": args.budget_gib, "max_slots": args.slots},
+            "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3), "max": round(float(lat.max()), 3)},
+            "mean_batch": round(float(bsz.mean()), 3), "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +223,10 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--requests", type=int, default=256, help="serve: requests in the stream")
+    ap.add_argument("--rate", type=float, default=100.0, help="serve: mean arrivals per second")
+    ap.add_argument("--budget-gib", type=int, default=128, help="serve: admission budget")
+    ap.add_argument("--slots", type=int, default=256, help="serve: most requests per run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -83,6 +238,10 @@ def main():
     import paper_2012_13618_amd as bp
 
     torch.cuda.set_device(0)
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     h, desc = make_workload(args.workload)
     k, eps = h.meta["k"], h.meta["eps"]
     log(f"workload {args.workload}: N={h.num_nodes} E={h.num_hedges} P={h.num_pins} k={k} eps={eps}")
@@ -105,29 +264,7 @@ def main():
 
     roofline = None
     if not args.no_profile:
-        # one more step with per-launch hipEvent timing on the launching stream
-        bp.profile_reset()
-        bp.profile_enable(True)
-        bp.partition_device(dh, k, eps, part_out=part)
-        torch.cuda.synchronize()
-        bp.profile_enable(False)
-        stats = sorted(bp.profile_read(), key=lambda s: -s["total_ms"])
-        tot = sum(s["total_ms"] for s in stats)
-        log(f"kernel time (profiled step): {tot:.3f} ms over "
-            f"{sum(s['launches'] for s in stats)} launches")
-        for s in stats[:25]:
-            gbs = s["bytes"] / (s["total_ms"] * 1e6) if s["total_ms"] > 0 else 0
-            log(f"  {s['name']:<16} {s['launches']:6d} launches {s['total_ms']:8.3f} ms "
-                f"avg {1000 * s['total_ms'] / s['launches']:8.2f} us  {gbs:8.1f} GB/s")
-        dom = next((s for s in stats if s["bytes"] > 0), None)
-        if dom:
-            achieved = dom["bytes"] / (dom["total_ms"] * 1e6)
-            roofline = {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                        "avg_launch_us": round(1000 * dom["total_ms"] / dom["launches"], 3),
-                        "launches_per_step": dom["launches"],
-                        "share_of_kernel_time": round(dom["total_ms"] / tot, 4)}
+        roofline = profiled_step(lambda: bp.partition_device(dh, k, eps, part_out=part))
 
     cpu = None
     if not args.no_cpu_baseline:

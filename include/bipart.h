@@ -109,6 +109,7 @@ typedef struct {
     int64_t pins_refined;      /* sum of pins over every gain evaluation      */
     int32_t host_syncs;        /* device-to-host waits the call needed        */
     int32_t kernel_launches;   /* kernels launched by the call                */
+    int64_t device_bytes;      /* device memory the call held at its end      */
 } bp_report;
 
 /* Fills *p with the defaults listed above. */
@@ -181,6 +182,72 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
                                     const double *eps, const bp_params *params,
                                     int32_t *const *d_part_out, int64_t *cut_out, bp_report *reports,
                                     void *stream);
+
+/* ---- served form ----------------------------------------------------------
+ *
+ * A server owns a worker thread on one device.  Requests are submitted one
+ * at a time from any thread; the worker drains the queue in runs, each run
+ * partitioning every request it admitted as one batch (see
+ * bp_partition_batch).  Admission: a run takes queued requests in arrival
+ * order while the sum of their footprint estimates (bp_request_footprint)
+ * stays within hbm_budget_bytes and at most max_slots requests; requests
+ * that arrive during a run join the next one.  A request whose own estimate
+ * exceeds the budget is refused at submission with BP_ERR_REJECTED.  Every
+ * result equals bp_partition of that request alone.
+ */
+typedef struct bp_server bp_server;
+
+typedef struct {
+    int64_t hbm_budget_bytes;   /* > 0: device bytes the requests of one run may need together */
+    int32_t max_slots;          /* >= 1: most requests per run                                  */
+    int32_t max_batch_delay_us; /* >= 0: after the oldest queued request arrived, wait up to this
+                                   long for more before starting a run (0: start at once)      */
+    int32_t device;             /* HIP device id the worker uses                                */
+    int32_t reserved;           /* set to 0                                                     */
+    bp_params params;           /* partitioner parameters for every request                    */
+} bp_server_config;
+
+typedef struct {
+    int64_t cut, max_part_weight, part_weight_limit; /* as in bp_report               */
+    int32_t balanced;
+    int32_t batch_size;         /* requests in the run that served this one          */
+    int64_t footprint_bytes;    /* the admission estimate                            */
+    double queue_ms;            /* submission to the start of its run                */
+    double run_ms;              /* start of its run to results on the host           */
+    double latency_ms;          /* submission to results on the host                 */
+} bp_req_stats;
+
+/* Defaults: 64 GiB budget, 256 slots, no batching delay, device 0, default params. */
+void bp_server_default_config(bp_server_config *cfg);
+
+/* Footprint estimate (device bytes) of one partition of a hypergraph with
+ * the given sizes and k; an upper bound of the memory the call holds. */
+bp_status bp_request_footprint(int32_t num_nodes, int32_t num_hedges, int64_t num_pins, int32_t k,
+                               int64_t *bytes);
+
+/* Starts a server (its worker sets up the device lazily; a device failure
+ * is reported by every request as BP_ERR_DEVICE).  *out receives the handle. */
+bp_status bp_server_create(const bp_server_config *cfg, bp_server **out);
+
+/* Validates and copies a host hypergraph (as bp_partition) and queues it.
+ * Returns at once with *ticket; BP_ERR_REJECTED if its footprint estimate is
+ * above the budget; BP_ERR_SHUTDOWN once destroy has begun.  Thread-safe. */
+bp_status bp_server_submit(bp_server *srv, const bp_hypergraph *hg, int32_t k, double eps, uint64_t *ticket);
+
+/* Blocks until the request is done, then copies its part ids to part_out
+ * (host int32[num_nodes], nullable), its cut to *cut_out (nullable) and its
+ * timings to *stats (nullable).  Returns the request's status: BP_OK or
+ * BP_WARN_IMBALANCED, BP_ERR_SHUTDOWN if the server was destroyed before it
+ * ran, BP_ERR_DEVICE on a device failure, BP_ERR_NOT_FOUND for a ticket
+ * never issued or already collected.  Each ticket is collected once.
+ * Thread-safe; must not be called after bp_server_destroy has returned. */
+bp_status bp_server_wait(bp_server *srv, uint64_t ticket, int32_t *part_out, int64_t *cut_out,
+                         bp_req_stats *stats);
+
+/* Stops the server: the run in progress completes, requests still queued
+ * complete with BP_ERR_SHUTDOWN, threads blocked in bp_server_wait return,
+ * then every resource is freed. */
+bp_status bp_server_destroy(bp_server *srv);
 
 /*
  * Connectivity-1 cut and heaviest part of a given partition (problem

@@ -29,7 +29,8 @@ EXPORTS = [
     "bp_partition_device", "bp_compute_cut", "bp_compute_cut_device", "bp_step_match",
     "bp_step_coarsen", "bp_step_gains", "bp_step_initial", "bp_step_refine", "bp_step_bisect",
     "bp_profile_enable", "bp_profile_reset", "bp_profile_read", "bp_partition_batch",
-    "bp_partition_batch_device",
+    "bp_partition_batch_device", "bp_server_default_config", "bp_request_footprint",
+    "bp_server_create", "bp_server_submit", "bp_server_wait", "bp_server_destroy",
 ]
 
 
@@ -56,7 +57,24 @@ class Report(ctypes.Structure):
                 ("tree_levels", ctypes.c_int32), ("bisections", ctypes.c_int32),
                 ("coarsen_levels", ctypes.c_int32), ("pins_coarsened", ctypes.c_int64),
                 ("pins_refined", ctypes.c_int64), ("host_syncs", ctypes.c_int32),
-                ("kernel_launches", ctypes.c_int32)]
+                ("kernel_launches", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
+                ("max_batch_delay_us", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("params", Params)]
+
+
+class ReqStats(ctypes.Structure):
+    _fields_ = [("cut", ctypes.c_int64), ("max_part_weight", ctypes.c_int64),
+                ("part_weight_limit", ctypes.c_int64), ("balanced", ctypes.c_int32),
+                ("batch_size", ctypes.c_int32), ("footprint_bytes", ctypes.c_int64),
+                ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
+                ("latency_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -97,6 +115,13 @@ def lib():
         L.bp_step_bisect.argtypes = [P, i32, i32, u64, P, P, P, P]
         L.bp_partition_batch.argtypes = [i32, P, P, P, P, P, P, P]
         L.bp_partition_batch_device.argtypes = [i32, P, P, P, P, P, P, P, P]
+        L.bp_server_default_config.argtypes = [P]
+        L.bp_server_default_config.restype = None
+        L.bp_request_footprint.argtypes = [i32, i32, i64, i32, P]
+        L.bp_server_create.argtypes = [P, P]
+        L.bp_server_submit.argtypes = [P, P, i32, f64, P]
+        L.bp_server_wait.argtypes = [P, u64, P, P, P]
+        L.bp_server_destroy.argtypes = [P]
         L.bp_profile_enable.argtypes = [i32]
         L.bp_profile_enable.restype = None
         L.bp_profile_reset.argtypes = []
@@ -182,6 +207,67 @@ def partition_batch(graphs, ks, epss, prm: Params | None = None):
                                          cuts.ctypes.data, reps))
     return ([p[:h.num_nodes] for p, h in zip(parts, graphs)], [int(c) for c in cuts[:n]], st,
             [reps[i] for i in range(n)])
+
+
+def request_footprint(num_nodes, num_hedges, num_pins, k):
+    """Device bytes the library budgets for one partition of these sizes."""
+    b = ctypes.c_int64(0)
+    _check(lib().bp_request_footprint(num_nodes, num_hedges, num_pins, k, ctypes.byref(b)))
+    return int(b.value)
+
+
+class Server:
+    """The served form: submit host hypergraphs, wait for their partitions."""
+
+    def __init__(self, hbm_budget_bytes=None, max_slots=None, max_batch_delay_us=None, device=0,
+                 prm: Params | None = None):
+        cfg = ServerConfig()
+        lib().bp_server_default_config(ctypes.byref(cfg))
+        if hbm_budget_bytes is not None:
+            cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        if max_slots is not None:
+            cfg.max_slots = int(max_slots)
+        if max_batch_delay_us is not None:
+            cfg.max_batch_delay_us = int(max_batch_delay_us)
+        cfg.device = int(device)
+        if prm is not None:
+            cfg.params = prm
+        h = ctypes.c_void_p()
+        _check(lib().bp_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._nodes = {}
+
+    def submit(self, h, k=None, eps=None):
+        """Queues a copy of h; returns its ticket."""
+        k = h.meta.get("k", 2) if k is None else k
+        eps = h.meta.get("eps", 0.05) if eps is None else eps
+        keep = []
+        hg = _host_hg(h.num_nodes, h.offsets, h.pins, h.node_w, h.hedge_w, keep)
+        t = ctypes.c_uint64(0)
+        _check(lib().bp_server_submit(self._h, ctypes.byref(hg), k, eps, ctypes.byref(t)))
+        self._nodes[t.value] = h.num_nodes
+        return t.value
+
+    def wait(self, ticket):
+        """Blocks until the request is done: returns (part, cut, status, stats)."""
+        n = self._nodes.pop(ticket, 0)
+        part = np.empty(max(n, 1), np.int32)
+        cut = ctypes.c_int64(0)
+        st = ReqStats()
+        status = _check(lib().bp_server_wait(self._h, ctypes.c_uint64(ticket), part.ctypes.data,
+                                             ctypes.byref(cut), ctypes.byref(st)))
+        return part[:n], int(cut.value), status, st
+
+    def close(self):
+        if self._h:
+            _check(lib().bp_server_destroy(self._h))
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def compute_cut(n, off, pins, part, k, nw=None, hw=None):

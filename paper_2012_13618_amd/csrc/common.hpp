@@ -209,6 +209,13 @@ class Arena {
         blocks_.clear();
         cur_ = 0;
     }
+    // bytes handed out since the last reset (what the current call holds)
+    size_t used() const
+    {
+        size_t s = 0;
+        for (auto &b : blocks_) s += b.used;
+        return s;
+    }
     size_t reserved() const
     {
         size_t s = 0;

@@ -799,6 +799,7 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         rep->pins_refined = cx.pins_refined;
         rep->host_syncs = lc.syncs;
         rep->kernel_launches = lc.launches;
+        rep->device_bytes = (int64_t)cx.ar->used();
     }
     return balanced ? BP_OK : BP_WARN_IMBALANCED;
 }
@@ -1206,6 +1207,8 @@ static bp_status check_device_hg(const bp_hypergraph *hg)
     return BP_OK;
 }
 
+#include "server.hpp"
+
 extern "C" {
 
 void bp_default_params(bp_params *p)
@@ -1290,6 +1293,7 @@ static void fill_batch_reports(const Ctx &cx, const std::vector<BatchOut> &res, 
         r.pins_refined = cx.pins_refined;
         r.host_syncs = cx.lc.syncs;
         r.kernel_launches = cx.lc.launches;
+        r.device_bytes = (int64_t)cx.ar->used();
     }
 }
 
