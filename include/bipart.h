@@ -325,6 +325,10 @@ void bp_profile_enable(int32_t on);
 void bp_profile_reset(void);
 /* Copies up to cap entries into out (host) and returns how many exist. */
 int32_t bp_profile_read(bp_kernel_stat *out, int32_t cap);
+/* Launches n empty kernels on stream, timed like every other launch under
+ * the family "event_floor": the per-launch cost of the event timing itself,
+ * to be set against the timings of short kernels. */
+bp_status bp_profile_floor(int32_t n, void *stream);
 
 #ifdef __cplusplus
 }

@@ -31,6 +31,7 @@ EXPORTS = [
     "bp_profile_enable", "bp_profile_reset", "bp_profile_read", "bp_partition_batch",
     "bp_partition_batch_device", "bp_server_default_config", "bp_request_footprint",
     "bp_server_create", "bp_server_submit", "bp_server_wait", "bp_server_destroy",
+    "bp_profile_floor",
 ]
 
 
@@ -127,6 +128,7 @@ def lib():
         L.bp_profile_reset.argtypes = []
         L.bp_profile_reset.restype = None
         L.bp_profile_read.argtypes = [P, i32]
+        L.bp_profile_floor.argtypes = [i32, P]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is ctypes.c_int:
@@ -426,6 +428,11 @@ def profile_enable(on=True):
 
 def profile_reset():
     lib().bp_profile_reset()
+
+
+def profile_floor(n=200):
+    """Times n empty launches under the family "event_floor"."""
+    _check(lib().bp_profile_floor(n, _stream()))
 
 
 def profile_read():

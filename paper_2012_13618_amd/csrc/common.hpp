@@ -79,7 +79,10 @@ struct LaunchCtx {
         const char *name;
         double bytes;
         hipEvent_t a, b;
+        int64_t serial;
     };
+    int64_t serial = 0;  // launches recorded so far (profiling)
+    int hold = 0;        // > 0: keep timings pending (a chunk of rounds is open)
     std::vector<Pending> pending;
     std::vector<hipEvent_t> pool;
 
@@ -115,11 +118,18 @@ struct LaunchCtx {
         }
         for (auto e : pool) (void)hipEventDestroy(e);
     }
-    void sync()
+    void sync(bool flush_timings = true)
     {
         syncs++;
         BP_HIP(hipStreamSynchronize(stream));
-        if (prof) flush();
+        if (prof && flush_timings) flush();
+    }
+    // Launches with serial in [lo, hi) turned out to have no work (a round
+    // that found nothing to do): they keep their time but count no bytes.
+    void no_bytes(int64_t lo, int64_t hi)
+    {
+        for (auto &p : pending)
+            if (p.serial >= lo && p.serial < hi) p.bytes = 0.0;
     }
 };
 
@@ -139,8 +149,8 @@ inline void launch3(LaunchCtx &lc, const char *name, double bytes, K kernel, dim
     lc.launches++;
     if (lc.prof) {
         BP_HIP(hipEventRecord(b, lc.stream));
-        lc.pending.push_back({name, bytes, a, b});
-        if (lc.pending.size() > 4096) lc.flush();
+        lc.pending.push_back({name, bytes, a, b, lc.serial++});
+        if (lc.pending.size() > 4096 && !lc.hold) lc.flush();
     }
 }
 
@@ -161,8 +171,8 @@ inline void launch(LaunchCtx &lc, const char *name, double bytes, K kernel, int6
     lc.launches++;
     if (lc.prof) {
         BP_HIP(hipEventRecord(b, lc.stream));
-        lc.pending.push_back({name, bytes, a, b});
-        if (lc.pending.size() > 4096) lc.flush();
+        lc.pending.push_back({name, bytes, a, b, lc.serial++});
+        if (lc.pending.size() > 4096 && !lc.hold) lc.flush();
     }
 }
 

@@ -357,12 +357,14 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
     int idb = id_bits(L);
     int passes = 3 + (idb + kDigit - 1) / kDigit;
     int32_t nl = 2 * L.S;
-    bool fused = nl <= kFusedPickLists;
+    // picks: by the last workgroup (few lists), by the last workgroup of each
+    // segment (many lists), or by a launch of their own (no nodes at all)
+    int fused = nl <= kFusedPickLists ? 1 : (L.N > 0 ? 2 : 0);
     SelView sv = sel_view(L, sg, gain);
     int64_t grid = std::max<int64_t>(1, ceil_div(L.N, kSelNodes));
     for (int p = 0; p < passes; p++) {
         launch(lc, "select", 10.0 * L.N, k_select_pass, grid, kBlock, 0, L.N, p, nl, idb, sv, sg.st,
-               fused ? 1 : 0, go);
+               fused, go);
         if (!fused)
             launch(lc, "select_pick", 0.0, k_select_pick, nl, kBlock, 0, nl, p, idb, sv, sg.st, go);
     }
@@ -380,19 +382,30 @@ static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t
 template <typename Round>
 static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
 {
+    LaunchCtx &lc = cx.lc;
     int64_t issued = 0;
     int chunk = 2;
+    std::vector<int64_t> first;  // serial of each round's first launch (profiling)
+    lc.hold++;
     for (;;) {
         for (int i = 0; i < chunk; i++) {
+            first.push_back(lc.serial);
             round(issued == 0);
-            launch(cx.lc, "round", 0.0, k_round_end, 1, 1, 0, sg.go);
+            launch(lc, "round", 0.0, k_round_end, 1, 1, 0, sg.go);
             issued++;
         }
-        BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, cx.lc.stream));
-        cx.lc.sync();
+        BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
+        lc.sync(false);
         int32_t *g = (int32_t *)cx.info_h;
-        if (g[1] == 0) return g[2];
-        if (issued > limit) throw Error(BP_ERR_DEVICE, "round loop did not terminate");
+        int64_t ran = g[2];
+        bool end = g[1] == 0;
+        if (lc.prof && ran < (int64_t)first.size()) lc.no_bytes(first[ran], lc.serial);
+        if (end || issued > limit) {
+            lc.hold--;
+            if (lc.prof) lc.flush();
+            if (!end) throw Error(BP_ERR_DEVICE, "round loop did not terminate");
+            return ran;
+        }
         chunk = std::min(chunk * 2, 32);
     }
 }
@@ -491,6 +504,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     int32_t *gain = ar.get<int32_t>(lv[0].N);
     fill(lc, sg.st.hist, (int64_t)2 * sg.S * kBins, 0u);
     fill(lc, sg.st.ctl, 4, 0);
+    fill(lc, sg.st.tick, (int64_t)sg.S, 0);
     fill(lc, sg.st.rsel, (int64_t)2 * sg.S, 0);
 
     for (int32_t j = Lmax; j >= 0; j--) {
@@ -1554,6 +1568,7 @@ static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, i
     fill(cx.lc, sg.max1, 1, max1);
     fill(cx.lc, sg.st.hist, 2 * kBins, 0u);
     fill(cx.lc, sg.st.ctl, 4, 0);
+    fill(cx.lc, sg.st.tick, 1, 0);
     fill(cx.lc, sg.st.rsel, 2, 0);
     fill(cx.lc, sg.W, 1, (int64_t)0);
     launch(cx.lc, "seg_setup", 0.0, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
@@ -1649,6 +1664,16 @@ bp_status bp_step_bisect(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint64
 // ---- profiling -----------------------------------------------------------------------
 
 void bp_profile_enable(int32_t on) { Profiler::get().on = on != 0; }
+
+bp_status bp_profile_floor(int32_t n, void *stream)
+{
+    if (n < 0) return fail(BP_ERR_INVALID_ARG, "n < 0");
+    BP_GUARD_BEGIN
+    CtxGuard g((hipStream_t)stream, nullptr);
+    for (int32_t i = 0; i < n; i++) launch(g.cx.lc, "event_floor", 0.0, k_empty, 1, 64, 0, 0);
+    return BP_OK;
+    BP_GUARD_END
+}
 
 void bp_profile_reset(void)
 {

@@ -45,6 +45,8 @@ __global__ void k_set_segs_root(int32_t N, int32_t E, int32_t *nbase, int32_t *h
 
 __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
+__global__ void k_empty(int32_t) {}
+
 // Segment weights W[s] (block-aggregated).
 __global__ __launch_bounds__(kBlock) void k_seg_total(int32_t N, const int32_t *nseg,
                                                       const int32_t *nw, unsigned long long *W)
@@ -234,6 +236,7 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     st.lthr = ar.get<uint32_t>(2 * S);
     st.done = ar.get<uint8_t>(2 * S);
     st.ctl = ar.get<int32_t>(4);
+    st.tick = ar.get<int32_t>(S);
     g.go = ar.get<int32_t>(4);
     g.ccount = ar.get<int32_t>(S);
     return g;

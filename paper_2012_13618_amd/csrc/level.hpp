@@ -63,6 +63,7 @@ struct SelState {
     uint32_t *upre, *uthr, *lpre, *lthr;
     uint8_t *done;
     int32_t *ctl;     // [4]: [0] lists still open, [1] ticket
+    int32_t *tick;    // [S] per-segment tickets of the fused picks
 };
 
 // Per-segment bisection state (device arrays; 2S entries where per side).

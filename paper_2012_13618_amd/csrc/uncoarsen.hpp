@@ -367,8 +367,75 @@ __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, 
     __syncthreads();
 }
 
+// A list of a segment without nodes chooses nothing.
+__device__ __forceinline__ void empty_segment_done(const SelState &st, int32_t s)
+{
+    for (int sd = 0; sd < 2; sd++) {
+        int32_t c = 2 * s + sd;
+        st.rsel[c] = 0;
+        st.rem[c] = 0;
+        st.done[c] = 1;
+        atomicSub(&st.ctl[0], 1);
+    }
+}
+
+// Per-segment tickets: every workgroup whose node range meets segment s
+// counts itself in tick[s] after its histogram is flushed; the last one does
+// the picks of the segment's two lists.  Segments without nodes are settled
+// in pass 0 by the workgroup holding their position.
+__device__ void seg_tickets_pick(int32_t N, int p, int32_t nlists, int idbits, const SelView &sv,
+                                 const SelState &st, int64_t v0, int64_t *lds)
+{
+    __shared__ int32_t picks[kBlock];
+    __shared__ int npick;
+    int64_t v1 = v0 + kSelNodes < N ? v0 + kSelNodes : N;
+    int32_t S = nlists / 2;
+    if (p == 0) {
+        for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+            int32_t lo = v == 0 ? -1 : sv.nseg[v - 1], hi = sv.nseg[v];
+            for (int32_t s = lo + 1; s < hi; s++) empty_segment_done(st, s);
+        }
+        if (v1 == N)
+            for (int32_t s = sv.nseg[N - 1] + 1 + (int32_t)threadIdx.x; s < S; s += blockDim.x)
+                empty_segment_done(st, s);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        npick = 0;
+    }
+    __syncthreads();
+    int32_t sf = sv.nseg[v0], sl = sv.nseg[v1 - 1];
+    for (int32_t base = sf; base <= sl; base += blockDim.x) {
+        int32_t s = base + (int32_t)threadIdx.x;
+        if (s <= sl) {
+            int32_t a = sv.nbase[s], b = sv.nbase[s + 1];
+            if (b > a) {
+                int32_t nb = (b - 1) / kSelNodes - a / kSelNodes + 1;
+                if (atomicAdd(&st.tick[s], 1) == nb - 1) {
+                    st.tick[s] = 0;
+                    picks[atomicAdd(&npick, 1)] = s;
+                }
+            }
+        }
+        __syncthreads();
+        int np = npick;
+        if (np > 0) {
+            if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            __syncthreads();
+            for (int i = 0; i < np; i++) {
+                sel_pick_list(st, 2 * picks[i], p, idbits, sv.mode, sv.m, lds);
+                sel_pick_list(st, 2 * picks[i] + 1, p, idbits, sv.mode, sv.m, lds);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) npick = 0;
+        __syncthreads();
+    }
+}
+
 // Histogram of global pass p; the last workgroup to finish does the picks
-// when there are few lists.
+// when there are few lists, the last one of each segment when there are many.
 __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_t nlists, int idbits,
                                                         SelView sv, SelState st, int fused,
                                                         const int32_t *go)
@@ -425,6 +492,10 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
         }
     }
     if (!fused) return;
+    if (fused == 2) {
+        seg_tickets_pick(N, p, nlists, idbits, sv, st, v0, lds);
+        return;
+    }
     // ticket: the last workgroup sees every histogram
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -520,6 +591,7 @@ __device__ __forceinline__ void reset_lists(SelState st, int32_t s)
         st.gmin[c] = INT32_MAX;
         st.done[c] = 0;
     }
+    st.tick[s] = 0;
 }
 
 // Algorithm 3 loop test per segment: P0 below its share and P1 non-empty.
