@@ -20,6 +20,10 @@ static void check_lists(const Level &L)
         throw Error(BP_ERR_DEVICE, "internal: node schedule lists missing");
 }
 
+// Levels with at least this many pins update balance-round gains from the
+// moves instead of recomputing them.
+constexpr int32_t kIncrementalMinPins = 1 << 18;
+
 // ---- one coarsening step ------------------------------------------------------
 
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
@@ -275,8 +279,11 @@ void build_incidence(Ctx &cx, Level &L)
     L.chunk_big = ar.get<int32_t>(L.nchunk_bound);
     L.big_chunks = ar.get<int32_t>(L.nbig_bound);
     L.big_done = ar.get<int32_t>(L.nbig_bound);
+    L.bigslot = ar.get<int32_t>(N);
+    fill(lc, L.bigslot, N, -1);
     launch(lc, "incidence", 0.0, k_big_chunks, 1, kBlock, 0, (const int32_t *)L.lnbig,
-           (const int32_t *)L.noff, L.ncount, L.chunk_node, L.chunk_beg, L.chunk_big, L.big_chunks);
+           (const int32_t *)L.noff, L.ncount, L.chunk_node, L.chunk_beg, L.chunk_big, L.big_chunks,
+           L.bigslot);
     L.cc = ar.get<int2>(E);
 }
 
@@ -379,6 +386,16 @@ static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t
 // Rounds issued in chunks with one readback per chunk: the round kernels keep
 // a device counter of segments still running and every later kernel of a
 // finished round returns at once.
+static bool trace_on()
+{
+    static int on = -1;
+    if (on < 0) {
+        const char *e = getenv("BP_TRACE");
+        on = (e && *e && *e != '0') ? 1 : 0;
+    }
+    return on == 1;
+}
+
 template <typename Round>
 static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
 {
@@ -440,33 +457,71 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     if (cx.prm.refine_iters == 0)
         launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
                sg.mode, sg.gmask, sg.done, sg.st, sg.go);
-    // balance step
+    // balance step: the first round computes every gain; later rounds update
+    // the gains from the hyperedges of the nodes the previous round moved
     fill(lc, sg.go, 4, 0);
     int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
-    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, [&](bool) {
+    Arena &ar = *cx.ar;
+    // incremental gains pay off once a full recomputation is long against
+    // the three short launches they take
+    bool incr = L.P >= kIncrementalMinPins;
+    MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
+    uint32_t *bits = nullptr;
+    int32_t *lsmall = nullptr, *lbig = nullptr;
+    int64_t nbits = ceil_div(L.E, 32);
+    if (incr) {
+        int64_t chunks = (int64_t)L.P / kLogChunk + L.N + 1;
+        ml.moved = ar.get<uint8_t>(L.N);
+        ml.cnode = ar.get<int32_t>(chunks);
+        ml.cbeg = ar.get<int32_t>(chunks);
+        ml.count = ar.get<int32_t>(4);
+        bits = ar.get<uint32_t>(nbits);
+        lsmall = ar.get<int32_t>(L.E);
+        lbig = ar.get<int32_t>(L.E);
+        fill(lc, ml.moved, L.N, (uint8_t)0);
+        fill(lc, bits, nbits, 0u);
+        fill(lc, ml.count, 4, 0);
+    }
+    int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
+    int32_t gsmall = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.E, kBlock), 1024));
+    int64_t gbig = std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.E, kBlock / 64), 1024));
+    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, [&](bool first) {
         launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
                (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
                sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go);
-        run_gains(cx, L, sg, gain, true, sg.go);
+        if (first || !incr) {
+            run_gains(cx, L, sg, gain, true, sg.go);
+        } else {
+            launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
+                   (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
+                   (const int32_t *)L.inc, (const int32_t *)L.off, bits, lsmall, lbig, ml.count,
+                   (const int32_t *)sg.go);
+            launch(lc, "gain_update", 0.0, k_gain_update, gsmall + gbig, kBlock, 0, (const int32_t *)ml.count,
+                   (const int32_t *)lsmall, (const int32_t *)lbig, gsmall, (const int32_t *)L.off,
+                   (const int32_t *)L.pins, (const int32_t *)L.hw, (const uint8_t *)L.side,
+                   (const uint8_t *)ml.moved, L.cc, gain, bits, (const int32_t *)L.bigslot,
+                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)sg.go);
+            if (trace_on() && lc.prof) {
+                int32_t c[4];
+                BP_HIP(hipMemcpyAsync(c, ml.count, sizeof(c), hipMemcpyDeviceToHost, lc.stream));
+                lc.sync(false);
+                fprintf(stderr, "[bp]   N=%d P=%d moved=%d small=%d big=%d\n", L.N, L.P, c[0], c[1], c[2]);
+            }
+            launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+                   (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
+                   (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
+                   ml.moved, ml.count, (const int32_t *)sg.go);
+        }
         run_select(cx, L, sg, gain, sg.go);
         launch(lc, "balance", 10.0 * L.N, k_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
                sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, (const int32_t *)sg.go);
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
                (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
                (const int32_t *)L.nw, (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
-               (unsigned long long *)sg.w, sg.done, sg.stuck);
+               (unsigned long long *)sg.w, sg.done, sg.stuck, ml);
     });
 }
 
-static bool trace_on()
-{
-    static int on = -1;
-    if (on < 0) {
-        const char *e = getenv("BP_TRACE");
-        on = (e && *e && *e != '0') ? 1 : 0;
-    }
-    return on == 1;
-}
 
 // ---- the multilevel bisection of every segment of a level-0 CSR ---------------------
 

@@ -38,6 +38,7 @@ struct Level {
     int32_t *chunk_node = nullptr, *chunk_beg = nullptr, *chunk_big = nullptr;
     int32_t *big_chunks = nullptr, *big_done = nullptr;  // per big node
     int64_t nchunk_bound = 0;
+    int32_t *bigslot = nullptr;  // [N] index of a big node in lnbig, else -1
     int2 *cc = nullptr;         // [E] per-hyperedge gain contributions (scratch)
 };
 

@@ -58,6 +58,44 @@ __global__ __launch_bounds__(kBlock) void k_side_weights(int32_t N, const int32_
     }
 }
 
+constexpr int kLogChunk = 64;  // incidences of a moved node per logged chunk
+
+// What a balance round moved, for the next round's gain update: moved[v] is
+// set for every moved node, and its incidence range is logged in chunks of
+// 64 (node, first incidence) so that the next step is evenly parallel.
+struct MoveLog {
+    const int32_t *noff;
+    uint8_t *moved;
+    int32_t *cnode, *cbeg;
+    int32_t *count;  // [0] logged chunks, [1] listed small hyperedges, [2] listed big ones
+};
+
+// Logs the moves of the first p keys' nodes (one workgroup).
+__device__ void log_moves(int32_t p, const uint64_t *a, const MoveLog &ml, int64_t *lds64)
+{
+    __shared__ int32_t base_s;
+    for (int32_t base = 0; base < p; base += blockDim.x) {
+        int32_t i = base + threadIdx.x;
+        int32_t v = 0, b = 0, c = 0;
+        if (i < p) {
+            v = (int32_t)(uint32_t)(a[i] & 0xffffffffu);
+            b = ml.noff[v];
+            c = (int32_t)ceil_div(ml.noff[v + 1] - b, kLogChunk);
+            ml.moved[v] = 1;
+        }
+        int64_t tot;
+        int64_t ex = block_excl_scan((int64_t)c, lds64, &tot);
+        if (threadIdx.x == 0) base_s = tot ? atomicAdd(&ml.count[0], (int32_t)tot) : 0;
+        __syncthreads();
+        int32_t o = base_s + (int32_t)ex;
+        for (int32_t j = 0; j < c; j++) {
+            ml.cnode[o + j] = v;
+            ml.cbeg[o + j] = b + j * kLogChunk;
+        }
+        __syncthreads();
+    }
+}
+
 // One workgroup per balancing segment: sort its candidates, take the shortest
 // prefix covering the excess, cut back to what the other side can take, move.
 __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *mode,
@@ -66,7 +104,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
                                                      const int32_t *nw,
                                                      const int64_t *need, const int64_t *room,
                                                      uint8_t *side, unsigned long long *segw,
-                                                     uint8_t *done, int32_t *stuck)
+                                                     uint8_t *done, int32_t *stuck, MoveLog ml)
 {
     extern __shared__ uint64_t keys_lds[];
     __shared__ int64_t lds64[16];
@@ -124,6 +162,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
         moved += nw[v];
     }
     moved = block_sum(moved, lds64);
+    if (ml.cnode) log_moves(p, a, ml, lds64);
     if (threadIdx.x == 0) {
         if (p == 0) {
             stuck[s] = 1;

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kBlock) void k_classify_nodes(int32_t N, const int3
 __global__ __launch_bounds__(kBlock) void k_big_chunks(const int32_t *lnbig, const int32_t *noff,
                                                        int32_t *ncount, int32_t *chunk_node,
                                                        int32_t *chunk_beg, int32_t *chunk_big,
-                                                       int32_t *big_chunks)
+                                                       int32_t *big_chunks, int32_t *bigslot)
 {
     __shared__ int32_t lds[16];
     int32_t cb = ncount[1], q0 = 0;
@@ -146,6 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_big_chunks(const int32_t *lnbig, con
             b = noff[v];
             n = (int32_t)ceil_div(noff[v + 1] - b, kNodeChunk);
             big_chunks[i] = n;
+            bigslot[v] = i;
         }
         int32_t tot;
         int32_t q = q0 + block_excl_scan(n, lds, &tot);

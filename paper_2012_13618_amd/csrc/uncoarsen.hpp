@@ -92,6 +92,142 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
     }
 }
 
+// ---- gains after a balance round: updated from what it moved -------------------------
+
+// One wavefront per logged chunk of a moved node's incidences: each
+// hyperedge not yet listed this round (bitmap test-and-set, read first so a
+// set bit costs no atomic) goes to the small (degree <= 8) or big list.
+__global__ __launch_bounds__(kBlock) void k_log_hedges(const int32_t *count, const int32_t *cnode,
+                                                       const int32_t *cbeg, const int32_t *noff,
+                                                       const int32_t *inc, const int32_t *off,
+                                                       uint32_t *bits, int32_t *lsmall, int32_t *lbig,
+                                                       int32_t *counts, const int32_t *go)
+{
+    if (go && *go == 0) return;
+    int32_t n = count[0];
+    int lane = threadIdx.x & 63;
+    const int64_t wpb = kBlock / 64;
+    for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * wpb) {
+        int32_t v = cnode[i];
+        int32_t j = cbeg[i] + lane, end = noff[v + 1];
+        bool fresh = false;
+        int32_t e = 0;
+        if (j < end) {
+            e = inc[j];
+            uint32_t bit = 1u << (e & 31);
+            if (!(__hip_atomic_load(&bits[e >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
+                fresh = !(atomicOr(&bits[e >> 5], bit) & bit);
+        }
+        bool small = fresh && off[e + 1] - off[e] <= kSmallMax;
+        wave_append(small, e, lsmall, &counts[1]);
+        wave_append(fresh && !small, e, lbig, &counts[2]);
+    }
+}
+
+__device__ __forceinline__ int2 hedge_contrib_value(int32_t w, int32_t d, int32_t n1)
+{
+    int32_t n0 = d - n1;
+    int2 c;
+    c.x = n0 == 1 ? w : (n0 == d ? -w : 0);
+    c.y = n1 == 1 ? w : (n1 == d ? -w : 0);
+    return c;
+}
+
+constexpr int kUpdSlots = 1024;  // big nodes whose gain changes gather in LDS first
+
+// adds delta to gain[u]: in the workgroup's LDS slot when u is one of the
+// first kUpdSlots big nodes (many hyperedges, so many updates), else globally
+__device__ __forceinline__ void add_gain(int32_t u, int32_t delta, const int32_t *bigslot, int32_t *slot,
+                                        int32_t *gain)
+{
+    int32_t k = bigslot[u];
+    if (k >= 0 && k < kUpdSlots) atomicAdd(&slot[k], delta);
+    else atomicAdd(&gain[u], delta);
+}
+
+// Listed hyperedges (small ones one per thread, big ones one per wavefront):
+// recount the sides, replace the contribution, and add the change to every
+// pin's gain (a pin that moved trades its old side's contribution for its new
+// side's).  Integer sums, so the result equals a recomputation.
+__device__ __forceinline__ void update_hedges(const int32_t *counts, const int32_t *lsmall,
+                                              const int32_t *lbig, int32_t gsmall,
+                                              const int32_t *off, const int32_t *pins,
+                                              const int32_t *hw, const uint8_t *side,
+                                              const uint8_t *moved, int2 *cc, int32_t *gain,
+                                              uint32_t *bits, const int32_t *bigslot, int32_t *slot)
+{
+    if ((int32_t)blockIdx.x < gsmall) {
+        int32_t n = counts[1];
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gsmall * kBlock) {
+            int32_t e = lsmall[i];
+            int32_t b = off[e], d = off[e + 1] - b;
+            int32_t u[kSmallMax];
+            uint8_t sn[kSmallMax], so[kSmallMax];
+            int32_t n1 = 0;
+#pragma unroll
+            for (int j = 0; j < kSmallMax; j++)
+                if (j < d) {
+                    u[j] = pins[b + j];
+                    sn[j] = side[u[j]];
+                    so[j] = sn[j] ^ moved[u[j]];
+                    n1 += sn[j];
+                }
+            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+#pragma unroll
+            for (int j = 0; j < kSmallMax; j++)
+                if (j < d) {
+                    int32_t delta = (sn[j] ? nc.y : nc.x) - (so[j] ? oc.y : oc.x);
+                    if (delta) add_gain(u[j], delta, bigslot, slot, gain);
+                }
+            cc[e] = nc;
+            atomicAnd(&bits[e >> 5], ~(1u << (e & 31)));
+        }
+        return;
+    }
+    int32_t n = counts[2];
+    int lane = threadIdx.x & 63;
+    const int64_t wpb = kBlock / 64;
+    int64_t gb = (int64_t)gridDim.x - gsmall;
+    for (int64_t i = ((int64_t)blockIdx.x - gsmall) * wpb + (threadIdx.x >> 6); i < n; i += gb * wpb) {
+        int32_t e = lbig[i];
+        int32_t b = off[e], d = off[e + 1] - b;
+        int32_t n1 = 0;
+        for (int j = lane; j < d; j += 64) n1 += side[pins[b + j]];
+        n1 = wave_sum(n1);
+        int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+        for (int j = lane; j < d; j += 64) {
+            int32_t u = pins[b + j];
+            int sn = side[u], so = sn ^ moved[u];
+            int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
+            if (delta) add_gain(u, delta, bigslot, slot, gain);
+        }
+        if (lane == 0) {
+            cc[e] = nc;
+            atomicAnd(&bits[e >> 5], ~(1u << (e & 31)));
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gain_update(const int32_t *counts, const int32_t *lsmall,
+                                                        const int32_t *lbig, int32_t gsmall,
+                                                        const int32_t *off, const int32_t *pins,
+                                                        const int32_t *hw, const uint8_t *side,
+                                                        const uint8_t *moved, int2 *cc, int32_t *gain,
+                                                        uint32_t *bits, const int32_t *bigslot,
+                                                        const int32_t *lnbig, const int32_t *ncount,
+                                                        const int32_t *go)
+{
+    __shared__ int32_t slot[kUpdSlots];
+    if (go && *go == 0) return;
+    int32_t nb = min(ncount[1], kUpdSlots);
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
+    __syncthreads();
+    update_hedges(counts, lsmall, lbig, gsmall, off, pins, hw, side, moved, cc, gain, bits, bigslot, slot);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (slot[i]) atomicAdd(&gain[lnbig[i]], slot[i]);
+}
+
 // eligibility of a node for its list under the segment's selection mode
 __device__ __forceinline__ bool sel_list(int32_t s, int sd, int32_t g, const uint8_t *mode)
 {
@@ -229,6 +365,56 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
                 }
             }
         }
+    }
+}
+
+// Per-list counts and gain extremes after a gain update (what the node pass
+// records otherwise); clears the move marks and the hyperedge list.
+__global__ __launch_bounds__(kBlock) void k_gain_stats(int32_t N, const int32_t *nseg, const uint8_t *gmask,
+                                                       const uint8_t *side, const int32_t *gain,
+                                                       const uint8_t *mode, int32_t *tot, int32_t *gmax,
+                                                       int32_t *gmin, uint8_t *moved, int32_t *counts,
+                                                       const int32_t *go)
+{
+    __shared__ int32_t agg[6];
+    if (go && *go == 0) return;
+    if (blockIdx.x == 0 && threadIdx.x < 3) counts[threadIdx.x] = 0;
+    int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int64_t vf = (int64_t)blockIdx.x * kBlock, vl = vf + kBlock - 1 < N ? vf + kBlock - 1 : N - 1;
+    bool one = nseg[vf] == nseg[vl];
+    int32_t s0 = nseg[vf];
+    if (threadIdx.x < 2) {
+        agg[3 * threadIdx.x] = 0;
+        agg[3 * threadIdx.x + 1] = INT32_MIN;
+        agg[3 * threadIdx.x + 2] = INT32_MAX;
+    }
+    __syncthreads();
+    if (v < N) {
+        if (moved[v]) moved[v] = 0;
+        int32_t s = nseg[v];
+        if (gmask[s]) {
+            int sd = side[v];
+            int32_t g = gain[v];
+            if (sel_list(s, sd, g, mode)) {
+                if (one) {
+                    atomicAdd(&agg[3 * sd], 1);
+                    atomicMax(&agg[3 * sd + 1], g);
+                    atomicMin(&agg[3 * sd + 2], g);
+                } else {
+                    int32_t c = 2 * s + sd;
+                    atomicAdd(&tot[c], 1);
+                    atomicMax(&gmax[c], g);
+                    atomicMin(&gmin[c], g);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (one && threadIdx.x < 2 && agg[3 * threadIdx.x] > 0) {
+        int32_t c = 2 * s0 + threadIdx.x;
+        atomicAdd(&tot[c], agg[3 * threadIdx.x]);
+        atomicMax(&gmax[c], agg[3 * threadIdx.x + 1]);
+        atomicMin(&gmin[c], agg[3 * threadIdx.x + 2]);
     }
 }
 
