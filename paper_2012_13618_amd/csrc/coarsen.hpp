@@ -468,15 +468,6 @@ __global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t 
     }
 }
 
-// Appends a hyperedge of degree d (0 = none) to the schedule lists; every
-// active lane of the wavefront must call it.
-__device__ __forceinline__ void classify_append(int32_t id, int32_t d, int32_t *lmid,
-                                                int32_t *lbig, int32_t *lhuge, int32_t *counters)
-{
-    wave_append(d > kSmallMax && d <= kMidMax, id, lmid, &counters[1]);
-    wave_append(d > kMidMax, id, lbig, &counters[2]);
-    wave_append(d > kBigMax, id, lhuge, &counters[3]);
-}
 
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_copy_pins(int32_t count, const int32_t *list,

@@ -38,6 +38,25 @@ inline void hip_check(hipError_t e, const char *what)
 
 __host__ __device__ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Reductions over all nodes that end in per-segment atomics run on at most
+// this many workgroups, each over a contiguous chunk of whole tiles: a global
+// atomic on one address costs about 11 ns and serialises across workgroups.
+constexpr int64_t kReduceBlocks = 512;
+__host__ __device__ inline int64_t reduce_grid(int64_t n)
+{
+    int64_t g = ceil_div(n, 256);
+    return g < kReduceBlocks ? g : kReduceBlocks;
+}
+// lists (two per segment) a chunk aggregates in LDS before its atomics
+constexpr int kAggLists = 64;
+// [lo, hi): chunk of workgroup b of g over n items, in tiles of 256
+__host__ __device__ inline void reduce_chunk(int64_t n, int64_t g, int64_t b, int64_t &lo, int64_t &hi)
+{
+    int64_t per = ceil_div(ceil_div(n, 256), g) * 256;
+    lo = b * per < n ? b * per : n;
+    hi = lo + per < n ? lo + per : n;
+}
+
 // ---- per-kernel timing (bp_profile_*) ---------------------------------------
 
 struct Profiler {
@@ -385,6 +404,19 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds /* >= 16 */, T *total)
 // Appends id to list for every active lane with take set, using one atomic
 // per wavefront.  Call from all active lanes (the ballot spans them).
 __device__ __forceinline__ void wave_append(bool take, int32_t id, int32_t *list, int32_t *counter)
+{
+    unsigned long long m = __ballot(take);
+    if (!m) return;
+    int lane = threadIdx.x & 63;
+    int leader = __ffsll((long long)m) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(m));
+    base = __shfl(base, leader, 64);
+    if (take) list[base + __popcll(m & ((1ull << lane) - 1))] = id;
+}
+
+// wave_append into a workgroup-local list (LDS counter).
+__device__ __forceinline__ void lds_append(bool take, int32_t id, int32_t *list, int32_t *counter)
 {
     unsigned long long m = __ballot(take);
     if (!m) return;

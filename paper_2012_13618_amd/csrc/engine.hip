@@ -152,7 +152,6 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
         const int32_t *rep = b.rep, *qlen = b.qlen, *hseg = f.hseg, *hbase = f.hbase,
                       *wsum = b.wsum;
         int32_t *coff = c.off, *chw = c.hw, *chseg = c.hseg, *hdst = b.hdst, *hbt = b.hb_tmp;
-        int32_t *lmid = c.lmid, *lbig = c.lbig, *lhuge = c.lhuge, *ctr = b.counters;
         scan<uint64_t>(
             lc, ar, "hedge_ids", E,
             [=] __device__(int64_t e) -> uint64_t {
@@ -168,9 +167,10 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
                     chseg[id] = s;
                     hdst[e] = (int32_t)ex;
                 }
-                classify_append(id, val ? qlen[e] : 0, lmid, lbig, lhuge, ctr);
             },
             b.totEP);
+        launch(lc, "classify", 4.0 * E, k_classify, ceil_div(E, kClsItems), kBlock, 0, E, (const int32_t *)c.off,
+               (const uint64_t *)b.totEP, c.lmid, c.lbig, c.lhuge, b.counters);
         launch(lc, "copy_pins_small", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
                (const int32_t *)nullptr, (const int32_t *)f.off, rep, qlen,
                (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
@@ -271,7 +271,7 @@ void build_incidence(Ctx &cx, Level &L)
     L.lnbig = ar.get<int32_t>(L.nbig_bound);
     L.ncount = ar.get<int32_t>(4);
     fill(lc, L.ncount, 4, 0);
-    launch(lc, "incidence", 8.0 * N, k_classify_nodes, ceil_div(N, kBlock), kBlock, 0, N,
+    launch(lc, "incidence", 8.0 * N, k_classify_nodes, ceil_div(N, kClsNodes), kBlock, 0, N,
            (const int32_t *)L.noff, L.lnmid, L.lnbig, L.ncount);
     L.nchunk_bound = (int64_t)P / kNodeChunk + L.nbig_bound + 1;
     L.chunk_node = ar.get<int32_t>(L.nchunk_bound);
@@ -325,7 +325,8 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
            (const uint8_t *)L.side, L.cc, go, (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gain,
            L.big_done);
-    int64_t nv = ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64) + L.nchunk_bound;
+    int32_t nw = (int32_t)std::min<int64_t>(ceil_div(L.nmid_bound, kBlock / 64), kReduceBlocks);
+    int64_t nv = reduce_grid(L.N) + nw + L.nchunk_bound;
     double nb = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 1.0 * L.N + 4.0 * L.N;
     launch(lc, "gain_nodes", nb, k_gain_nodes, nv, kBlock, 0, L.N, (const int32_t *)L.lnmid,
            (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)L.noff,
@@ -333,7 +334,7 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int
            (const uint8_t *)L.side, (const int2 *)L.cc, gain, (const uint8_t *)sg.mode,
            stats ? sg.st.tot : nullptr, sg.st.gmax, sg.st.gmin, go, (const int32_t *)L.chunk_node,
            (const int32_t *)L.chunk_beg, (const int32_t *)L.chunk_big, (const int32_t *)L.big_chunks,
-           L.big_done);
+           L.big_done, L.S, nw);
 }
 
 static int id_bits(const Level &L)
@@ -379,7 +380,7 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
 
 static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
-    launch(cx.lc, "flip", 6.0 * L.N, k_flip, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+    launch(cx.lc, "flip", 6.0 * L.N, k_flip, reduce_grid(L.N), kBlock, 0, L.N,
            sel_view(L, sg, gain), sg.st, L.side, (const int32_t *)L.nw, (unsigned long long *)sg.w, go);
 }
 
@@ -396,12 +397,15 @@ static bool trace_on()
     return on == 1;
 }
 
+// With estimate (balance rounds), go[3] holds the rounds the segments still
+// need as estimated by the last round: the next chunk is that long, and an
+// estimate of zero ends the loop.
 template <typename Round>
-static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
+static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, Round round)
 {
     LaunchCtx &lc = cx.lc;
     int64_t issued = 0;
-    int chunk = 2;
+    int chunk = estimate ? 1 : 2;
     std::vector<int64_t> first;  // serial of each round's first launch (profiling)
     lc.hold++;
     for (;;) {
@@ -415,7 +419,7 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
         lc.sync(false);
         int32_t *g = (int32_t *)cx.info_h;
         int64_t ran = g[2];
-        bool end = g[1] == 0;
+        bool end = g[1] == 0 || (estimate && g[3] == 0);
         if (lc.prof && ran < (int64_t)first.size()) lc.no_bytes(first[ran], lc.serial);
         if (end || issued > limit) {
             lc.hold--;
@@ -423,7 +427,8 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, Round round)
             if (!end) throw Error(BP_ERR_DEVICE, "round loop did not terminate");
             return ran;
         }
-        chunk = std::min(chunk * 2, 32);
+        // the estimate decides the next chunk, growing at most twofold
+        chunk = estimate ? std::min({std::max(g[3], 1), 2 * chunk, 32}) : std::min(chunk * 2, 32);
     }
 }
 
@@ -432,7 +437,7 @@ static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *g
     LaunchCtx &lc = cx.lc;
     int64_t gs = ceil_div(L.S, kBlock);
     fill(lc, sg.go, 4, 0);
-    return chunked_rounds(cx, sg, (int64_t)L.N + 2, [&](bool first) {
+    return chunked_rounds(cx, sg, (int64_t)L.N + 2, false, [&](bool first) {
         launch(lc, "round", 0.0, k_round_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
                (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
                (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, first ? 1 : 0,
@@ -460,6 +465,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // balance step: the first round computes every gain; later rounds update
     // the gains from the hyperedges of the nodes the previous round moved
     fill(lc, sg.go, 4, 0);
+    fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
     int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
     Arena &ar = *cx.ar;
     // incremental gains pay off once a full recomputation is long against
@@ -467,7 +473,6 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     bool incr = L.P >= kIncrementalMinPins;
     MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
     uint32_t *bits = nullptr;
-    int32_t *lsmall = nullptr, *lbig = nullptr;
     int64_t nbits = ceil_div(L.E, 32);
     if (incr) {
         int64_t chunks = (int64_t)L.P / kLogChunk + L.N + 1;
@@ -476,16 +481,13 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         ml.cbeg = ar.get<int32_t>(chunks);
         ml.count = ar.get<int32_t>(4);
         bits = ar.get<uint32_t>(nbits);
-        lsmall = ar.get<int32_t>(L.E);
-        lbig = ar.get<int32_t>(L.E);
         fill(lc, ml.moved, L.N, (uint8_t)0);
         fill(lc, bits, nbits, 0u);
         fill(lc, ml.count, 4, 0);
     }
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
-    int32_t gsmall = (int32_t)std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.E, kBlock), 1024));
-    int64_t gbig = std::max<int64_t>(1, std::min<int64_t>(ceil_div(L.E, kBlock / 64), 1024));
-    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, [&](bool first) {
+    int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
+    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](bool first) {
         launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
                (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
                sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go);
@@ -494,20 +496,12 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         } else {
             launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
                    (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
-                   (const int32_t *)L.inc, (const int32_t *)L.off, bits, lsmall, lbig, ml.count,
-                   (const int32_t *)sg.go);
-            launch(lc, "gain_update", 0.0, k_gain_update, gsmall + gbig, kBlock, 0, (const int32_t *)ml.count,
-                   (const int32_t *)lsmall, (const int32_t *)lbig, gsmall, (const int32_t *)L.off,
-                   (const int32_t *)L.pins, (const int32_t *)L.hw, (const uint8_t *)L.side,
-                   (const uint8_t *)ml.moved, L.cc, gain, bits, (const int32_t *)L.bigslot,
+                   (const int32_t *)L.inc, bits, (const int32_t *)sg.go);
+            launch(lc, "gain_update", 4.0 * nbits, k_gain_update, ugrid, kBlock, 0, nbits, bits,
+                   (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
+                   (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
                    (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)sg.go);
-            if (trace_on() && lc.prof) {
-                int32_t c[4];
-                BP_HIP(hipMemcpyAsync(c, ml.count, sizeof(c), hipMemcpyDeviceToHost, lc.stream));
-                lc.sync(false);
-                fprintf(stderr, "[bp]   N=%d P=%d moved=%d small=%d big=%d\n", L.N, L.P, c[0], c[1], c[2]);
-            }
-            launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+            launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
                    ml.moved, ml.count, (const int32_t *)sg.go);
@@ -518,7 +512,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
                (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
                (const int32_t *)L.nw, (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
-               (unsigned long long *)sg.w, sg.done, sg.stuck, ml);
+               (unsigned long long *)sg.w, sg.done, sg.stuck, ml, sg.go, sg.bal_moved);
     });
 }
 
@@ -570,7 +564,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
                (const int32_t *)(j < Lmax ? L.parent : nullptr),
                (const uint8_t *)(j < Lmax ? lv[j + 1].side : nullptr), L.side);
         fill(lc, sg.w, (int64_t)2 * sg.S, (int64_t)0);
-        launch(lc, "side_weights", 5.0 * L.N, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+        launch(lc, "side_weights", 5.0 * L.N, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
                (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
                (unsigned long long *)sg.w);
         int64_t ir = stops[j] > 0 ? initial_rounds(cx, L, sg, j, gain) : 0;
@@ -598,7 +592,7 @@ static void seg_setup(Ctx &cx, TreeLevel &t, const int32_t *k0_fixed = nullptr)
     LaunchCtx &lc = cx.lc;
     Level &L = t.L;
     fill(lc, t.sg.W, (int64_t)L.S, (int64_t)0);
-    launch(lc, "seg_setup", 8.0 * L.N, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+    launch(lc, "seg_setup", 8.0 * L.N, k_seg_total, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)t.sg.W);
     launch(lc, "seg_setup", 0.0, k_seg_setup, ceil_div(L.S, kBlock), kBlock, 0, L.S,
            (const int32_t *)t.ksub, k0_fixed, (const int64_t *)t.sg.W, (const uint64_t *)t.F,
@@ -1626,7 +1620,7 @@ static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, i
     fill(cx.lc, sg.st.tick, 1, 0);
     fill(cx.lc, sg.st.rsel, 2, 0);
     fill(cx.lc, sg.W, 1, (int64_t)0);
-    launch(cx.lc, "seg_setup", 0.0, k_seg_total, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+    launch(cx.lc, "seg_setup", 0.0, k_seg_total, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)sg.W);
     int32_t mm = (int32_t)ceil_sqrt_i64(L.N);
     sg.cand_stride = next_pow2(std::max(mm, 1));
@@ -1650,7 +1644,7 @@ bp_status bp_step_initial(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint8
            (const int32_t *)L.nseg, (const int32_t *)sg.coarsest, (const int32_t *)nullptr,
            (const uint8_t *)nullptr, L.side);
     fill(cx.lc, sg.w, 2, (int64_t)0);
-    launch(cx.lc, "side_weights", 0.0, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+    launch(cx.lc, "side_weights", 0.0, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
            (unsigned long long *)sg.w);
     initial_rounds(cx, L, sg, 0, gain);
@@ -1673,7 +1667,7 @@ bp_status bp_step_refine(const bp_hypergraph *hg, int32_t iters, int64_t max0, i
     L.side = d_side;
     int32_t *gain = cx.ar->get<int32_t>(L.N);
     fill(cx.lc, sg.w, 2, (int64_t)0);
-    launch(cx.lc, "side_weights", 0.0, k_side_weights, ceil_div(L.N, kBlock), kBlock, 0, L.N,
+    launch(cx.lc, "side_weights", 0.0, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
            (unsigned long long *)sg.w);
     refine_level(cx, L, sg, 0, gain);

@@ -47,24 +47,28 @@ __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 
 __global__ void k_empty(int32_t) {}
 
-// Segment weights W[s] (block-aggregated).
+// Segment weights W[s] (chunked; per-segment sums in LDS).
 __global__ __launch_bounds__(kBlock) void k_seg_total(int32_t N, const int32_t *nseg,
                                                       const int32_t *nw, unsigned long long *W)
 {
-    __shared__ int64_t lds[16];
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t vf = (int64_t)blockIdx.x * blockDim.x;
-    int64_t vl = vf + blockDim.x - 1 < N ? vf + blockDim.x - 1 : N - 1;
-    bool one = nseg[vf] == nseg[vl];
-    int64_t w = 0;
-    if (v < N) {
-        if (one) w = nw[v];
-        else atomicAdd(&W[nseg[v]], (unsigned long long)nw[v]);
+    __shared__ unsigned long long acc[kAggLists];
+    int64_t lo, hi;
+    reduce_chunk(N, gridDim.x, blockIdx.x, lo, hi);
+    if (lo >= hi) return;
+    int32_t s0 = nseg[lo], ns = nseg[hi - 1] + 1 - s0;
+    bool local = ns <= kAggLists;
+    for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) acc[i] = 0;
+    __syncthreads();
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        unsigned long long w = (unsigned long long)nw[v];
+        if (!w) continue;
+        if (local) atomicAdd(&acc[nseg[v] - s0], w);
+        else atomicAdd(&W[nseg[v]], w);
     }
-    if (one) {
-        w = block_sum(w, lds);
-        if (threadIdx.x == 0 && w) atomicAdd(&W[nseg[vf]], (unsigned long long)w);
-    }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x)
+            if (acc[i]) atomicAdd(&W[s0 + i], acc[i]);
 }
 
 // Bisection split, side bounds and coarsening start state of every segment.
@@ -117,8 +121,8 @@ inline void alloc_lists(Arena &ar, Level &L, int64_t bound)
 inline void classify(Ctx &cx, Level &L, int32_t *counters)
 {
     alloc_lists(*cx.ar, L, L.E);
-    launch(cx.lc, "classify", 4.0 * L.E, k_classify, ceil_div(L.E, kBlock), kBlock, 0, L.E,
-           (const int32_t *)L.off, L.lmid, L.lbig, L.lhuge, counters);
+    launch(cx.lc, "classify", 4.0 * L.E, k_classify, ceil_div(L.E, kClsItems), kBlock, 0, L.E,
+           (const int32_t *)L.off, (const uint64_t *)nullptr, L.lmid, L.lbig, L.lhuge, counters);
 }
 
 // Level 0 of the root problem: the input without hyperedges of < 2 pins.
@@ -219,6 +223,7 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     g.m = ar.get<int32_t>(S);
     g.need = ar.get<int64_t>(S);
     g.room = ar.get<int64_t>(S);
+    g.bal_moved = ar.get<int64_t>(2 * S);
     g.done = ar.get<uint8_t>(S);
     g.stuck = ar.get<int32_t>(S);
     g.root_levels = ar.get<int32_t>(1);

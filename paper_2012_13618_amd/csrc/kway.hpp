@@ -86,19 +86,45 @@ __global__ void k_copy_weights(int64_t n, const int32_t *src, int32_t *dst)
         dst[i] = src ? src[i] : 1;
 }
 
-// Schedule lists of a freshly built level.
-__global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *off, int32_t *lmid,
-                                                     int32_t *lbig, int32_t *lhuge,
+// Schedule lists of a freshly built level: each workgroup stages the
+// hyperedges of its kClsItems ids in LDS and reserves room in each list with
+// one atomic (same-address atomics from many workgroups serialise).  With
+// tot (a level just compacted) the count and the pin total come from the
+// device: E is then only a bound.  List order is arbitrary; every consumer
+// treats its items independently.
+constexpr int kClsItems = 2048;
+
+__global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *off, const uint64_t *tot,
+                                                     int32_t *lmid, int32_t *lbig, int32_t *lhuge,
                                                      int32_t *counters)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t d = e < E ? off[e + 1] - off[e] : 0;
-    wave_append(d > kSmallMax && d <= kMidMax, (int32_t)e, lmid, &counters[1]);
-    wave_append(d > kMidMax, (int32_t)e, lbig, &counters[2]);
-    wave_append(d > kBigMax, (int32_t)e, lhuge, &counters[3]);
+    __shared__ int32_t items[3][kClsItems];
+    __shared__ int32_t cnt[3], base[3];
+    int32_t P = 0;
+    if (tot) {
+        E = (int32_t)(*tot >> 32);
+        P = (int32_t)(*tot & 0xffffffffu);
+    }
+    int64_t first = (int64_t)blockIdx.x * kClsItems;
+    if (first >= E) return;
+    if (!tot) P = off[E];
+    if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int r = 0; r < kClsItems / kBlock; r++) {
+        int64_t e = first + r * kBlock + threadIdx.x;
+        int32_t d = 0;
+        if (e < E) d = (e + 1 < E ? off[e + 1] : P) - off[e];
+        lds_append(d > kSmallMax && d <= kMidMax, (int32_t)e, items[0], &cnt[0]);
+        lds_append(d > kMidMax, (int32_t)e, items[1], &cnt[1]);
+        lds_append(d > kBigMax, (int32_t)e, items[2], &cnt[2]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 3) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&counters[1 + threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt[0]; i += blockDim.x) lmid[base[0] + i] = items[0][i];
+    for (int i = threadIdx.x; i < cnt[1]; i += blockDim.x) lbig[base[1] + i] = items[1][i];
+    for (int i = threadIdx.x; i < cnt[2]; i += blockDim.x) lhuge[base[2] + i] = items[2][i];
 }
-
-// ---- Algorithm 6: children of every bisection, by cut-net splitting -------------
 
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_count_side1(int32_t count, const int32_t *list,

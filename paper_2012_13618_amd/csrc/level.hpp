@@ -82,6 +82,7 @@ struct Segs {
     uint8_t *gmask;           // segments whose gains are needed
     int32_t *m;               // ceil(sqrt(nodes)) at the current level
     int64_t *need, *room;     // balance step
+    int64_t *bal_moved;       // [2S]: weight moved and rounds run by the level's balance step
     uint8_t *done;
     int32_t *stuck;           // balance stopped over the bound (any level)
     int32_t *root_levels;     // coarsening steps

@@ -27,35 +27,30 @@ __global__ __launch_bounds__(kBlock) void k_project(int32_t N, int32_t j, const 
     else if (c == j) side[v] = 1;
 }
 
-// Side weights of every segment (block-aggregated atomics).
+// Side weights of every segment (chunked; per-segment sums in LDS).
 __global__ __launch_bounds__(kBlock) void k_side_weights(int32_t N, const int32_t *nseg,
                                                          const uint8_t *side, const int32_t *nw,
                                                          unsigned long long *segw)
 {
-    __shared__ int64_t lds[16];
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t vf = (int64_t)blockIdx.x * blockDim.x;
-    int64_t vl = vf + blockDim.x - 1 < N ? vf + blockDim.x - 1 : N - 1;
-    bool one_seg = nseg[vf] == nseg[vl];
-    int64_t w0 = 0, w1 = 0;
-    if (v < N) {
-        int64_t w = nw[v];
-        if (one_seg) {
-            if (side[v]) w1 = w;
-            else w0 = w;
-        } else {
-            atomicAdd(&segw[2 * nseg[v] + side[v]], (unsigned long long)w);
-        }
+    __shared__ unsigned long long acc[kAggLists];
+    int64_t lo, hi;
+    reduce_chunk(N, gridDim.x, blockIdx.x, lo, hi);
+    if (lo >= hi) return;
+    int32_t c0 = 2 * nseg[lo], nl = 2 * nseg[hi - 1] + 2 - c0;
+    bool local = nl <= kAggLists;
+    for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) acc[i] = 0;
+    __syncthreads();
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        int32_t c = 2 * nseg[v] + side[v];
+        unsigned long long w = (unsigned long long)nw[v];
+        if (!w) continue;
+        if (local) atomicAdd(&acc[c - c0], w);
+        else atomicAdd(&segw[c], w);
     }
-    if (one_seg) {
-        w0 = block_sum(w0, lds);
-        w1 = block_sum(w1, lds);
-        if (threadIdx.x == 0) {
-            int32_t s = nseg[vf];
-            if (w0) atomicAdd(&segw[2 * s], (unsigned long long)w0);
-            if (w1) atomicAdd(&segw[2 * s + 1], (unsigned long long)w1);
-        }
-    }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < nl; i += blockDim.x)
+            if (acc[i]) atomicAdd(&segw[c0 + i], acc[i]);
 }
 
 constexpr int kLogChunk = 64;  // incidences of a moved node per logged chunk
@@ -104,7 +99,8 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
                                                      const int32_t *nw,
                                                      const int64_t *need, const int64_t *room,
                                                      uint8_t *side, unsigned long long *segw,
-                                                     uint8_t *done, int32_t *stuck, MoveLog ml)
+                                                     uint8_t *done, int32_t *stuck, MoveLog ml,
+                                                     int32_t *go, int64_t *bal_moved)
 {
     extern __shared__ uint64_t keys_lds[];
     __shared__ int64_t lds64[16];
@@ -170,6 +166,16 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
         } else {
             atomicAdd(&segw[2 * s + h], (unsigned long long)(-moved));
             atomicAdd(&segw[2 * s + 1 - h], (unsigned long long)moved);
+            // rounds still needed if later rounds move what the level's
+            // rounds moved on average
+            int64_t mw = bal_moved[2 * s] + moved, mr = bal_moved[2 * s + 1] + 1;
+            bal_moved[2 * s] = mw;
+            bal_moved[2 * s + 1] = mr;
+            int64_t rest = nd - moved;
+            if (rest > 0) {
+                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
+                atomicMax(&go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
+            }
         }
     }
 }

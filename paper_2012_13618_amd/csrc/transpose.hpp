@@ -119,14 +119,30 @@ __global__ __launch_bounds__(kBlock) void k_node_offsets(const uint32_t *keys, i
     noff[v] = (int32_t)lo;
 }
 
+// Node buckets, staged per workgroup like the hyperedge lists.
+constexpr int kClsNodes = 2048;
+
 __global__ __launch_bounds__(kBlock) void k_classify_nodes(int32_t N, const int32_t *noff,
                                                            int32_t *lmid, int32_t *lbig,
                                                            int32_t *counters)
 {
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int32_t d = v < N ? noff[v + 1] - noff[v] : 0;
-    wave_append(d > kNodeSmallMax && d <= kNodeMidMax, (int32_t)v, lmid, &counters[0]);
-    wave_append(d > kNodeMidMax, (int32_t)v, lbig, &counters[1]);
+    __shared__ int32_t items[2][kClsNodes];
+    __shared__ int32_t cnt[2], base[2];
+    int64_t first = (int64_t)blockIdx.x * kClsNodes;
+    if (first >= N) return;
+    if (threadIdx.x < 2) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    for (int r = 0; r < kClsNodes / kBlock; r++) {
+        int64_t v = first + r * kBlock + threadIdx.x;
+        int32_t d = v < N ? noff[v + 1] - noff[v] : 0;
+        lds_append(d > kNodeSmallMax && d <= kNodeMidMax, (int32_t)v, items[0], &cnt[0]);
+        lds_append(d > kNodeMidMax, (int32_t)v, items[1], &cnt[1]);
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) base[threadIdx.x] = cnt[threadIdx.x] ? atomicAdd(&counters[threadIdx.x], cnt[threadIdx.x]) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < cnt[0]; i += blockDim.x) lmid[base[0] + i] = items[0][i];
+    for (int i = threadIdx.x; i < cnt[1]; i += blockDim.x) lbig[base[1] + i] = items[1][i];
 }
 
 // Chunk table of the big nodes: one workgroup walks them in tiles of 256 and

@@ -94,14 +94,13 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
 
 // ---- gains after a balance round: updated from what it moved -------------------------
 
-// One wavefront per logged chunk of a moved node's incidences: each
-// hyperedge not yet listed this round (bitmap test-and-set, read first so a
-// set bit costs no atomic) goes to the small (degree <= 8) or big list.
+// One wavefront per logged chunk of a moved node's incidences: marks each
+// hyperedge in the bitmap.  The chunk's hyperedges ascend, so lanes sharing a
+// bitmap word are adjacent and the first lane of each run sets the run's bits
+// with one atomic (none when they are all set already).
 __global__ __launch_bounds__(kBlock) void k_log_hedges(const int32_t *count, const int32_t *cnode,
                                                        const int32_t *cbeg, const int32_t *noff,
-                                                       const int32_t *inc, const int32_t *off,
-                                                       uint32_t *bits, int32_t *lsmall, int32_t *lbig,
-                                                       int32_t *counts, const int32_t *go)
+                                                       const int32_t *inc, uint32_t *bits, const int32_t *go)
 {
     if (go && *go == 0) return;
     int32_t n = count[0];
@@ -110,17 +109,25 @@ __global__ __launch_bounds__(kBlock) void k_log_hedges(const int32_t *count, con
     for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * wpb) {
         int32_t v = cnode[i];
         int32_t j = cbeg[i] + lane, end = noff[v + 1];
-        bool fresh = false;
-        int32_t e = 0;
-        if (j < end) {
-            e = inc[j];
-            uint32_t bit = 1u << (e & 31);
-            if (!(__hip_atomic_load(&bits[e >> 5], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & bit))
-                fresh = !(atomicOr(&bits[e >> 5], bit) & bit);
+        bool valid = j < end;
+        int32_t e = valid ? inc[j] : 0;
+        int32_t w = valid ? (e >> 5) : -1;
+        uint32_t bit = valid ? 1u << (e & 31) : 0u;
+        int32_t pw = __shfl_up(w, 1, 64);
+        bool head = valid && (lane == 0 || pw != w);
+        unsigned long long heads = __ballot(head);
+        int lead = 63 - __clzll((long long)(heads & ((2ull << lane) - 1ull)));
+        uint32_t run = bit;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t t = __shfl_down(run, o, 64);
+            int tl = __shfl_down(lead, o, 64);
+            if (lane + o < 64 && tl == lead) run |= t;
         }
-        bool small = fresh && off[e + 1] - off[e] <= kSmallMax;
-        wave_append(small, e, lsmall, &counts[1]);
-        wave_append(fresh && !small, e, lbig, &counts[2]);
+        if (head) {
+            uint32_t old = __hip_atomic_load(&bits[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if ((old & run) != run) atomicOr(&bits[w], run);
+        }
     }
 }
 
@@ -145,85 +152,102 @@ __device__ __forceinline__ void add_gain(int32_t u, int32_t delta, const int32_t
     else atomicAdd(&gain[u], delta);
 }
 
-// Listed hyperedges (small ones one per thread, big ones one per wavefront):
-// recount the sides, replace the contribution, and add the change to every
-// pin's gain (a pin that moved trades its old side's contribution for its new
-// side's).  Integer sums, so the result equals a recomputation.
-__device__ __forceinline__ void update_hedges(const int32_t *counts, const int32_t *lsmall,
-                                              const int32_t *lbig, int32_t gsmall,
-                                              const int32_t *off, const int32_t *pins,
-                                              const int32_t *hw, const uint8_t *side,
-                                              const uint8_t *moved, int2 *cc, int32_t *gain,
-                                              uint32_t *bits, const int32_t *bigslot, int32_t *slot)
+constexpr int kUpdWords = 64;                // bitmap words a workgroup sweeps per step
+constexpr int kUpdQueue = kUpdWords * 32;  // hyperedges those words can hold
+
+// recount of hyperedge e's sides: its new contribution
+__device__ __forceinline__ int2 recount_small(int32_t e, const int32_t *off, const int32_t *pins,
+                                              const int32_t *hw, const uint8_t *side, const uint8_t *moved,
+                                              int2 oc, const int32_t *bigslot, int32_t *slot, int32_t *gain)
 {
-    if ((int32_t)blockIdx.x < gsmall) {
-        int32_t n = counts[1];
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gsmall * kBlock) {
-            int32_t e = lsmall[i];
-            int32_t b = off[e], d = off[e + 1] - b;
-            int32_t u[kSmallMax];
-            uint8_t sn[kSmallMax], so[kSmallMax];
-            int32_t n1 = 0;
+    int32_t b = off[e], d = off[e + 1] - b;
+    int32_t u[kSmallMax];
+    uint8_t sn[kSmallMax], so[kSmallMax];
+    int32_t n1 = 0;
 #pragma unroll
-            for (int j = 0; j < kSmallMax; j++)
-                if (j < d) {
-                    u[j] = pins[b + j];
-                    sn[j] = side[u[j]];
-                    so[j] = sn[j] ^ moved[u[j]];
-                    n1 += sn[j];
-                }
-            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+    for (int j = 0; j < kSmallMax; j++)
+        if (j < d) {
+            u[j] = pins[b + j];
+            sn[j] = side[u[j]];
+            so[j] = sn[j] ^ moved[u[j]];
+            n1 += sn[j];
+        }
+    int2 nc = hedge_contrib_value(hw[e], d, n1);
 #pragma unroll
-            for (int j = 0; j < kSmallMax; j++)
-                if (j < d) {
-                    int32_t delta = (sn[j] ? nc.y : nc.x) - (so[j] ? oc.y : oc.x);
-                    if (delta) add_gain(u[j], delta, bigslot, slot, gain);
-                }
-            cc[e] = nc;
-            atomicAnd(&bits[e >> 5], ~(1u << (e & 31)));
+    for (int j = 0; j < kSmallMax; j++)
+        if (j < d) {
+            int32_t delta = (sn[j] ? nc.y : nc.x) - (so[j] ? oc.y : oc.x);
+            if (delta) add_gain(u[j], delta, bigslot, slot, gain);
         }
-        return;
-    }
-    int32_t n = counts[2];
-    int lane = threadIdx.x & 63;
-    const int64_t wpb = kBlock / 64;
-    int64_t gb = (int64_t)gridDim.x - gsmall;
-    for (int64_t i = ((int64_t)blockIdx.x - gsmall) * wpb + (threadIdx.x >> 6); i < n; i += gb * wpb) {
-        int32_t e = lbig[i];
-        int32_t b = off[e], d = off[e + 1] - b;
-        int32_t n1 = 0;
-        for (int j = lane; j < d; j += 64) n1 += side[pins[b + j]];
-        n1 = wave_sum(n1);
-        int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
-        for (int j = lane; j < d; j += 64) {
-            int32_t u = pins[b + j];
-            int sn = side[u], so = sn ^ moved[u];
-            int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
-            if (delta) add_gain(u, delta, bigslot, slot, gain);
-        }
-        if (lane == 0) {
-            cc[e] = nc;
-            atomicAnd(&bits[e >> 5], ~(1u << (e & 31)));
-        }
-    }
+    return nc;
 }
 
-__global__ __launch_bounds__(kBlock) void k_gain_update(const int32_t *counts, const int32_t *lsmall,
-                                                        const int32_t *lbig, int32_t gsmall,
-                                                        const int32_t *off, const int32_t *pins,
-                                                        const int32_t *hw, const uint8_t *side,
-                                                        const uint8_t *moved, int2 *cc, int32_t *gain,
-                                                        uint32_t *bits, const int32_t *bigslot,
+// Marked hyperedges, found by sweeping the bitmap (64 words per step):
+// recount the sides, replace the contribution, and add the change to every
+// pin's gain (a pin that moved trades its old side's contribution for its new
+// side's).  Each sweep step queues its hyperedges in LDS - degree <= 8 from
+// the front, taken one per thread, larger ones from the back, taken one per
+// wavefront.  Integer sums, so the result equals a recomputation.  The sweep
+// clears the bitmap.
+__global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t *bits, const int32_t *off,
+                                                        const int32_t *pins, const int32_t *hw,
+                                                        const uint8_t *side, const uint8_t *moved, int2 *cc,
+                                                        int32_t *gain, const int32_t *bigslot,
                                                         const int32_t *lnbig, const int32_t *ncount,
                                                         const int32_t *go)
 {
     __shared__ int32_t slot[kUpdSlots];
+    __shared__ int32_t queue[kUpdQueue];
+    __shared__ int32_t qs, qb;
     if (go && *go == 0) return;
     int32_t nb = min(ncount[1], kUpdSlots);
     for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
+    if (threadIdx.x == 0) {
+        qs = 0;
+        qb = 0;
+    }
     __syncthreads();
-    update_hedges(counts, lsmall, lbig, gsmall, off, pins, hw, side, moved, cc, gain, bits, bigslot, slot);
-    __syncthreads();
+    int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int64_t base = (int64_t)blockIdx.x * kUpdWords; base < nwords; base += (int64_t)gridDim.x * kUpdWords) {
+        int64_t wi = base + threadIdx.x;
+        uint32_t word = (threadIdx.x < kUpdWords && wi < nwords) ? bits[wi] : 0u;
+        if (word) bits[wi] = 0;
+        while (word) {
+            int k = __ffs((int)word) - 1;
+            word &= word - 1;
+            int32_t e = (int32_t)(wi * 32 + k);
+            // front and back never meet: a step holds at most kUpdQueue hyperedges
+            if (off[e + 1] - off[e] <= kSmallMax) queue[atomicAdd(&qs, 1)] = e;
+            else queue[kUpdQueue - 1 - atomicAdd(&qb, 1)] = e;
+        }
+        __syncthreads();
+        int32_t ns = qs, nbq = qb;
+        for (int32_t q = threadIdx.x; q < ns; q += blockDim.x) {
+            int32_t e = queue[q];
+            cc[e] = recount_small(e, off, pins, hw, side, moved, cc[e], bigslot, slot, gain);
+        }
+        for (int32_t q = wv; q < nbq; q += blockDim.x >> 6) {
+            int32_t e = queue[kUpdQueue - 1 - q];
+            int32_t b = off[e], d = off[e + 1] - b;
+            int32_t n1 = 0;
+            for (int j = lane; j < d; j += 64) n1 += side[pins[b + j]];
+            n1 = wave_sum(n1);
+            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+            for (int j = lane; j < d; j += 64) {
+                int32_t u = pins[b + j];
+                int sn = side[u], so = sn ^ moved[u];
+                int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
+                if (delta) add_gain(u, delta, bigslot, slot, gain);
+            }
+            if (lane == 0) cc[e] = nc;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            qs = 0;
+            qb = 0;
+        }
+        __syncthreads();
+    }
     for (int i = threadIdx.x; i < nb; i += blockDim.x)
         if (slot[i]) atomicAdd(&gain[lnbig[i]], slot[i]);
 }
@@ -278,63 +302,105 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
                                                        const int32_t *go, const int32_t *chunk_node,
                                                        const int32_t *chunk_beg,
                                                        const int32_t *chunk_big,
-                                                       const int32_t *big_chunks, int32_t *big_done)
+                                                       const int32_t *big_chunks, int32_t *big_done,
+                                                       int32_t S, int32_t nw)
 {
     __shared__ int32_t lds[16];
-    __shared__ int32_t agg[6];
+    __shared__ int32_t at[kAggLists], amax[kAggLists], amin[kAggLists];
     if (go && *go == 0) return;
     bool stats = tot != nullptr;
     int32_t cm = ncount[0], ck = ncount[2];
-    int64_t ns = ceil_div(N, kBlock), nw = ceil_div(cm, kBlock / 64);
+    int64_t ns = reduce_grid(N);
     int64_t vb = blockIdx.x;
     if (vb < ns) {
-        int64_t v = vb * kBlock + threadIdx.x;
-        int64_t vf = vb * kBlock, vl = vf + kBlock - 1 < N ? vf + kBlock - 1 : N - 1;
-        bool one = nseg[vf] == nseg[vl];
-        int32_t s0 = nseg[vf];
-        if (threadIdx.x < 2) {
-            agg[3 * threadIdx.x] = 0;
-            agg[3 * threadIdx.x + 1] = INT32_MIN;
-            agg[3 * threadIdx.x + 2] = INT32_MAX;
+        // nodes of degree <= 32, one per thread, over a contiguous chunk
+        int64_t lo, hi;
+        reduce_chunk(N, ns, vb, lo, hi);
+        if (lo >= hi) return;
+        int32_t c0 = 2 * nseg[lo], nl = 2 * nseg[hi - 1] + 2 - c0;
+        bool local = nl <= kAggLists;
+        for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) {
+            at[i] = 0;
+            amax[i] = INT32_MIN;
+            amin[i] = INT32_MAX;
         }
         __syncthreads();
-        if (v < N) {
+        for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
             int32_t b = noff[v], d = noff[v + 1] - b;
             int32_t s = nseg[v];
-            if (d <= kNodeSmallMax && gmask[s]) {
-                int sd = side[v];
-                int32_t g = 0;
-                for (int i = 0; i < d; i++) {
-                    int2 c = cc[inc[b + i]];
-                    g += sd ? c.y : c.x;
-                }
-                gain[v] = g;
-                if (stats && sel_list(s, sd, g, mode)) {
-                    if (one) {
-                        atomicAdd(&agg[3 * sd], 1);
-                        atomicMax(&agg[3 * sd + 1], g);
-                        atomicMin(&agg[3 * sd + 2], g);
-                    } else {
-                        int32_t c = 2 * s + sd;
-                        atomicAdd(&tot[c], 1);
-                        atomicMax(&gmax[c], g);
-                        atomicMin(&gmin[c], g);
-                    }
-                }
+            if (d > kNodeSmallMax || !gmask[s]) continue;
+            int sd = side[v];
+            int32_t g = 0;
+            for (int i = 0; i < d; i++) {
+                int2 c = cc[inc[b + i]];
+                g += sd ? c.y : c.x;
+            }
+            gain[v] = g;
+            if (!stats || !sel_list(s, sd, g, mode)) continue;
+            int32_t c = 2 * s + sd;
+            if (local) {
+                atomicAdd(&at[c - c0], 1);
+                atomicMax(&amax[c - c0], g);
+                atomicMin(&amin[c - c0], g);
+            } else {
+                atomicAdd(&tot[c], 1);
+                atomicMax(&gmax[c], g);
+                atomicMin(&gmin[c], g);
             }
         }
         __syncthreads();
-        if (stats && one && threadIdx.x < 2 && agg[3 * threadIdx.x] > 0) {
-            int32_t c = 2 * s0 + threadIdx.x;
-            atomicAdd(&tot[c], agg[3 * threadIdx.x]);
-            atomicMax(&gmax[c], agg[3 * threadIdx.x + 1]);
-            atomicMin(&gmin[c], agg[3 * threadIdx.x + 2]);
-        }
+        if (stats && local)
+            for (int i = threadIdx.x; i < nl; i += blockDim.x)
+                if (at[i]) {
+                    atomicAdd(&tot[c0 + i], at[i]);
+                    atomicMax(&gmax[c0 + i], amax[i]);
+                    atomicMin(&gmin[c0 + i], amin[i]);
+                }
     } else if (vb < ns + nw) {
-        int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6);
-        if (i < cm)
-            node_gain_one<WAVE>(lnmid[i], threadIdx.x & 63, 64, noff, inc, nseg, gmask, side, cc, gain,
-                                lds, mode, tot, gmax, gmin, stats);
+        // nodes of degree 33..2048, one per wavefront, nw workgroups striding
+        // over the list; with few segments the lists aggregate in LDS
+        bool local = 2 * S <= kAggLists;
+        for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) {
+            at[i] = 0;
+            amax[i] = INT32_MIN;
+            amin[i] = INT32_MAX;
+        }
+        __syncthreads();
+        int lane = threadIdx.x & 63;
+        for (int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6); i < cm; i += (int64_t)nw * (kBlock / 64)) {
+            int32_t v = lnmid[i];
+            int32_t s = nseg[v];
+            if (!gmask[s]) continue;
+            int32_t b = noff[v], d = noff[v + 1] - b;
+            int sd = side[v];
+            int32_t g = 0;
+            for (int j = lane; j < d; j += 64) {
+                int2 c = cc[inc[b + j]];
+                g += sd ? c.y : c.x;
+            }
+            g = wave_sum(g);
+            if (lane != 0) continue;
+            gain[v] = g;
+            if (!stats || !sel_list(s, sd, g, mode)) continue;
+            int32_t c = 2 * s + sd;
+            if (local) {
+                atomicAdd(&at[c], 1);
+                atomicMax(&amax[c], g);
+                atomicMin(&amin[c], g);
+            } else {
+                atomicAdd(&tot[c], 1);
+                atomicMax(&gmax[c], g);
+                atomicMin(&gmin[c], g);
+            }
+        }
+        __syncthreads();
+        if (stats && local)
+            for (int i = threadIdx.x; i < 2 * S; i += blockDim.x)
+                if (at[i]) {
+                    atomicAdd(&tot[i], at[i]);
+                    atomicMax(&gmax[i], amax[i]);
+                    atomicMin(&gmin[i], amin[i]);
+                }
     } else if (vb - ns - nw < ck) {
         // one chunk of a big node: partial sum, then the last chunk of the
         // node records its statistics
@@ -369,53 +435,54 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
 }
 
 // Per-list counts and gain extremes after a gain update (what the node pass
-// records otherwise); clears the move marks and the hyperedge list.
+// records otherwise); clears the move marks and the hyperedge list.  Chunked:
+// the lists of a chunk aggregate in LDS and end in one atomic each.
 __global__ __launch_bounds__(kBlock) void k_gain_stats(int32_t N, const int32_t *nseg, const uint8_t *gmask,
                                                        const uint8_t *side, const int32_t *gain,
                                                        const uint8_t *mode, int32_t *tot, int32_t *gmax,
                                                        int32_t *gmin, uint8_t *moved, int32_t *counts,
                                                        const int32_t *go)
 {
-    __shared__ int32_t agg[6];
+    __shared__ int32_t at[kAggLists], amax[kAggLists], amin[kAggLists];
     if (go && *go == 0) return;
-    if (blockIdx.x == 0 && threadIdx.x < 3) counts[threadIdx.x] = 0;
-    int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    int64_t vf = (int64_t)blockIdx.x * kBlock, vl = vf + kBlock - 1 < N ? vf + kBlock - 1 : N - 1;
-    bool one = nseg[vf] == nseg[vl];
-    int32_t s0 = nseg[vf];
-    if (threadIdx.x < 2) {
-        agg[3 * threadIdx.x] = 0;
-        agg[3 * threadIdx.x + 1] = INT32_MIN;
-        agg[3 * threadIdx.x + 2] = INT32_MAX;
+    if (blockIdx.x == 0 && threadIdx.x == 0) counts[0] = 0;
+    int64_t lo, hi;
+    reduce_chunk(N, gridDim.x, blockIdx.x, lo, hi);
+    if (lo >= hi) return;
+    int32_t c0 = 2 * nseg[lo], nl = 2 * nseg[hi - 1] + 2 - c0;
+    bool local = nl <= kAggLists;
+    for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) {
+        at[i] = 0;
+        amax[i] = INT32_MIN;
+        amin[i] = INT32_MAX;
     }
     __syncthreads();
-    if (v < N) {
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
         if (moved[v]) moved[v] = 0;
         int32_t s = nseg[v];
-        if (gmask[s]) {
-            int sd = side[v];
-            int32_t g = gain[v];
-            if (sel_list(s, sd, g, mode)) {
-                if (one) {
-                    atomicAdd(&agg[3 * sd], 1);
-                    atomicMax(&agg[3 * sd + 1], g);
-                    atomicMin(&agg[3 * sd + 2], g);
-                } else {
-                    int32_t c = 2 * s + sd;
-                    atomicAdd(&tot[c], 1);
-                    atomicMax(&gmax[c], g);
-                    atomicMin(&gmin[c], g);
-                }
-            }
+        if (!gmask[s]) continue;
+        int sd = side[v];
+        int32_t g = gain[v];
+        if (!sel_list(s, sd, g, mode)) continue;
+        int32_t c = 2 * s + sd;
+        if (local) {
+            atomicAdd(&at[c - c0], 1);
+            atomicMax(&amax[c - c0], g);
+            atomicMin(&amin[c - c0], g);
+        } else {
+            atomicAdd(&tot[c], 1);
+            atomicMax(&gmax[c], g);
+            atomicMin(&gmin[c], g);
         }
     }
     __syncthreads();
-    if (one && threadIdx.x < 2 && agg[3 * threadIdx.x] > 0) {
-        int32_t c = 2 * s0 + threadIdx.x;
-        atomicAdd(&tot[c], agg[3 * threadIdx.x]);
-        atomicMax(&gmax[c], agg[3 * threadIdx.x + 1]);
-        atomicMin(&gmin[c], agg[3 * threadIdx.x + 2]);
-    }
+    if (local)
+        for (int i = threadIdx.x; i < nl; i += blockDim.x)
+            if (at[i]) {
+                atomicAdd(&tot[c0 + i], at[i]);
+                atomicMax(&gmax[c0 + i], amax[i]);
+                atomicMin(&gmin[c0 + i], amin[i]);
+            }
 }
 
 // ---- radix select ----------------------------------------------------------------------
@@ -726,33 +793,36 @@ __global__ __launch_bounds__(kBlock) void k_flip(int32_t N, SelView sv, SelState
                                                  const int32_t *nw, unsigned long long *segw,
                                                  const int32_t *go)
 {
-    __shared__ int64_t lds[16];
+    __shared__ unsigned long long dw[kAggLists / 2];  // two's complement sums
     if (go && *go == 0) return;
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    int64_t vf = (int64_t)blockIdx.x * blockDim.x;
-    int64_t vl = vf + blockDim.x - 1 < N ? vf + blockDim.x - 1 : N - 1;
-    bool one = sv.nseg[vf] == sv.nseg[vl];
-    int64_t d01 = 0;
-    if (v < N && sel_chosen(v, sv, st)) {
+    int64_t lo, hi;
+    reduce_chunk(N, gridDim.x, blockIdx.x, lo, hi);
+    if (lo >= hi) return;
+    int32_t s0 = sv.nseg[lo], ns = sv.nseg[hi - 1] + 1 - s0;
+    bool local = 2 * ns <= kAggLists;
+    for (int i = threadIdx.x; i < kAggLists / 2; i += blockDim.x) dw[i] = 0;
+    __syncthreads();
+    for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
+        if (!sel_chosen(v, sv, st)) continue;
         int32_t sd = side[v];
         int64_t w = nw[v];
         side[v] = (uint8_t)(1 - sd);
-        if (one) {
-            d01 += sd ? -w : w;
+        int32_t s = sv.nseg[v];
+        // weight moving from side 0 to side 1 (negative: the other way)
+        if (local) {
+            atomicAdd(&dw[s - s0], (unsigned long long)(sd ? -w : w));
         } else {
-            int32_t s = sv.nseg[v];
             atomicAdd(&segw[2 * s + sd], (unsigned long long)(-w));
             atomicAdd(&segw[2 * s + 1 - sd], (unsigned long long)w);
         }
     }
-    if (one) {
-        d01 = block_sum(d01, lds);
-        if (threadIdx.x == 0 && d01 != 0) {
-            int32_t s = sv.nseg[vf];
-            atomicAdd(&segw[2 * s], (unsigned long long)(-d01));
-            atomicAdd(&segw[2 * s + 1], (unsigned long long)d01);
-        }
-    }
+    __syncthreads();
+    if (local)
+        for (int i = threadIdx.x; i < ns; i += blockDim.x)
+            if (dw[i]) {
+                atomicAdd(&segw[2 * (s0 + i)], 0ull - dw[i]);
+                atomicAdd(&segw[2 * (s0 + i) + 1], dw[i]);
+            }
 }
 
 __global__ __launch_bounds__(kBlock) void k_gather(int32_t N, SelView sv, SelState st, int32_t *ccount,
@@ -837,7 +907,10 @@ __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned 
                                 int64_t *room, int32_t *ccount, SelState st, int32_t *go)
 {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) st.ctl[0] = 2 * S;
+    if (s == 0) {
+        st.ctl[0] = 2 * S;
+        go[3] = 0;
+    }
     if (s >= S) return;
     uint8_t md = 0;
     ccount[s] = 0;
@@ -862,7 +935,8 @@ __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned 
 }
 
 // Rotates the round counters: go[1] = this round's count, go[0] = 0 for the
-// next round's test; go[2] accumulates rounds run.
+// next round's test; go[2] accumulates rounds run.  go[3] (balance rounds):
+// the most further rounds any segment is estimated to need.
 __global__ void k_round_end(int32_t *go)
 {
     go[1] = go[0];
