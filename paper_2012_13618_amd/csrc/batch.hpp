@@ -114,19 +114,9 @@ __global__ __launch_bounds__(kBlock) void k_batch_scatter(const GraphDesc *d, in
 
 // ---- per-graph cut and part weights ------------------------------------------------
 
-// adds c to acc[seg]: one atomic per wavefront when all its lanes share a
-// segment, else one per lane (c == 0 adds nothing)
-__device__ __forceinline__ void seg_add(int64_t c, int32_t seg, unsigned long long *acc)
-{
-    int32_t s0 = __shfl(seg, 0, 64);
-    if (__all(seg == s0)) {
-        c = wave_sum(c);
-        if ((threadIdx.x & 63) == 0 && c && s0 >= 0) atomicAdd(&acc[s0], (unsigned long long)c);
-    } else if (c && seg >= 0) {
-        atomicAdd(&acc[seg], (unsigned long long)c);
-    }
-}
-
+// Per-graph connectivity-1 cut.  SMALL: hyperedges of degree <= 8 over
+// contiguous chunks, per-graph sums in LDS (one atomic per graph and chunk);
+// WAVE / BLOCK: the listed hyperedges, one atomic per cut hyperedge.
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t *list,
                                                     const int32_t *off, const int32_t *pins,
@@ -136,51 +126,42 @@ __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t
 {
     __shared__ unsigned long long orl[16];
     __shared__ int32_t lds[16];
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
-    int64_t contrib = 0;
-    int32_t seg = -1;
-    bool live = e >= 0;
-    int32_t b = 0, d = 0;
-    if (live) {
-        b = off[e];
-        d = off[e + 1] - b;
-        if (S == SMALL && d > kSmallMax) live = false;
-    }
-    int32_t lam = 0;
-    if (kmax <= 64) {
-        unsigned long long m = 0;
-        if (live)
-            for (int i = lane; i < d; i += stride) m |= 1ull << (part[pins[b + i]] & 63);
-        if (S != SMALL) {
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
+    __shared__ unsigned long long acc[kAggLists];
+    bool mask64 = kmax <= 64;
+    if (S == SMALL) {
+        int64_t lo, hi;
+        reduce_chunk(count, gridDim.x, blockIdx.x, lo, hi);
+        if (lo >= hi) return;
+        int32_t s0 = hseg[lo], ns = hseg[hi - 1] + 1 - s0;
+        bool local = ns <= kAggLists;
+        for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) acc[i] = 0;
+        __syncthreads();
+        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
+            if (off[e + 1] - off[e] > kSmallMax) continue;
+            int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
+            if (lam <= 1) continue;
+            unsigned long long c = (unsigned long long)hw[e] * (lam - 1);
+            if (local) atomicAdd(&acc[hseg[e] - s0], c);
+            else atomicAdd(&cut[hseg[e]], c);
         }
-        if (S == BLOCK) {
-            if ((threadIdx.x & 63) == 0) orl[threadIdx.x >> 6] = m;
-            __syncthreads();
-            m = 0;
-            for (int i = 0; i < (int)(blockDim.x >> 6); i++) m |= orl[i];
+        __syncthreads();
+        if (local)
+            for (int i = threadIdx.x; i < ns; i += blockDim.x)
+                if (acc[i]) atomicAdd(&cut[s0 + i], acc[i]);
+    } else if (S == WAVE) {
+        int64_t wpb = blockDim.x >> 6;
+        for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += (int64_t)gridDim.x * wpb) {
+            int32_t e = list[i];
+            int32_t lam = hedge_lambda<WAVE>(e, threadIdx.x & 63, 64, off, pins, part, mask64, orl, lds);
+            if ((threadIdx.x & 63) == 0 && lam > 1)
+                atomicAdd(&cut[hseg[e]], (unsigned long long)hw[e] * (lam - 1));
         }
-        lam = __popcll(m);
     } else {
-        if (live)
-            for (int i = lane; i < d; i += stride) {
-                int32_t p = part[pins[b + i]];
-                bool first = true;
-                for (int j = 0; j < i && first; j++) first = part[pins[b + j]] != p;
-                lam += first ? 1 : 0;
-            }
-        lam = group_sum<S>(lam, lds);
-    }
-    if (e >= 0 && lane == 0) {
-        seg = hseg[e];
-        if (live && lam > 1) contrib = (int64_t)hw[e] * (lam - 1);
-    }
-    if (S == BLOCK) {
-        if (threadIdx.x == 0 && contrib) atomicAdd(&cut[seg], (unsigned long long)contrib);
-    } else {
-        seg_add(contrib, seg, cut);
+        for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+            int32_t e = list[i];
+            int32_t lam = hedge_lambda<BLOCK>(e, threadIdx.x, blockDim.x, off, pins, part, mask64, orl, lds);
+            if (threadIdx.x == 0 && lam > 1) atomicAdd(&cut[hseg[e]], (unsigned long long)hw[e] * (lam - 1));
+        }
     }
 }
 

@@ -353,6 +353,7 @@ static SelView sel_view(Level &L, Segs &sg, const int32_t *gain)
     sv.side = L.side;
     sv.mode = sg.mode;
     sv.m = sg.m;
+    sv.idbits = id_bits(L);
     return sv;
 }
 
@@ -363,7 +364,8 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
 {
     LaunchCtx &lc = cx.lc;
     int idb = id_bits(L);
-    int passes = 3 + (idb + kDigit - 1) / kDigit;
+    // digits of the widest key: gain span (bounded per level) + node id
+    int passes = std::max(1, (L.span_bits + idb + kDigit - 1) / kDigit);
     int32_t nl = 2 * L.S;
     // picks: by the last workgroup (few lists), by the last workgroup of each
     // segment (many lists), or by a launch of their own (no nodes at all)
@@ -543,6 +545,26 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     }
     if (cx.first_levels < 0) cx.first_levels = l;
     int32_t Lmax = l;
+
+    // per level: a bound on the gain span, for the number of selection passes
+    {
+        unsigned long long *bd = ar.get<unsigned long long>(2 * (Lmax + 1));
+        fill(lc, bd, 2 * (int64_t)(Lmax + 1), 0ull);
+        for (int32_t j = 0; j <= Lmax; j++)
+            launch(lc, "level_bound", 4.0 * (lv[j].N + lv[j].E), k_level_bound,
+                   reduce_grid(std::max(lv[j].N, lv[j].E)), kBlock, 0, lv[j].N, lv[j].E,
+                   (const int32_t *)lv[j].noff, (const int32_t *)lv[j].hw, bd + 2 * j);
+        std::vector<unsigned long long> hb(2 * (Lmax + 1));
+        BP_HIP(hipMemcpyAsync(hb.data(), bd, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost,
+                              lc.stream));
+        lc.sync();
+        for (int32_t j = 0; j <= Lmax; j++) {
+            unsigned __int128 span = (unsigned __int128)2 * hb[2 * j] * hb[2 * j + 1];
+            int bits = 0;
+            while (bits < 32 && ((unsigned __int128)1 << bits) <= span) bits++;
+            lv[j].span_bits = bits;
+        }
+    }
 
     // balance candidate buffers sized for the largest segment
     int32_t maxn = 1;
@@ -742,31 +764,20 @@ static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *
     check_lists(L);
     unsigned long long *acc = ar.get<unsigned long long>(4);
     fill(lc, acc, 4, 0ull);
-    if (k <= 64) {
-        launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut_mask<SMALL>, sched_grid<SMALL>(L.E), kBlock, 0,
-               L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut_wave", 0.0, k_cut_mask<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
-               (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut_block", 0.0, k_cut_mask<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
-               (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-    } else {
-        launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut_general<SMALL>, sched_grid<SMALL>(L.E), kBlock,
-               0, L.E, (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut_wave", 0.0, k_cut_general<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
-               (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-        launch(lc, "cut_block", 0.0, k_cut_general<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
-               (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins,
-               (const int32_t *)L.hw, d_part, acc);
-    }
+    int mask64 = k <= 64 ? 1 : 0;
+    launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut<SMALL>, reduce_grid(L.E), kBlock, 0, L.E,
+           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
+           d_part, mask64, acc);
+    launch(lc, "cut_wave", 0.0, k_cut<WAVE>, std::min<int64_t>(sched_grid<WAVE>(L.nmid), kReduceBlocks), kBlock,
+           0, L.nmid, (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
+           (const int32_t *)L.hw, d_part, mask64, acc);
+    launch(lc, "cut_block", 0.0, k_cut<BLOCK>, std::min<int64_t>(L.nbig, kReduceBlocks), kBlock, 0, L.nbig,
+           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
+           d_part, mask64, acc);
     unsigned long long *pw = ar.get<unsigned long long>(k);
     fill(lc, pw, k, 0ull);
     launch(lc, "part_weights", 8.0 * N_nodes, k_part_weights,
-           std::max<int64_t>(1, std::min<int64_t>(ceil_div(N_nodes, kBlock), 1024)), kBlock, 0, N_nodes, k,
+           std::max<int64_t>(1, reduce_grid(N_nodes)), kBlock, 0, N_nodes, k,
            d_part, nw_in, pw);
     launch(lc, "cut", 0.0, k_max_u64, 1, 1024, 0, k, (const unsigned long long *)pw, acc + 1);
     BP_HIP(hipMemcpyAsync(cx.info_h, acc, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, lc.stream));
@@ -1053,13 +1064,15 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
         fill(lc, acc, 2 * S, 0ull);
         fill(lc, pw, kb[S], 0ull);
         check_lists(root);
-        launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, sched_grid<SMALL>(root.E), kBlock,
+        launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, reduce_grid(root.E), kBlock,
                0, root.E, (const int32_t *)nullptr, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
-        launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, sched_grid<WAVE>(root.nmid), kBlock, 0, root.nmid,
+        launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, std::min<int64_t>(sched_grid<WAVE>(root.nmid), kReduceBlocks),
+               kBlock, 0, root.nmid,
                (const int32_t *)root.lmid, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
-        launch(lc, "cut_block", 0.0, k_cut_seg<BLOCK>, sched_grid<BLOCK>(root.nbig), kBlock, 0, root.nbig,
+        launch(lc, "cut_block", 0.0, k_cut_seg<BLOCK>, std::min<int64_t>(root.nbig, kReduceBlocks), kBlock, 0,
+               root.nbig,
                (const int32_t *)root.lbig, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
         launch(lc, "part_weights", 8.0 * Neng, k_part_weights_seg, ceil_div(Neng, kBlock), kBlock, 0,

@@ -234,11 +234,9 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     st.gmin = ar.get<int32_t>(2 * S);
     st.rsel = ar.get<int32_t>(2 * S);
     st.rem = ar.get<int32_t>(2 * S);
-    st.gpass = ar.get<int32_t>(2 * S);
-    st.upre = ar.get<uint32_t>(2 * S);
-    st.uthr = ar.get<uint32_t>(2 * S);
-    st.lpre = ar.get<uint32_t>(2 * S);
-    st.lthr = ar.get<uint32_t>(2 * S);
+    st.kbits = ar.get<int32_t>(2 * S);
+    st.kpre = ar.get<uint64_t>(2 * S);
+    st.kthr = ar.get<uint64_t>(2 * S);
     st.done = ar.get<uint8_t>(2 * S);
     st.ctl = ar.get<int32_t>(4);
     st.tick = ar.get<int32_t>(S);

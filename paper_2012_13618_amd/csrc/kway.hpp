@@ -293,79 +293,76 @@ __global__ __launch_bounds__(kBlock) void k_extract_hedges(
 
 // ---- connectivity-1 cut of the final partition ----------------------------------
 
-// k <= 64: a part-set bitmask per hyperedge.
+// Connectivity (number of distinct parts) of hyperedge e, computed by its
+// schedule group: a part bitmask when every part id is below 64, else a
+// count of parts not seen at an earlier pin (O(d^2), rare large hyperedges).
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_cut_mask(int32_t count, const int32_t *list,
-                                                     const int32_t *off, const int32_t *pins,
-                                                     const int32_t *hw, const int32_t *part,
-                                                     unsigned long long *cut)
+__device__ __forceinline__ int32_t hedge_lambda(int32_t e, int lane, int stride, const int32_t *off,
+                                                const int32_t *pins, const int32_t *part, bool mask64,
+                                                unsigned long long *orl, int32_t *lds)
 {
-    __shared__ unsigned long long lds[16];
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
-    int64_t contrib = 0;
-    if (e >= 0) {
-        int32_t b = off[e], d = off[e + 1] - b;
-        if (!(S == SMALL && d > kSmallMax)) {
-            unsigned long long m = 0;
-            for (int i = lane; i < d; i += stride) m |= 1ull << (part[pins[b + i]] & 63);
-            if (S == WAVE) {
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (mask64) {
+        unsigned long long m = 0;
+        for (int i = lane; i < d; i += stride) m |= 1ull << (part[pins[b + i]] & 63);
+        if (S != SMALL) {
 #pragma unroll
-                for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
-            } else if (S == BLOCK) {
-                // OR-reduce through LDS
-                __shared__ unsigned long long orl[16];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
-                if ((threadIdx.x & 63) == 0) orl[threadIdx.x >> 6] = m;
-                __syncthreads();
-                m = 0;
-                for (int i = 0; i < (int)(blockDim.x >> 6); i++) m |= orl[i];
-            }
-            int lam = __popcll(m);
-            if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+            for (int o = 32; o > 0; o >>= 1) m |= __shfl_xor(m, o, 64);
         }
+        if (S == BLOCK) {
+            if ((threadIdx.x & 63) == 0) orl[threadIdx.x >> 6] = m;
+            __syncthreads();
+            m = 0;
+            for (int i = 0; i < (int)(blockDim.x >> 6); i++) m |= orl[i];
+            __syncthreads();
+        }
+        return __popcll(m);
     }
-    if (S != BLOCK) {
-        contrib = block_sum(contrib, (int64_t *)lds);
-        if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
-    } else if (lane == 0 && contrib) {
-        atomicAdd(cut, (unsigned long long)contrib);
+    int32_t lam = 0;
+    for (int i = lane; i < d; i += stride) {
+        int32_t p = part[pins[b + i]];
+        bool first = true;
+        for (int j = 0; j < i && first; j++) first = part[pins[b + j]] != p;
+        lam += first ? 1 : 0;
     }
+    return group_sum<S>(lam, lds);
 }
 
-// any k: per hyperedge, count parts not seen at an earlier pin (O(d^2) for the
-// rare large hyperedges; small ones sort parts in registers)
+// Connectivity-1 cut, summed over the hyperedges of one schedule (SMALL: all
+// hyperedges of degree <= 8, one per thread; WAVE / BLOCK: the listed ones).
+// Strided over at most kReduceBlocks workgroups, one atomic each.
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_cut_general(int32_t count, const int32_t *list,
-                                                        const int32_t *off, const int32_t *pins,
-                                                        const int32_t *hw, const int32_t *part,
-                                                        unsigned long long *cut)
+__global__ __launch_bounds__(kBlock) void k_cut(int32_t count, const int32_t *list, const int32_t *off,
+                                                const int32_t *pins, const int32_t *hw, const int32_t *part,
+                                                int mask64, unsigned long long *cut)
 {
-    __shared__ int64_t lds[16];
-    int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    __shared__ unsigned long long orl[16];
+    __shared__ int32_t lds[16];
+    __shared__ int64_t lds64[16];
     int64_t contrib = 0;
-    if (e >= 0) {
-        int32_t b = off[e], d = off[e + 1] - b;
-        if (!(S == SMALL && d > kSmallMax)) {
-            int32_t lam = 0;
-            for (int i = lane; i < d; i += stride) {
-                int32_t p = part[pins[b + i]];
-                bool first = true;
-                for (int j = 0; j < i && first; j++) first = part[pins[b + j]] != p;
-                lam += first ? 1 : 0;
-            }
-            lam = group_sum<S>(lam, (int32_t *)lds);
-            if (lane == 0 && lam > 1) contrib = (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+    if (S == SMALL) {
+        for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+             e += (int64_t)gridDim.x * blockDim.x) {
+            if (off[e + 1] - off[e] > kSmallMax) continue;
+            int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
+            if (lam > 1) contrib += (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+        }
+    } else if (S == WAVE) {
+        int64_t wpb = blockDim.x >> 6;
+        for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += (int64_t)gridDim.x * wpb) {
+            int32_t e = list[i];
+            int32_t lam = hedge_lambda<WAVE>(e, threadIdx.x & 63, 64, off, pins, part, mask64, orl, lds);
+            if ((threadIdx.x & 63) == 0 && lam > 1) contrib += (int64_t)(hw ? hw[e] : 1) * (lam - 1);
+        }
+    } else {
+        for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+            int32_t e = list[i];
+            int32_t lam = hedge_lambda<BLOCK>(e, threadIdx.x, blockDim.x, off, pins, part, mask64, orl, lds);
+            if (threadIdx.x == 0 && lam > 1) contrib += (int64_t)(hw ? hw[e] : 1) * (lam - 1);
         }
     }
-    if (S != BLOCK) {
-        contrib = block_sum(contrib, lds);
-        if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
-    } else if (lane == 0 && contrib) {
-        atomicAdd(cut, (unsigned long long)contrib);
-    }
+    contrib = block_sum(contrib, lds64);
+    if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
 }
 
 // Part weights: registers for k <= 8, an LDS histogram for k <= 4096, else

@@ -39,6 +39,9 @@ struct Level {
     int32_t *big_chunks = nullptr, *big_done = nullptr;  // per big node
     int64_t nchunk_bound = 0;
     int32_t *bigslot = nullptr;  // [N] index of a big node in lnbig, else -1
+    // bits of a bound on any list's gain span (max - min gain): 2 max_v sum of
+    // w(e) over v's hyperedges <= 2 (max degree)(max hyperedge weight)
+    int32_t span_bits = 32;
     int2 *cc = nullptr;         // [E] per-hyperedge gain contributions (scratch)
 };
 
@@ -60,8 +63,9 @@ struct SelState {
     int32_t *gmax, *gmin;
     int32_t *rsel;    // r, the number to choose (0 = none)
     int32_t *rem;     // remaining inside the current prefix
-    int32_t *gpass;   // digits over u for this list
-    uint32_t *upre, *uthr, *lpre, *lthr;
+    int32_t *kbits;   // width of the list's key (u << idbits | lid)
+    uint64_t *kpre;   // key bits fixed by the passes so far
+    uint64_t *kthr;   // the r-th smallest key once found
     uint8_t *done;
     int32_t *ctl;     // [4]: [0] lists still open, [1] ticket
     int32_t *tick;    // [S] per-segment tickets of the fused picks

@@ -176,6 +176,32 @@ __global__ __launch_bounds__(kBlock) void k_big_chunks(const int32_t *lnbig, con
     if (threadIdx.x == 0) ncount[2] = q0;
 }
 
+// Largest node degree and largest hyperedge weight of a level (the gain span
+// bound of the selection).
+__global__ __launch_bounds__(kBlock) void k_level_bound(int32_t N, int32_t E, const int32_t *noff,
+                                                        const int32_t *hw, unsigned long long *out)
+{
+    int64_t n = N > E ? N : E, lo, hi;
+    reduce_chunk(n, gridDim.x, blockIdx.x, lo, hi);
+    unsigned long long d = 0, w = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        if (i < N) {
+            unsigned long long x = (unsigned long long)(noff[i + 1] - noff[i]);
+            d = x > d ? x : d;
+        }
+        if (i < E) {
+            unsigned long long x = (unsigned long long)hw[i];
+            w = x > w ? x : w;
+        }
+    }
+    d = wave_max(d);
+    w = wave_max(w);
+    if ((threadIdx.x & 63) == 0) {
+        if (d) atomicMax(&out[0], d);
+        if (w) atomicMax(&out[1], w);
+    }
+}
+
 // ---- Algorithm 1, node side ------------------------------------------------------
 
 // Big nodes: each workgroup takes one chunk and folds its minimum in with a

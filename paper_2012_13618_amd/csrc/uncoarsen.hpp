@@ -491,30 +491,35 @@ struct SelView {
     const int32_t *gain, *nseg, *nbase;
     const uint8_t *side, *mode;
     const int32_t *m;
+    int idbits;  // bits of the largest local node id of the level
 };
 
-// The digit of list c's element (u, lid) at global pass p, or -1 when the
-// element does not match the list's current prefix.  ph = digit range.
-__device__ __forceinline__ int sel_digit(const SelState &st, int32_t c, int p, int idbits,
-                                         uint32_t u, uint32_t lid)
+// Selection key of a node in its list: u = gmax - gain (ascending u is
+// descending gain) above the node's local id, so ascending keys are the
+// (gain desc, id asc) order and every key of a list is distinct.
+__device__ __forceinline__ uint64_t sel_key(int32_t gmax, int32_t g, uint32_t lid, int idbits)
 {
-    int gp = st.gpass[c];
-    int ubits = gp * kDigit;  // u is handled as a gp*12-bit number
-    if (p < gp) {
-        int hi = ubits - kDigit * p, lo = hi - kDigit;
-        if (hi < 32 && p > 0 && ((u ^ st.upre[c]) >> hi) != 0) return -1;
-        return (int)((u >> lo) & (kBins - 1));
-    }
-    if (u != st.upre[c]) return -1;
-    int q = p - gp;
-    int ipass = (idbits + kDigit - 1) / kDigit;
-    if (q >= ipass) return -1;
-    int hi = idbits - kDigit * q, lo = hi - kDigit > 0 ? hi - kDigit : 0;
-    if (q > 0 && hi < 32 && ((lid ^ st.lpre[c]) >> hi) != 0) return -1;
-    return (int)((lid >> lo) & ((1u << (hi - lo)) - 1u));
+    return ((uint64_t)(uint32_t)((int64_t)gmax - g) << idbits) | lid;
 }
 
-// Pick of list c after pass p: the digit holding the rem-th element.  One
+// Width in bits of a list's keys, from its gain extremes.
+__device__ __forceinline__ int sel_kbits(int32_t gmax, int32_t gmin, int idbits)
+{
+    return bitlen_u32((uint32_t)((int64_t)gmax - gmin)) + idbits;
+}
+
+// Digit (12 bits, from the top of the T-bit key) of key k at pass p, or -1
+// when k does not carry the prefix fixed by the earlier passes.
+__device__ __forceinline__ int sel_digit_k(uint64_t k, int T, int p, uint64_t pre)
+{
+    int hi = T - kDigit * p;
+    if (hi <= 0) return (p == 0 && T == 0) ? 0 : -1;  // a 0-bit key: one bin
+    int lo = hi - kDigit > 0 ? hi - kDigit : 0;
+    if (p > 0 && hi < 64 && ((k ^ pre) >> hi) != 0) return -1;
+    return (int)((k >> lo) & ((1ull << (hi - lo)) - 1ull));
+}
+
+// Pick of list c after pass p: the digit holding the rem-th key.  One
 // workgroup.  Clears the bins it read.
 __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, const uint8_t *mode,
                               const int32_t *m, int64_t *lds)
@@ -540,14 +545,10 @@ __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, 
             }
             st.rsel[c] = (int32_t)r;
             st.rem[c] = (int32_t)r;
-            st.upre[c] = 0;
-            st.lpre[c] = 0;
-            uint32_t range = r > 0 ? (uint32_t)((int64_t)st.gmax[c] - st.gmin[c]) : 0u;
-            int ub = bitlen_u32(range);
-            st.gpass[c] = (ub + kDigit - 1) / kDigit;
+            st.kpre[c] = 0;
+            st.kthr[c] = 0;
+            st.kbits[c] = r > 0 ? sel_kbits(st.gmax[c], st.gmin[c], idbits) : 0;
             st.done[c] = r == 0;
-            st.uthr[c] = 0;
-            st.lthr[c] = 0;
             if (r == 0) atomicSub(&st.ctl[0], 1);
         }
         __syncthreads();
@@ -583,36 +584,15 @@ __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, 
     __syncthreads();
     for (int j = 0; j < per; j++) hc[threadIdx.x * per + j] = 0;
     if (threadIdx.x == 0 && sbin >= 0) {
-        int gp = st.gpass[c];
+        int T = st.kbits[c];
+        int hi = T - kDigit * p, lo = hi - kDigit > 0 ? hi - kDigit : 0;
         int32_t left = r - sbefore;
-        bool all = left == sin_;
+        uint64_t pre = st.kpre[c] | ((uint64_t)sbin << lo);
+        st.kpre[c] = pre;
         st.rem[c] = left;
-        bool fin = false;
-        if (p < gp) {
-            int hi = gp * kDigit - kDigit * p, lo = hi - kDigit;
-            uint32_t pre = st.upre[c] | ((uint32_t)sbin << lo);
-            st.upre[c] = pre;
-            if (all) {
-                st.uthr[c] = pre | (lo ? ((1u << lo) - 1u) : 0u);
-                st.lthr[c] = 0xffffffffu;
-                fin = true;
-            } else if (lo == 0 && idbits == 0) {
-                st.uthr[c] = pre;
-                st.lthr[c] = 0xffffffffu;
-                fin = true;
-            }
-        } else {
-            int q = p - gp;
-            int hi = idbits - kDigit * q, lo = hi - kDigit > 0 ? hi - kDigit : 0;
-            uint32_t pre = st.lpre[c] | ((uint32_t)sbin << lo);
-            st.lpre[c] = pre;
-            if (all || lo == 0) {
-                st.uthr[c] = st.upre[c];
-                st.lthr[c] = pre | (lo ? ((1u << lo) - 1u) : 0u);
-                fin = true;
-            }
-        }
-        if (fin) {
+        // done when the whole bin is taken or the bin is a single key
+        if (left == sin_ || lo == 0) {
+            st.kthr[c] = pre | (lo ? ((1ull << lo) - 1ull) : 0ull);
             st.done[c] = 1;
             atomicSub(&st.ctl[0], 1);
         }
@@ -714,25 +694,12 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
             if (!sel_list(s, sd, g, sv.mode)) continue;
             int32_t c = 2 * s + sd;
             if (p > 0 && st.done[c]) continue;
-            // pass 0 runs before the pick has set the schedule: u digit 0 of
-            // the span computed from the node pass's extremes
-            uint32_t u = (uint32_t)((int64_t)st.gmax[c] - g);
-            uint32_t lid = (uint32_t)(v - sv.nbase[s]);
-            int dig;
-            if (p == 0) {
-                int ub = bitlen_u32((uint32_t)((int64_t)st.gmax[c] - st.gmin[c]));
-                int gp = (ub + kDigit - 1) / kDigit;
-                if (gp > 0) {
-                    dig = (int)((u >> (gp * kDigit - kDigit)) & (kBins - 1));
-                } else {
-                    // every gain equal: the first digit is over the id
-                    int hi = idbits, lo = hi - kDigit > 0 ? hi - kDigit : 0;
-                    dig = (int)((lid >> lo) & ((1u << (hi - lo)) - 1u));
-                }
-            } else {
-                dig = sel_digit(st, c, p, idbits, u, lid);
-                if (dig < 0) continue;
-            }
+            uint64_t k = sel_key(st.gmax[c], g, (uint32_t)(v - sv.nbase[s]), idbits);
+            // pass 0 runs before the pick has fixed the key width: from the
+            // extremes the node pass recorded
+            int T = p == 0 ? sel_kbits(st.gmax[c], st.gmin[c], idbits) : st.kbits[c];
+            int dig = sel_digit_k(k, T, p, p == 0 ? 0ull : st.kpre[c]);
+            if (dig < 0) continue;
             if (use_lds) atomicAdd(&h[(c - cbase) * kBins + dig], 1u);
             else atomicAdd(&st.hist[(int64_t)c * kBins + dig], 1u);
         }
@@ -782,9 +749,7 @@ __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const S
     if (!sel_list(s, sd, g, sv.mode)) return false;
     int32_t c = 2 * s + sd;
     if (st.rsel[c] <= 0) return false;
-    uint32_t u = (uint32_t)((int64_t)st.gmax[c] - g);
-    if (u != st.uthr[c]) return u < st.uthr[c];
-    return (uint32_t)(v - sv.nbase[s]) <= st.lthr[c];
+    return sel_key(st.gmax[c], g, (uint32_t)(v - sv.nbase[s]), sv.idbits) <= st.kthr[c];
 }
 
 // ---- moves ---------------------------------------------------------------------------------
