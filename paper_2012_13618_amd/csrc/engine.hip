@@ -401,7 +401,8 @@ static bool trace_on()
 
 // With estimate (balance rounds), go[3] holds the rounds the segments still
 // need as estimated by the last round: the next chunk is that long, and an
-// estimate of zero ends the loop.
+// estimate of zero ends the loop.  round(ri, gc) issues round ri; gc is its
+// active-segment counter, which every kernel of the round checks.
 template <typename Round>
 static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, Round round)
 {
@@ -413,15 +414,15 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, R
     for (;;) {
         for (int i = 0; i < chunk; i++) {
             first.push_back(lc.serial);
-            round(issued == 0);
-            launch(lc, "round", 0.0, k_round_end, 1, 1, 0, sg.go);
+            round((int32_t)issued, sg.go + 4 + issued % 3);
             issued++;
         }
-        BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
+        BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
         lc.sync(false);
         int32_t *g = (int32_t *)cx.info_h;
-        int64_t ran = g[2];
-        bool end = g[1] == 0 || (estimate && g[3] == 0);
+        int32_t last = g[4 + (issued - 1) % 3];
+        int64_t ran = g[2] + (last > 0 ? 1 : 0);
+        bool end = last == 0 || (estimate && g[3] == 0);
         if (lc.prof && ran < (int64_t)first.size()) lc.no_bytes(first[ran], lc.serial);
         if (end || issued > limit) {
             lc.hold--;
@@ -438,15 +439,15 @@ static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *g
 {
     LaunchCtx &lc = cx.lc;
     int64_t gs = ceil_div(L.S, kBlock);
-    fill(lc, sg.go, 4, 0);
-    return chunked_rounds(cx, sg, (int64_t)L.N + 2, false, [&](bool first) {
+    fill(lc, sg.go, 8, 0);
+    return chunked_rounds(cx, sg, (int64_t)L.N + 2, false, [&](int32_t ri, const int32_t *gc) {
         launch(lc, "round", 0.0, k_round_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
                (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
-               (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, first ? 1 : 0,
-               sg.mode, sg.gmask, sg.m, sg.st, sg.go);
-        run_gains(cx, L, sg, gain, true, sg.go);
-        run_select(cx, L, sg, gain, sg.go);
-        flip(cx, L, sg, gain, sg.go);
+               (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, ri, sg.mode, sg.gmask, sg.m,
+               sg.st, sg.go);
+        run_gains(cx, L, sg, gain, true, gc);
+        run_select(cx, L, sg, gain, gc);
+        flip(cx, L, sg, gain, gc);
     });
 }
 
@@ -466,7 +467,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                sg.mode, sg.gmask, sg.done, sg.st, sg.go);
     // balance step: the first round computes every gain; later rounds update
     // the gains from the hyperedges of the nodes the previous round moved
-    fill(lc, sg.go, 4, 0);
+    fill(lc, sg.go, 8, 0);
     fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
     int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
     Arena &ar = *cx.ar;
@@ -489,28 +490,28 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     }
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
     int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
-    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](bool first) {
+    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](int32_t ri, const int32_t *gc) {
         launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
                (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
-               sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go);
-        if (first || !incr) {
-            run_gains(cx, L, sg, gain, true, sg.go);
+               sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go, ri);
+        if (ri == 0 || !incr) {
+            run_gains(cx, L, sg, gain, true, gc);
         } else {
             launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
                    (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
-                   (const int32_t *)L.inc, bits, (const int32_t *)sg.go);
+                   (const int32_t *)L.inc, bits, gc);
             launch(lc, "gain_update", 4.0 * nbits, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
                    (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
-                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)sg.go);
+                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc);
             launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
-                   ml.moved, ml.count, (const int32_t *)sg.go);
+                   ml.moved, ml.count, gc);
         }
-        run_select(cx, L, sg, gain, sg.go);
+        run_select(cx, L, sg, gain, gc);
         launch(lc, "balance", 10.0 * L.N, k_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
-               sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, (const int32_t *)sg.go);
+               sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, gc);
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
                (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
                (const int32_t *)L.nw, (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
@@ -552,7 +553,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
         fill(lc, bd, 2 * (int64_t)(Lmax + 1), 0ull);
         for (int32_t j = 0; j <= Lmax; j++)
             launch(lc, "level_bound", 4.0 * (lv[j].N + lv[j].E), k_level_bound,
-                   reduce_grid(std::max(lv[j].N, lv[j].E)), kBlock, 0, lv[j].N, lv[j].E,
+                   std::min<int64_t>(reduce_grid(std::max(lv[j].N, lv[j].E)), 128), kBlock, 0, lv[j].N, lv[j].E,
                    (const int32_t *)lv[j].noff, (const int32_t *)lv[j].hw, bd + 2 * j);
         std::vector<unsigned long long> hb(2 * (Lmax + 1));
         BP_HIP(hipMemcpyAsync(hb.data(), bd, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost,

@@ -240,7 +240,7 @@ inline Segs alloc_segs(Arena &ar, int32_t S)
     st.done = ar.get<uint8_t>(2 * S);
     st.ctl = ar.get<int32_t>(4);
     st.tick = ar.get<int32_t>(S);
-    g.go = ar.get<int32_t>(4);
+    g.go = ar.get<int32_t>(8);
     g.ccount = ar.get<int32_t>(S);
     return g;
 }

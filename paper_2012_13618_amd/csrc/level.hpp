@@ -93,7 +93,8 @@ struct Segs {
     int32_t *ccount;          // balance candidates per segment
     uint64_t *cand;           // [S * cand_stride]
     int32_t cand_stride = 0;
-    int32_t *go;              // [4] round counters (current, last, rounds run)
+    int32_t *go;              // [8] round counters: [1] last count, [2] rounds run, [3] estimate,
+                              // [4..6] per-round active counts (round i uses slot 4 + i % 3)
     SelState st;              // selection state of the 2S lists
 };
 

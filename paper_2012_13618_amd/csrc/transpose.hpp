@@ -194,9 +194,19 @@ __global__ __launch_bounds__(kBlock) void k_level_bound(int32_t N, int32_t E, co
             w = x > w ? x : w;
         }
     }
+    __shared__ unsigned long long ld[16], lw[16];
     d = wave_max(d);
     w = wave_max(w);
     if ((threadIdx.x & 63) == 0) {
+        ld[threadIdx.x >> 6] = d;
+        lw[threadIdx.x >> 6] = w;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < (int)(blockDim.x >> 6); i++) {
+            d = ld[i] > d ? ld[i] : d;
+            w = lw[i] > w ? lw[i] : w;
+        }
         if (d) atomicMax(&out[0], d);
         if (w) atomicMax(&out[1], w);
     }

@@ -816,15 +816,33 @@ __device__ __forceinline__ void reset_lists(SelState st, int32_t s)
 }
 
 // Algorithm 3 loop test per segment: P0 below its share and P1 non-empty.
+// Round counters without a launch of their own: round ri counts its active
+// segments in slot ri % 3, reads the previous round's count from slot
+// (ri - 1) % 3 (complete) and clears slot (ri + 1) % 3 for the next round.
+__device__ __forceinline__ int32_t round_counters(int32_t *go, int32_t ri, int32_t s)
+{
+    int32_t prev = ri > 0 ? go[4 + (ri + 2) % 3] : 0;
+    if (s == 0) {
+        go[4 + (ri + 1) % 3] = 0;
+        go[1] = prev;
+        if (prev) go[2] += 1;
+        go[3] = 0;
+    }
+    return prev;
+}
+
 __global__ void k_round_initial(int32_t S, int32_t j, const int32_t *nbase, const int32_t *coarsest,
                                 const int32_t *k0, const int32_t *k1, const int64_t *W,
-                                const unsigned long long *segw, int32_t *cnt1, int first,
+                                const unsigned long long *segw, int32_t *cnt1, int32_t ri,
                                 uint8_t *mode, uint8_t *gmask, int32_t *m, SelState st, int32_t *go)
 {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    bool first = ri == 0;
     if (s == 0) st.ctl[0] = 2 * S;
+    int32_t prev = round_counters(go, ri, s);
+    int32_t *cur = go + 4 + ri % 3;
     if (s >= S) return;
-    if (go[1] == 0 && !first) {  // the previous round found nothing to do
+    if (prev == 0 && !first) {  // the previous round found nothing to do
         mode[s] = 0;
         gmask[s] = 0;
         return;
@@ -839,7 +857,7 @@ __global__ void k_round_initial(int32_t S, int32_t j, const int32_t *nbase, cons
         if (run) {
             md = kList1;
             m[s] = (int32_t)ceil_sqrt_i64(n);
-            atomicAdd(&go[0], 1);
+            atomicAdd(cur, 1);
         }
     }
     mode[s] = md;
@@ -853,10 +871,7 @@ __global__ void k_round_refine(int32_t S, int32_t j, const int32_t *coarsest, ui
                                uint8_t *gmask, uint8_t *done, SelState st, int32_t *go)
 {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) {
-        st.ctl[0] = 2 * S;
-        go[0] = 1;
-    }
+    if (s == 0) st.ctl[0] = 2 * S;
     if (s >= S) return;
     bool present = coarsest[s] >= j;
     mode[s] = present ? (kList0 | kList1 | kGainNonNeg | kMinPair) : 0;
@@ -869,13 +884,12 @@ __global__ void k_round_refine(int32_t S, int32_t j, const int32_t *coarsest, ui
 __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned long long *segw,
                                 const int64_t *max0, const int64_t *max1, uint8_t *done,
                                 uint8_t *mode, uint8_t *gmask, int32_t *m, int64_t *need,
-                                int64_t *room, int32_t *ccount, SelState st, int32_t *go)
+                                int64_t *room, int32_t *ccount, SelState st, int32_t *go, int32_t ri)
 {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) {
-        st.ctl[0] = 2 * S;
-        go[3] = 0;
-    }
+    if (s == 0) st.ctl[0] = 2 * S;
+    round_counters(go, ri, s);
+    int32_t *cur = go + 4 + ri % 3;
     if (s >= S) return;
     uint8_t md = 0;
     ccount[s] = 0;
@@ -891,7 +905,7 @@ __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned 
             need[s] = h ? w1 - max1[s] : w0 - max0[s];
             room[s] = h ? max0[s] - w0 : max1[s] - w1;
             m[s] = (int32_t)ceil_sqrt_i64(nbase[s + 1] - nbase[s]);
-            atomicAdd(&go[0], 1);
+            atomicAdd(cur, 1);
         }
     }
     mode[s] = md;
@@ -899,14 +913,5 @@ __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned 
     reset_lists(st, s);
 }
 
-// Rotates the round counters: go[1] = this round's count, go[0] = 0 for the
-// next round's test; go[2] accumulates rounds run.  go[3] (balance rounds):
-// the most further rounds any segment is estimated to need.
-__global__ void k_round_end(int32_t *go)
-{
-    go[1] = go[0];
-    if (go[0]) go[2] += 1;
-    go[0] = 0;
-}
 
 }  // namespace bp
