@@ -380,6 +380,24 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
     }
 }
 
+static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go);
+
+// Selection and flip of the chosen nodes (Algorithm 3 rounds, Algorithm 5
+// swaps): one workgroup per segment when every segment is small, else the
+// multi-workgroup passes and a flip launch.
+static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
+{
+    if (L.maxseg_nodes <= kSegSelectMax) {
+        BalFinish bf{};
+        bf.side = L.side;
+        launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
+               sg.st, id_bits(L), 0, (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go);
+        return;
+    }
+    run_select(cx, L, sg, gain, go);
+    flip(cx, L, sg, gain, go);
+}
+
 static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
     launch(cx.lc, "flip", 6.0 * L.N, k_flip, reduce_grid(L.N), kBlock, 0, L.N,
@@ -446,8 +464,7 @@ static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *g
                (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, ri, sg.mode, sg.gmask, sg.m,
                sg.st, sg.go);
         run_gains(cx, L, sg, gain, true, gc);
-        run_select(cx, L, sg, gain, gc);
-        flip(cx, L, sg, gain, gc);
+        select_and_flip(cx, L, sg, gain, gc);
     });
 }
 
@@ -459,8 +476,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
                sg.mode, sg.gmask, sg.done, sg.st, sg.go);
         run_gains(cx, L, sg, gain, true, nullptr);
-        run_select(cx, L, sg, gain, nullptr);
-        flip(cx, L, sg, gain, nullptr);
+        select_and_flip(cx, L, sg, gain, nullptr);
     }
     if (cx.prm.refine_iters == 0)
         launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
@@ -488,6 +504,8 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         fill(lc, bits, nbits, 0u);
         fill(lc, ml.count, 4, 0);
     }
+    BalFinish bf{sg.mode, L.nw, sg.need, sg.room, L.side, (unsigned long long *)sg.w, sg.done, sg.stuck, ml,
+                 sg.go, sg.bal_moved};
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
     int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
     return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](int32_t ri, const int32_t *gc) {
@@ -509,13 +527,16 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
                    ml.moved, ml.count, gc);
         }
+        if (L.maxseg_nodes <= kSegSelectMax) {
+            launch(lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
+                   sg.st, id_bits(L), 1, (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc);
+            return;
+        }
         run_select(cx, L, sg, gain, gc);
         launch(lc, "balance", 10.0 * L.N, k_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
                sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, gc);
-        launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S,
-               (const uint8_t *)sg.mode, (const int32_t *)sg.ccount, sg.cand, sg.cand_stride, cap,
-               (const int32_t *)L.nw, (const int64_t *)sg.need, (const int64_t *)sg.room, L.side,
-               (unsigned long long *)sg.w, sg.done, sg.stuck, ml, sg.go, sg.bal_moved);
+        launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S, (const int32_t *)sg.ccount,
+               sg.cand, sg.cand_stride, cap, bf);
     });
 }
 

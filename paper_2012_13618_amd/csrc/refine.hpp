@@ -91,34 +91,29 @@ __device__ void log_moves(int32_t p, const uint64_t *a, const MoveLog &ml, int64
     }
 }
 
-// One workgroup per balancing segment: sort its candidates, take the shortest
-// prefix covering the excess, cut back to what the other side can take, move.
-__global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *mode,
-                                                     const int32_t *ccount, uint64_t *cand,
-                                                     int32_t stride, int32_t lds_cap,
-                                                     const int32_t *nw,
-                                                     const int64_t *need, const int64_t *room,
-                                                     uint8_t *side, unsigned long long *segw,
-                                                     uint8_t *done, int32_t *stuck, MoveLog ml,
-                                                     int32_t *go, int64_t *bal_moved)
+// What the balance step of a segment needs besides its sorted candidates.
+struct BalFinish {
+    const uint8_t *mode;
+    const int32_t *nw;
+    const int64_t *need, *room;
+    uint8_t *side;
+    unsigned long long *segw;
+    uint8_t *done;
+    int32_t *stuck;
+    MoveLog ml;
+    int32_t *go;          // go[3]: most further rounds a segment is estimated to need
+    int64_t *bal_moved;   // [2S] weight moved and rounds run this level
+};
+
+// Balance step of segment s given its candidates a[0..cnt) in ascending
+// (gain desc, id asc) order: take the shortest prefix covering the excess,
+// cut back to what the other side can take, move it.  One workgroup.
+__device__ void bal_take_prefix(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf, int64_t *lds64)
 {
-    extern __shared__ uint64_t keys_lds[];
-    __shared__ int64_t lds64[16];
     __shared__ int64_t carry;
     __shared__ int32_t p1s, ps;
-    int32_t s = blockIdx.x;
-    uint8_t md = mode[s];
-    if (!md) return;
-    int h = (md & kList1) ? 1 : 0;
-    int32_t cnt = ccount[s];
-    int n2 = next_pow2(cnt > 0 ? cnt : 1);
-    // sort in LDS when the launch reserved room for it, else in place
-    uint64_t *a = n2 <= lds_cap ? keys_lds : cand + (int64_t)s * stride;
-    for (int i = threadIdx.x; i < n2; i += blockDim.x)
-        a[i] = i < cnt ? cand[(int64_t)s * stride + i] : kNoKey;
-    __syncthreads();
-    block_bitonic_sort(a, n2);
-    int64_t nd = need[s], rm = room[s];
+    int h = (bf.mode[s] & kList1) ? 1 : 0;
+    int64_t nd = bf.need[s], rm = bf.room[s];
     if (threadIdx.x == 0) {
         carry = 0;
         p1s = cnt;
@@ -128,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
     // prefix weights in sorted order, chunk by chunk
     for (int base = 0; base < cnt; base += blockDim.x) {
         int i = base + threadIdx.x;
-        int64_t w = i < cnt ? (int64_t)nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
+        int64_t w = i < cnt ? (int64_t)bf.nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
         int64_t tot;
         int64_t incl = block_excl_scan(w, lds64, &tot) + w + carry;
         // prefix length i+1 reaches the excess
@@ -142,7 +137,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
     __syncthreads();
     for (int base = 0; base < p1; base += blockDim.x) {
         int i = base + threadIdx.x;
-        int64_t w = i < p1 ? (int64_t)nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
+        int64_t w = i < p1 ? (int64_t)bf.nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
         int64_t tot;
         int64_t incl = block_excl_scan(w, lds64, &tot) + w + carry;
         if (i < p1 && incl <= rm) atomicMax(&ps, i + 1);
@@ -154,31 +149,50 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const uint8_t *m
     int64_t moved = 0;
     for (int i = threadIdx.x; i < p; i += blockDim.x) {
         uint32_t v = (uint32_t)(a[i] & 0xffffffffu);
-        side[v] = (uint8_t)(1 - h);
-        moved += nw[v];
+        bf.side[v] = (uint8_t)(1 - h);
+        moved += bf.nw[v];
     }
     moved = block_sum(moved, lds64);
-    if (ml.cnode) log_moves(p, a, ml, lds64);
+    if (bf.ml.cnode) log_moves(p, a, bf.ml, lds64);
     if (threadIdx.x == 0) {
         if (p == 0) {
-            stuck[s] = 1;
-            done[s] = 1;
+            bf.stuck[s] = 1;
+            bf.done[s] = 1;
         } else {
-            atomicAdd(&segw[2 * s + h], (unsigned long long)(-moved));
-            atomicAdd(&segw[2 * s + 1 - h], (unsigned long long)moved);
+            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
+            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
             // rounds still needed if later rounds move what the level's
             // rounds moved on average
-            int64_t mw = bal_moved[2 * s] + moved, mr = bal_moved[2 * s + 1] + 1;
-            bal_moved[2 * s] = mw;
-            bal_moved[2 * s + 1] = mr;
+            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            bf.bal_moved[2 * s] = mw;
+            bf.bal_moved[2 * s + 1] = mr;
             int64_t rest = nd - moved;
             if (rest > 0) {
                 int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
-                atomicMax(&go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
+                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
             }
         }
     }
 }
 
+// One workgroup per balancing segment: sort its gathered candidates, then
+// the prefix step.
+__global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *ccount, uint64_t *cand,
+                                                     int32_t stride, int32_t lds_cap, BalFinish bf)
+{
+    extern __shared__ uint64_t keys_lds[];
+    __shared__ int64_t lds64[16];
+    int32_t s = blockIdx.x;
+    if (!bf.mode[s]) return;
+    int32_t cnt = ccount[s];
+    int n2 = next_pow2(cnt > 0 ? cnt : 1);
+    // sort in LDS when the launch reserved room for it, else in place
+    uint64_t *a = n2 <= lds_cap ? keys_lds : cand + (int64_t)s * stride;
+    for (int i = threadIdx.x; i < n2; i += blockDim.x)
+        a[i] = i < cnt ? cand[(int64_t)s * stride + i] : kNoKey;
+    __syncthreads();
+    block_bitonic_sort(a, n2);
+    bal_take_prefix(s, a, cnt, bf, lds64);
+}
 
 }  // namespace bp

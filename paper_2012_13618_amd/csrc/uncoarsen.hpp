@@ -752,6 +752,159 @@ __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const S
     return sel_key(st.gmax[c], g, (uint32_t)(v - sv.nbase[s]), sv.idbits) <= st.kthr[c];
 }
 
+// ---- small segments: the whole selection and the moves in one workgroup --------------------
+
+constexpr int kSegThreads = 1024;
+constexpr int kSegItems = 16;                           // nodes per thread, kept in registers
+constexpr int32_t kSegSelectMax = kSegThreads * kSegItems;  // largest segment taken this way
+constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
+
+// One workgroup per segment of at most kSegSelectMax nodes: each list's
+// r-th key by the same 12-bit radix select as the multi-workgroup passes,
+// with the segment's gains in registers and the histogram in LDS, then the
+// moves (bf.side is written): kind 0 flips the chosen nodes of both lists
+// (Algorithm 3 and the swap of Algorithm 5); kind 1 sorts the chosen nodes of
+// the over-weight side and takes the balance prefix (Algorithm 5).  The chosen
+// set is the one the multi-workgroup path chooses: the same keys, the same r.
+__global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
+                                                           int kind, const int32_t *nw,
+                                                           unsigned long long *segw, BalFinish bf,
+                                                           const int32_t *go)
+{
+    __shared__ uint32_t hist[kBins];
+    __shared__ int64_t lds64[16];
+    __shared__ int32_t sbin, sbefore, sin_;
+    __shared__ uint64_t keys[kSegKeys];
+    __shared__ int32_t nkeys;
+    if (go && *go == 0) return;
+    int32_t s = blockIdx.x;
+    uint8_t md = sv.mode[s];
+    if (!md) return;
+    int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
+    int32_t g[kSegItems];
+    uint32_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
+#pragma unroll
+    for (int j = 0; j < kSegItems; j++) {
+        int32_t i = j * kSegThreads + (int32_t)threadIdx.x;
+        g[j] = 0;
+        if (i < n) {
+            int sd = sv.side[a0 + i];
+            g[j] = sv.gain[a0 + i];
+            sbits |= (uint32_t)sd << j;
+            ebits |= (sel_list(s, sd, g[j], sv.mode) ? 1u : 0u) << j;
+        }
+    }
+    uint64_t thr[2] = {0, 0};
+    int32_t rr[2] = {0, 0};
+    int per = kBins / kSegThreads;
+    for (int sd = 0; sd < 2; sd++) {
+        int32_t c = 2 * s + sd;
+        int64_t r = 0;
+        if ((md >> sd) & 1) {
+            int64_t t = st.tot[c];
+            if (md & kMinPair) {
+                int64_t o = st.tot[c ^ 1];
+                r = t < o ? t : o;
+            } else {
+                r = t < (int64_t)sv.m[s] ? t : (int64_t)sv.m[s];
+            }
+        }
+        rr[sd] = (int32_t)r;
+        if (r == 0) continue;
+        int32_t gmax = st.gmax[c];
+        int T = bitlen_u32((uint32_t)((int64_t)gmax - st.gmin[c])) + idbits;
+        uint64_t pre = 0;
+        int32_t rem = (int32_t)r;
+        for (int p = 0;; p++) {
+            int hi = T - kDigit * p, lo = hi - kDigit > 0 ? hi - kDigit : 0;
+            for (int j = 0; j < per; j++) hist[threadIdx.x * per + j] = 0;
+            __syncthreads();
+            uint32_t mine = ebits & (sd ? sbits : ~sbits);
+#pragma unroll
+            for (int j = 0; j < kSegItems; j++) {
+                if (!((mine >> j) & 1)) continue;
+                uint64_t k = sel_key(gmax, g[j], (uint32_t)(j * kSegThreads + threadIdx.x), idbits);
+                if (p > 0 && ((k ^ pre) >> hi) != 0) continue;
+                int dig = hi > 0 ? (int)((k >> lo) & ((1ull << (hi - lo)) - 1ull)) : 0;
+                atomicAdd(&hist[dig], 1u);
+            }
+            __syncthreads();
+            int64_t loc = 0, tot;
+            for (int j = 0; j < per; j++) loc += hist[threadIdx.x * per + j];
+            int64_t ex = block_excl_scan(loc, lds64, &tot);
+            if (ex < rem && rem <= ex + loc) {
+                int64_t acc = ex;
+                for (int j = 0; j < per; j++) {
+                    int64_t x = hist[threadIdx.x * per + j];
+                    if (acc + x >= rem) {
+                        sbin = threadIdx.x * per + j;
+                        sbefore = (int32_t)acc;
+                        sin_ = (int32_t)x;
+                        break;
+                    }
+                    acc += x;
+                }
+            }
+            __syncthreads();
+            int32_t bin = sbin, left = rem - sbefore, inb = sin_;
+            __syncthreads();
+            pre |= (uint64_t)bin << lo;
+            rem = left;
+            if (left == inb || lo == 0) {
+                thr[sd] = pre | (lo ? ((1ull << lo) - 1ull) : 0ull);
+                break;
+            }
+        }
+    }
+    if (threadIdx.x == 0) {
+        st.rsel[2 * s] = rr[0];
+        st.rsel[2 * s + 1] = rr[1];
+    }
+    if (kind == 0) {
+        // flip the chosen nodes of both lists
+        int64_t d01 = 0;  // weight moving from side 0 to side 1
+#pragma unroll
+        for (int j = 0; j < kSegItems; j++) {
+            if (!((ebits >> j) & 1)) continue;
+            int sd = (sbits >> j) & 1;
+            if (rr[sd] == 0) continue;
+            uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
+            if (sel_key(st.gmax[2 * s + sd], g[j], lid, idbits) > thr[sd]) continue;
+            int32_t v = a0 + (int32_t)lid;
+            int64_t w = nw[v];
+            bf.side[v] = (uint8_t)(1 - sd);
+            d01 += sd ? -w : w;
+        }
+        d01 = block_sum(d01, lds64);
+        if (threadIdx.x == 0 && d01 != 0) {
+            atomicAdd(&segw[2 * s], (unsigned long long)(-d01));
+            atomicAdd(&segw[2 * s + 1], (unsigned long long)d01);
+        }
+        return;
+    }
+    // balance: the chosen nodes of the over-weight side, sorted, then the prefix
+    int h = (md & kList1) ? 1 : 0;
+    if (threadIdx.x == 0) nkeys = 0;
+    __syncthreads();
+    if (rr[h] > 0) {
+        uint32_t mine = ebits & (h ? sbits : ~sbits);
+#pragma unroll
+        for (int j = 0; j < kSegItems; j++) {
+            if (!((mine >> j) & 1)) continue;
+            uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
+            if (sel_key(st.gmax[2 * s + h], g[j], lid, idbits) > thr[h]) continue;
+            keys[atomicAdd(&nkeys, 1)] = gain_order_key(g[j], (uint32_t)(a0 + (int32_t)lid));
+        }
+    }
+    __syncthreads();
+    int32_t cnt = nkeys;
+    int n2 = next_pow2(cnt > 0 ? cnt : 1);
+    for (int i = cnt + (int)threadIdx.x; i < n2; i += blockDim.x) keys[i] = kNoKey;
+    __syncthreads();
+    block_bitonic_sort(keys, n2);
+    bal_take_prefix(s, keys, cnt, bf, lds64);
+}
+
 // ---- moves ---------------------------------------------------------------------------------
 
 __global__ __launch_bounds__(kBlock) void k_flip(int32_t N, SelView sv, SelState st, uint8_t *side,
