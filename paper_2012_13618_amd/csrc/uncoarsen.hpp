@@ -546,10 +546,11 @@ __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, 
             st.rsel[c] = (int32_t)r;
             st.rem[c] = (int32_t)r;
             st.kpre[c] = 0;
-            st.kthr[c] = 0;
+            bool whole = r > 0 && r == st.tot[c];  // the whole list: no digit needed
+            st.kthr[c] = whole ? ~0ull : 0ull;
             st.kbits[c] = r > 0 ? sel_kbits(st.gmax[c], st.gmin[c], idbits) : 0;
-            st.done[c] = r == 0;
-            if (r == 0) atomicSub(&st.ctl[0], 1);
+            st.done[c] = r == 0 || whole;
+            if (r == 0 || whole) atomicSub(&st.ctl[0], 1);
         }
         __syncthreads();
     }
@@ -694,6 +695,11 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
             if (!sel_list(s, sd, g, sv.mode)) continue;
             int32_t c = 2 * s + sd;
             if (p > 0 && st.done[c]) continue;
+            if (p == 0) {  // a list taken whole needs no histogram
+                int64_t t = st.tot[c];
+                int64_t r = (sv.mode[s] & kMinPair) ? min(t, (int64_t)st.tot[c ^ 1]) : min(t, (int64_t)sv.m[s]);
+                if (r == t) continue;
+            }
             uint64_t k = sel_key(st.gmax[c], g, (uint32_t)(v - sv.nbase[s]), idbits);
             // pass 0 runs before the pick has fixed the key width: from the
             // extremes the node pass recorded
@@ -811,6 +817,10 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         }
         rr[sd] = (int32_t)r;
         if (r == 0) continue;
+        if (r == st.tot[c]) {  // the whole list: no pass needed
+            thr[sd] = ~0ull;
+            continue;
+        }
         int32_t gmax = st.gmax[c];
         int T = bitlen_u32((uint32_t)((int64_t)gmax - st.gmin[c])) + idbits;
         uint64_t pre = 0;
