@@ -173,6 +173,12 @@ def bench_batch(args):
     dev = [bp.DeviceHypergraph.from_host(h) for h in hs]
     outs = [torch.empty(max(h.num_nodes, 1), dtype=torch.int32, device="cuda") for h in hs]
     torch.cuda.synchronize()
+    sched = None
+    if args.autotune:
+        best, best_ms = bp.autotune_batch_device(dev, ks, es)
+        bp.schedule_set(best)
+        sched = best.as_dict()
+        log(f"autotuned schedule {sched} ({best_ms:.3f} ms in the tuner)")
     run = lambda: bp.partition_batch_device(dev, ks, es, parts_out=outs)
     for _ in range(args.warmup):
         run()
@@ -205,7 +211,8 @@ def bench_batch(args):
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
             "data": "synthetic",
             "config": {"workload": BATCH_DESC, "graphs": 256, "pins": pins, "parallelism": "1 GPU",
-                       "one_call_per_graph_ms": None if seq_ms is None else round(seq_ms, 3), "total_cut": sum(cuts)},
+                       "one_call_per_graph_ms": None if seq_ms is None else round(seq_ms, 3), "total_cut": sum(cuts),
+                       "schedule": sched if sched else bp.schedule_get().as_dict()},
             "roofline": roofline, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
@@ -276,6 +283,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="first run one plain device copy of this many MiB (a known-size kernel "
                          "for scaling hardware byte counters)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="batch: pick the launch schedule with the autotuner first")
     ap.add_argument("--no-compare", action="store_true",
                     help="batch: skip timing the graphs one call at a time")
     ap.add_argument("--requests", type=int, default=256, help="serve: requests in the stream")

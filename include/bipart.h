@@ -183,6 +183,45 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
                                     int32_t *const *d_part_out, int64_t *cut_out, bp_report *reports,
                                     void *stream);
 
+/* ---- launch schedule --------------------------------------------------------
+ *
+ * Knobs of how the work is laid out on the device.  They never change a
+ * result - every schedule gives the same partitions and cuts (tested) - only
+ * the time.  Process-wide; a call uses the schedule current when it starts.
+ */
+typedef struct {
+    int32_t incremental_min_pins;  /* levels with at least this many pins update balance-round gains
+                                      from the moves; INT32_MAX: always recompute (default 262144) */
+    int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes (capped
+                                      at 16384) select and move in one workgroup per segment;
+                                      0: never (default 16384) */
+    int32_t round_chunk_max;       /* most rounds issued between host checks, 1..64 (default 32) */
+    int32_t fused_pick_lists;      /* up to this many lists the digit picks run in the histogram
+                                      launch's last workgroup, above in per-segment ones,
+                                      0..4096 (default 8) */
+} bp_schedule;
+
+/* Fills *s with the defaults above. */
+void bp_schedule_default(bp_schedule *s);
+/* Makes *s the process-wide schedule (BP_ERR_INVALID_ARG if out of range). */
+bp_status bp_schedule_set(const bp_schedule *s);
+/* Copies the process-wide schedule into *s. */
+bp_status bp_schedule_get(bp_schedule *s);
+
+/*
+ * Autotuner for the batched form: partitions the batch (as
+ * bp_partition_batch_device) under each candidate schedule, trials times
+ * each (>= 1), checks that every candidate gives exactly the partitions and
+ * cuts of the current schedule (BP_ERR_DEVICE if not - never expected), and
+ * writes the fastest schedule to *best and its best time (ms) to *best_ms.
+ * The process-wide schedule is left as it was; pass *best to
+ * bp_schedule_set to use it.  d_scratch_parts: device int32 buffers, one per
+ * graph, for the candidate runs' outputs (caller-owned).
+ */
+bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const int32_t *k, const double *eps,
+                                   const bp_params *params, int32_t *const *d_scratch_parts, int32_t trials,
+                                   bp_schedule *best, double *best_ms, void *stream);
+
 /* ---- served form ----------------------------------------------------------
  *
  * A server owns a worker thread on one device.  Requests are submitted one

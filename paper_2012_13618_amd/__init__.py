@@ -31,7 +31,8 @@ EXPORTS = [
     "bp_profile_enable", "bp_profile_reset", "bp_profile_read", "bp_partition_batch",
     "bp_partition_batch_device", "bp_server_default_config", "bp_request_footprint",
     "bp_server_create", "bp_server_submit", "bp_server_wait", "bp_server_destroy",
-    "bp_profile_floor",
+    "bp_profile_floor", "bp_schedule_default", "bp_schedule_set", "bp_schedule_get",
+    "bp_autotune_batch_device",
 ]
 
 
@@ -76,6 +77,14 @@ class ReqStats(ctypes.Structure):
                 ("batch_size", ctypes.c_int32), ("footprint_bytes", ctypes.c_int64),
                 ("queue_ms", ctypes.c_double), ("run_ms", ctypes.c_double),
                 ("latency_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("incremental_min_pins", ctypes.c_int32), ("seg_select_max_nodes", ctypes.c_int32),
+                ("round_chunk_max", ctypes.c_int32), ("fused_pick_lists", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -129,6 +138,11 @@ def lib():
         L.bp_profile_reset.restype = None
         L.bp_profile_read.argtypes = [P, i32]
         L.bp_profile_floor.argtypes = [i32, P]
+        L.bp_schedule_default.argtypes = [P]
+        L.bp_schedule_default.restype = None
+        L.bp_schedule_set.argtypes = [P]
+        L.bp_schedule_get.argtypes = [P]
+        L.bp_autotune_batch_device.argtypes = [i32, P, P, P, P, P, i32, P, P, P]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is ctypes.c_int:
@@ -352,6 +366,40 @@ def partition_batch_device(dhs, ks, epss, prm: Params | None = None, parts_out=N
                                                 cuts.ctypes.data, reps, _stream()))
     return ([p[:d.num_nodes] for p, d in zip(parts_out, dhs)], [int(c) for c in cuts[:n]], st,
             [reps[i] for i in range(n)])
+
+
+def schedule_default() -> Schedule:
+    s = Schedule()
+    lib().bp_schedule_default(ctypes.byref(s))
+    return s
+
+
+def schedule_get() -> Schedule:
+    s = Schedule()
+    _check(lib().bp_schedule_get(ctypes.byref(s)))
+    return s
+
+
+def schedule_set(s: Schedule):
+    _check(lib().bp_schedule_set(ctypes.byref(s)))
+
+
+def autotune_batch_device(dhs, ks, epss, prm: Params | None = None, trials=1):
+    """Fastest launch schedule for this batch: returns (Schedule, best ms)."""
+    import torch
+    n = len(dhs)
+    hgs = (Hypergraph * max(n, 1))()
+    for i, d in enumerate(dhs):
+        hgs[i] = d.struct()
+    ks, epss = _batch_arrays(n, ks, epss)
+    scratch = [torch.empty(max(d.num_nodes, 1), dtype=torch.int32, device="cuda") for d in dhs]
+    outs = (ctypes.c_void_p * max(n, 1))(*[p.data_ptr() for p in scratch])
+    best = Schedule()
+    ms = ctypes.c_double(0)
+    _check(lib().bp_autotune_batch_device(n, hgs, ks.ctypes.data, epss.ctypes.data,
+                                          None if prm is None else ctypes.byref(prm), outs, trials,
+                                          ctypes.byref(best), ctypes.byref(ms), _stream()))
+    return best, float(ms.value)
 
 
 def compute_cut_device(dh: DeviceHypergraph, part, k):

@@ -5,6 +5,8 @@
 #include <cstring>
 #include <string>
 #include <vector>
+#include <chrono>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -20,9 +22,20 @@ static void check_lists(const Level &L)
         throw Error(BP_ERR_DEVICE, "internal: node schedule lists missing");
 }
 
-// Levels with at least this many pins update balance-round gains from the
-// moves instead of recomputing them.
-constexpr int32_t kIncrementalMinPins = 1 << 18;
+static std::mutex g_sched_mu;
+static Schedule g_sched;
+
+Schedule current_schedule()
+{
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    return g_sched;
+}
+
+static void set_schedule(const Schedule &s)
+{
+    std::lock_guard<std::mutex> g(g_sched_mu);
+    g_sched = s;
+}
 
 // ---- one coarsening step ------------------------------------------------------
 
@@ -369,7 +382,7 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
     int32_t nl = 2 * L.S;
     // picks: by the last workgroup (few lists), by the last workgroup of each
     // segment (many lists), or by a launch of their own (no nodes at all)
-    int fused = nl <= kFusedPickLists ? 1 : (L.N > 0 ? 2 : 0);
+    int fused = nl <= cx.sched.fused_pick_lists ? 1 : (L.N > 0 ? 2 : 0);
     SelView sv = sel_view(L, sg, gain);
     int64_t grid = std::max<int64_t>(1, ceil_div(L.N, kSelNodes));
     for (int p = 0; p < passes; p++) {
@@ -387,7 +400,7 @@ static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t
 // multi-workgroup passes and a flip launch.
 static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
-    if (L.maxseg_nodes <= kSegSelectMax) {
+    if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, kSegSelectMax)) {
         BalFinish bf{};
         bf.side = L.side;
         launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
@@ -449,7 +462,8 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, R
             return ran;
         }
         // the estimate decides the next chunk, growing at most twofold
-        chunk = estimate ? std::min({std::max(g[3], 1), 2 * chunk, 32}) : std::min(chunk * 2, 32);
+        int cap = cx.sched.round_chunk_max;
+        chunk = estimate ? std::min({std::max(g[3], 1), 2 * chunk, cap}) : std::min(chunk * 2, cap);
     }
 }
 
@@ -489,7 +503,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     Arena &ar = *cx.ar;
     // incremental gains pay off once a full recomputation is long against
     // the three short launches they take
-    bool incr = L.P >= kIncrementalMinPins;
+    bool incr = L.P >= cx.sched.incremental_min_pins;
     MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
     uint32_t *bits = nullptr;
     int64_t nbits = ceil_div(L.E, 32);
@@ -527,7 +541,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
                    ml.moved, ml.count, gc);
         }
-        if (L.maxseg_nodes <= kSegSelectMax) {
+        if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, kSegSelectMax)) {
             launch(lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
                    sg.st, id_bits(L), 1, (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc);
             return;
@@ -1485,6 +1499,121 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
     BP_HIP(hipStreamSynchronize(cx.lc.stream));
     fill_batch_reports(cx, res, tl, cut_out, reports);
     return batch_status(res);
+    BP_GUARD_END
+}
+
+static Schedule to_schedule(const bp_schedule *s)
+{
+    Schedule r;
+    r.incremental_min_pins = s->incremental_min_pins;
+    r.seg_select_max_nodes = s->seg_select_max_nodes;
+    r.round_chunk_max = s->round_chunk_max;
+    r.fused_pick_lists = s->fused_pick_lists;
+    return r;
+}
+
+static void from_schedule(const Schedule &r, bp_schedule *s)
+{
+    s->incremental_min_pins = r.incremental_min_pins;
+    s->seg_select_max_nodes = r.seg_select_max_nodes;
+    s->round_chunk_max = r.round_chunk_max;
+    s->fused_pick_lists = r.fused_pick_lists;
+}
+
+static bool schedule_ok(const bp_schedule *s)
+{
+    return s && s->incremental_min_pins >= 0 && s->seg_select_max_nodes >= 0 && s->round_chunk_max >= 1 &&
+           s->round_chunk_max <= 64 && s->fused_pick_lists >= 0 && s->fused_pick_lists <= 4096;
+}
+
+void bp_schedule_default(bp_schedule *s)
+{
+    if (s) from_schedule(Schedule{}, s);
+}
+
+bp_status bp_schedule_set(const bp_schedule *s)
+{
+    if (!schedule_ok(s)) return fail(BP_ERR_INVALID_ARG, "schedule out of range");
+    set_schedule(to_schedule(s));
+    return BP_OK;
+}
+
+bp_status bp_schedule_get(bp_schedule *s)
+{
+    if (!s) return fail(BP_ERR_INVALID_ARG, "NULL schedule");
+    from_schedule(current_schedule(), s);
+    return BP_OK;
+}
+
+bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const int32_t *k, const double *eps,
+                                   const bp_params *params, int32_t *const *d_scratch_parts, int32_t trials,
+                                   bp_schedule *best, double *best_ms, void *stream)
+{
+    bp_status st = check_batch_args(n, graphs, k, eps, d_scratch_parts, params);
+    if (st != BP_OK) return st;
+    if (trials < 1 || !best) return fail(BP_ERR_INVALID_ARG, "trials < 1 or NULL best");
+    for (int32_t g = 0; g < n; g++)
+        if ((st = check_device_hg(&graphs[g])) != BP_OK)
+            return fail(st, "graph " + std::to_string(g) + ": " + g_last_error);
+    BP_GUARD_BEGIN
+    std::vector<BatchItem> items(n);
+    std::vector<int32_t *> outs(n);
+    int64_t total_nodes = 0;
+    for (int32_t g = 0; g < n; g++) {
+        Input in = device_input(&graphs[g]);
+        items[g] = BatchItem{in.N, in.E, in.off, in.pins, in.nw, in.hw, k[g], eps[g]};
+        outs[g] = d_scratch_parts[g];
+        total_nodes += in.N;
+    }
+    // one run under a schedule: time and the results (cuts and all part ids)
+    auto run = [&](const Schedule &sc, std::vector<int64_t> &cuts, std::vector<int32_t> &parts) -> double {
+        CtxGuard gd((hipStream_t)stream, params);
+        Ctx &cx = gd.cx;
+        cx.sched = sc;
+        BP_HIP(hipStreamSynchronize(cx.lc.stream));
+        auto t0 = std::chrono::steady_clock::now();
+        int32_t tl = 0;
+        std::vector<BatchOut> res = partition_batch(cx, items, outs, &tl);
+        BP_HIP(hipStreamSynchronize(cx.lc.stream));
+        double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        cuts.resize(n);
+        for (int32_t g = 0; g < n; g++) cuts[g] = res[g].cut;
+        parts.resize((size_t)total_nodes);
+        int64_t o = 0;
+        for (int32_t g = 0; g < n; g++) {
+            if (items[g].N > 0)
+                BP_HIP(hipMemcpy(parts.data() + o, outs[g], sizeof(int32_t) * (size_t)items[g].N,
+                                 hipMemcpyDeviceToHost));
+            o += items[g].N;
+        }
+        return ms;
+    };
+    Schedule base = current_schedule();
+    std::vector<int64_t> ref_cuts, cuts;
+    std::vector<int32_t> ref_parts, parts;
+    run(base, ref_cuts, ref_parts);  // also warms the device memory pool
+    std::vector<Schedule> cand;
+    for (int32_t inc : {1 << 16, 1 << 18, 1 << 20, INT32_MAX})
+        for (int32_t seg : {0, 4096, 16384})
+            for (int32_t chunk : {16, 32})
+                cand.push_back(Schedule{inc, seg, chunk, base.fused_pick_lists});
+    double best_t = 1e300;
+    Schedule best_s = base;
+    for (const Schedule &sc : cand) {
+        double t = 1e300;
+        for (int32_t r = 0; r < trials; r++) {
+            t = std::min(t, run(sc, cuts, parts));
+            if (cuts != ref_cuts || parts != ref_parts)
+                throw Error(BP_ERR_DEVICE, "a launch schedule changed the results");
+        }
+        if (t < best_t) {
+            best_t = t;
+            best_s = sc;
+        }
+    }
+    from_schedule(best_s, best);
+    if (best_ms) *best_ms = best_t;
+    return BP_OK;
     BP_GUARD_END
 }
 

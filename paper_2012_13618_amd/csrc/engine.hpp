@@ -14,8 +14,19 @@ struct Input {
     const int32_t *off = nullptr, *pins = nullptr, *nw = nullptr, *hw = nullptr;  // device
 };
 
+// Launch schedule (results never depend on it): see bp_schedule.
+struct Schedule {
+    int32_t incremental_min_pins = 1 << 18;
+    int32_t seg_select_max_nodes = 1 << 14;
+    int32_t round_chunk_max = 32;
+    int32_t fused_pick_lists = 8;
+};
+
+Schedule current_schedule();  // the process-wide schedule (a copy, taken under a lock)
+
 struct Ctx {
     LaunchCtx lc;
+    Schedule sched = current_schedule();
     Arena *ar = nullptr;
     LevelInfo *info_h = nullptr;  // pinned host
     LevelInfo *info_d = nullptr;  // device

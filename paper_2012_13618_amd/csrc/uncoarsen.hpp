@@ -27,7 +27,6 @@ namespace bp {
 constexpr int kDigit = 12;
 constexpr int kBins = 1 << kDigit;        // 4096
 constexpr int kSelNodes = 1024;           // nodes per workgroup in histogram passes
-constexpr int kFusedPickLists = 8;        // above: separate pick launch, one workgroup per list
 
 __device__ __forceinline__ int bitlen_u32(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 

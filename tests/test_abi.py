@@ -91,3 +91,22 @@ def test_batch_host_validation_errors():
         [2, 2], [0.05, 0.05]))
     with pytest.raises(ValueError):
         bp.partition_batch([a, b], [2], [0.05, 0.05])
+
+
+def test_schedule_defaults_and_validation():
+    d = bp.schedule_default()
+    assert d.as_dict() == {"incremental_min_pins": 1 << 18, "seg_select_max_nodes": 1 << 14,
+                           "round_chunk_max": 32, "fused_pick_lists": 8}
+    old = bp.schedule_get()
+    try:
+        s = bp.schedule_default()
+        s.round_chunk_max = 8
+        bp.schedule_set(s)
+        assert bp.schedule_get().round_chunk_max == 8
+        for field, bad in [("round_chunk_max", 0), ("round_chunk_max", 65), ("fused_pick_lists", -1),
+                           ("incremental_min_pins", -5), ("seg_select_max_nodes", -1)]:
+            s = bp.schedule_default()
+            setattr(s, field, bad)
+            _expect(-1, lambda: bp.schedule_set(s))
+    finally:
+        bp.schedule_set(old)

@@ -154,3 +154,52 @@ def test_full_batch_256(bp):
         p1, c1, _, r1 = bp.partition_device(dev[i], ks[i], es[i])
         assert torch.equal(parts[i], p1), i
         assert cuts[i] == c1 and reps[i].max_part_weight == r1.max_part_weight, i
+
+
+def test_schedules_never_change_results(bp):
+    """Every launch schedule gives the same partitions and cuts."""
+    items = _mixed() + [(I.batch_member(3), 4, 0.05), (I.batch_member(10), 2, 0.05)]
+    hs = [h for h, _, _ in items]
+    ks = [k for _, k, _ in items]
+    es = [e for _, _, e in items]
+    dev = [_dev(bp, h) for h in hs]
+    ref_parts, ref_cuts, _, _ = bp.partition_batch_device(dev, ks, es)
+    ref_parts = [p.cpu().numpy() for p in ref_parts]
+    old = bp.schedule_get()
+    try:
+        for inc, seg, chunk, fused in [(0, 0, 1, 0), (1 << 30, 16384, 64, 4096), (1 << 16, 4096, 7, 2),
+                                       (2 ** 31 - 1, 100, 3, 64)]:
+            s = bp.schedule_default()
+            s.incremental_min_pins, s.seg_select_max_nodes, s.round_chunk_max, s.fused_pick_lists = \
+                inc, seg, chunk, fused
+            bp.schedule_set(s)
+            say("schedule", s.as_dict())
+            parts, cuts, _, _ = bp.partition_batch_device(dev, ks, es)
+            assert cuts == ref_cuts
+            for a, b in zip(parts, ref_parts):
+                assert np.array_equal(a.cpu().numpy(), b)
+            h = hs[-1]
+            p1, c1, _, _ = bp.partition_device(dev[-1], ks[-1], es[-1])
+            assert np.array_equal(p1.cpu().numpy(), ref_parts[-1]) and c1 == ref_cuts[-1]
+    finally:
+        bp.schedule_set(old)
+
+
+def test_autotune_returns_a_valid_schedule(bp):
+    hs = [I.batch_member(i) for i in range(6)]
+    dev = [_dev(bp, h) for h in hs]
+    ks = [h.meta["k"] for h in hs]
+    es = [h.meta["eps"] for h in hs]
+    best, ms = bp.autotune_batch_device(dev, ks, es)
+    say("autotune", best.as_dict(), ms)
+    assert ms > 0 and 1 <= best.round_chunk_max <= 64
+    old = bp.schedule_get()
+    try:
+        ref = bp.partition_batch_device(dev, ks, es)
+        bp.schedule_set(best)
+        got = bp.partition_batch_device(dev, ks, es)
+        assert got[1] == ref[1]
+        for a, b in zip(got[0], ref[0]):
+            assert np.array_equal(a.cpu().numpy(), b.cpu().numpy())
+    finally:
+        bp.schedule_set(old)
