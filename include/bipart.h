@@ -192,9 +192,9 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
 typedef struct {
     int32_t incremental_min_pins;  /* levels with at least this many pins update balance-round gains
                                       from the moves; INT32_MAX: always recompute (default 262144) */
-    int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes (capped
-                                      at 16384) select and move in one workgroup per segment;
-                                      0: never (default 16384) */
+    int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes select
+                                      and move in one workgroup per segment (capped at 16384 for
+                                      swaps, 32768 for balance); 0: never (default 32768) */
     int32_t round_chunk_max;       /* most rounds issued between host checks, 1..64 (default 32) */
     int32_t fused_pick_lists;      /* up to this many lists the digit picks run in the histogram
                                       launch's last workgroup, above in per-segment ones,

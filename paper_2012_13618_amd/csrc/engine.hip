@@ -400,11 +400,11 @@ static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t
 // multi-workgroup passes and a flip launch.
 static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
-    if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, kSegSelectMax)) {
+    if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, seg_select_max<0>())) {
         BalFinish bf{};
         bf.side = L.side;
-        launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-               sg.st, id_bits(L), 0, (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go);
+        launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
+               sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go);
         return;
     }
     run_select(cx, L, sg, gain, go);
@@ -541,9 +541,9 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
                    ml.moved, ml.count, gc);
         }
-        if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, kSegSelectMax)) {
-            launch(lc, "seg_select", 10.0 * L.N, k_seg_select, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-                   sg.st, id_bits(L), 1, (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc);
+        if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, seg_select_max<1>())) {
+            launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
+                   sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc);
             return;
         }
         run_select(cx, L, sg, gain, gc);
@@ -1594,7 +1594,7 @@ bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const
     run(base, ref_cuts, ref_parts);  // also warms the device memory pool
     std::vector<Schedule> cand;
     for (int32_t inc : {1 << 16, 1 << 18, 1 << 20, INT32_MAX})
-        for (int32_t seg : {0, 4096, 16384})
+        for (int32_t seg : {0, 4096, 16384, 32768})
             for (int32_t chunk : {16, 32})
                 cand.push_back(Schedule{inc, seg, chunk, base.fused_pick_lists});
     double best_t = 1e300;

@@ -760,8 +760,11 @@ __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const S
 // ---- small segments: the whole selection and the moves in one workgroup --------------------
 
 constexpr int kSegThreads = 1024;
-constexpr int kSegItems = 16;                           // nodes per thread, kept in registers
-constexpr int32_t kSegSelectMax = kSegThreads * kSegItems;  // largest segment taken this way
+// nodes per thread, kept in registers: the flipping kind holds both lists'
+// thresholds as well and fits half as many without spilling
+template <int KIND> constexpr int seg_items() { return KIND == 0 ? 16 : 32; }
+template <int KIND> constexpr int32_t seg_select_max() { return kSegThreads * seg_items<KIND>(); }
+constexpr int32_t kSegSelectMax = kSegThreads * 32;      // largest segment either kind takes
 constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
 
 // One workgroup per segment of at most kSegSelectMax nodes: each list's
@@ -771,11 +774,13 @@ constexpr int kSegKeys = 256;                           // balance candidates: c
 // (Algorithm 3 and the swap of Algorithm 5); kind 1 sorts the chosen nodes of
 // the over-weight side and takes the balance prefix (Algorithm 5).  The chosen
 // set is the one the multi-workgroup path chooses: the same keys, the same r.
+template <int KIND>
 __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
-                                                           int kind, const int32_t *nw,
+                                                           const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
                                                            const int32_t *go)
 {
+    constexpr int kSegItems = seg_items<KIND>();
     __shared__ uint32_t hist[kBins];
     __shared__ int64_t lds64[16];
     __shared__ int32_t sbin, sbefore, sin_;
@@ -869,7 +874,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         st.rsel[2 * s] = rr[0];
         st.rsel[2 * s + 1] = rr[1];
     }
-    if (kind == 0) {
+    if (KIND == 0) {
         // flip the chosen nodes of both lists
         int64_t d01 = 0;  // weight moving from side 0 to side 1
 #pragma unroll
