@@ -395,16 +395,25 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
 
 static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go);
 
+// Whether a level's selections run in one workgroup per segment (kind 0:
+// flips, kind 1: balance); that kernel computes its lists' sizes and gain
+// extremes itself, so the gain passes need not.
+static bool seg_path(const Ctx &cx, const Level &L, int kind)
+{
+    int32_t cap = kind == 0 ? seg_select_max<0>() : seg_select_max<1>();
+    return L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, cap);
+}
+
 // Selection and flip of the chosen nodes (Algorithm 3 rounds, Algorithm 5
 // swaps): one workgroup per segment when every segment is small, else the
 // multi-workgroup passes and a flip launch.
 static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
 {
-    if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, seg_select_max<0>())) {
+    if (seg_path(cx, L, 0)) {
         BalFinish bf{};
         bf.side = L.side;
         launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-               sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go);
+               sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go, (uint8_t *)nullptr);
         return;
     }
     run_select(cx, L, sg, gain, go);
@@ -477,7 +486,7 @@ static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *g
                (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
                (const int64_t *)sg.W, (const unsigned long long *)sg.w, sg.cnt1, ri, sg.mode, sg.gmask, sg.m,
                sg.st, sg.go);
-        run_gains(cx, L, sg, gain, true, gc);
+        run_gains(cx, L, sg, gain, !seg_path(cx, L, 0), gc);
         select_and_flip(cx, L, sg, gain, gc);
     });
 }
@@ -489,7 +498,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     for (int it = 0; it < cx.prm.refine_iters; it++) {
         launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
                sg.mode, sg.gmask, sg.done, sg.st, sg.go);
-        run_gains(cx, L, sg, gain, true, nullptr);
+        run_gains(cx, L, sg, gain, !seg_path(cx, L, 0), nullptr);
         select_and_flip(cx, L, sg, gain, nullptr);
     }
     if (cx.prm.refine_iters == 0)
@@ -526,8 +535,9 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
                (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
                sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go, ri);
+        bool seg = seg_path(cx, L, 1);
         if (ri == 0 || !incr) {
-            run_gains(cx, L, sg, gain, true, gc);
+            run_gains(cx, L, sg, gain, !seg, gc);
         } else {
             launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
                    (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
@@ -535,15 +545,16 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
             launch(lc, "gain_update", 4.0 * nbits, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
                    (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
-                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc);
-            launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
+                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count);
+            if (!seg)
+                launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
                    ml.moved, ml.count, gc);
         }
-        if (L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, seg_select_max<1>())) {
+        if (seg) {
             launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-                   sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc);
+                   sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc, ml.moved);
             return;
         }
         run_select(cx, L, sg, gain, gc);

@@ -193,12 +193,14 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                                                         const uint8_t *side, const uint8_t *moved, int2 *cc,
                                                         int32_t *gain, const int32_t *bigslot,
                                                         const int32_t *lnbig, const int32_t *ncount,
-                                                        const int32_t *go)
+                                                        const int32_t *go, int32_t *logcount)
 {
     __shared__ int32_t slot[kUpdSlots];
     __shared__ int32_t queue[kUpdQueue];
     __shared__ int32_t qs, qb;
     if (go && *go == 0) return;
+    // the move log was read by the previous launch: empty it for this round's moves
+    if (logcount && blockIdx.x == 0 && threadIdx.x == 0) *logcount = 0;
     int32_t nb = min(ncount[1], kUpdSlots);
     for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
     if (threadIdx.x == 0) {
@@ -778,7 +780,7 @@ template <int KIND>
 __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
                                                            const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
-                                                           const int32_t *go)
+                                                           const int32_t *go, uint8_t *moved)
 {
     constexpr int kSegItems = seg_items<KIND>();
     __shared__ uint32_t hist[kBins];
@@ -788,11 +790,17 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
     __shared__ int32_t nkeys;
     if (go && *go == 0) return;
     int32_t s = blockIdx.x;
+    int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
+    // the previous round's move marks, in every segment (the gain update has used them)
+    if (moved)
+        for (int32_t i = threadIdx.x; i < n; i += kSegThreads)
+            if (moved[a0 + i]) moved[a0 + i] = 0;
     uint8_t md = sv.mode[s];
     if (!md) return;
-    int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
     int32_t g[kSegItems];
     uint32_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
+    // per list: size and gain extremes, from the gains just loaded
+    int32_t lc[2] = {0, 0}, lmax[2] = {INT32_MIN, INT32_MIN}, lmin[2] = {INT32_MAX, INT32_MAX};
 #pragma unroll
     for (int j = 0; j < kSegItems; j++) {
         int32_t i = j * kSegThreads + (int32_t)threadIdx.x;
@@ -801,8 +809,44 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
             int sd = sv.side[a0 + i];
             g[j] = sv.gain[a0 + i];
             sbits |= (uint32_t)sd << j;
-            ebits |= (sel_list(s, sd, g[j], sv.mode) ? 1u : 0u) << j;
+            if (sel_list(s, sd, g[j], sv.mode)) {
+                ebits |= 1u << j;
+                lc[sd]++;
+                lmax[sd] = max(lmax[sd], g[j]);
+                lmin[sd] = min(lmin[sd], g[j]);
+            }
         }
+    }
+    {
+        __shared__ int32_t red[kSegThreads / 64][6];
+        int32_t x[6] = {lc[0], lc[1], lmax[0], lmax[1], lmin[0], lmin[1]};
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            x[0] += __shfl_xor(x[0], o, 64);
+            x[1] += __shfl_xor(x[1], o, 64);
+            x[2] = max(x[2], __shfl_xor(x[2], o, 64));
+            x[3] = max(x[3], __shfl_xor(x[3], o, 64));
+            x[4] = min(x[4], __shfl_xor(x[4], o, 64));
+            x[5] = min(x[5], __shfl_xor(x[5], o, 64));
+        }
+        if ((threadIdx.x & 63) == 0)
+            for (int q = 0; q < 6; q++) red[threadIdx.x >> 6][q] = x[q];
+        __syncthreads();
+        lc[0] = red[0][0];
+        lc[1] = red[0][1];
+        lmax[0] = red[0][2];
+        lmax[1] = red[0][3];
+        lmin[0] = red[0][4];
+        lmin[1] = red[0][5];
+        for (int w = 1; w < kSegThreads / 64; w++) {
+            lc[0] += red[w][0];
+            lc[1] += red[w][1];
+            lmax[0] = max(lmax[0], red[w][2]);
+            lmax[1] = max(lmax[1], red[w][3]);
+            lmin[0] = min(lmin[0], red[w][4]);
+            lmin[1] = min(lmin[1], red[w][5]);
+        }
+        __syncthreads();
     }
     uint64_t thr[2] = {0, 0};
     int32_t rr[2] = {0, 0};
@@ -811,9 +855,9 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         int32_t c = 2 * s + sd;
         int64_t r = 0;
         if ((md >> sd) & 1) {
-            int64_t t = st.tot[c];
+            int64_t t = lc[sd];
             if (md & kMinPair) {
-                int64_t o = st.tot[c ^ 1];
+                int64_t o = lc[sd ^ 1];
                 r = t < o ? t : o;
             } else {
                 r = t < (int64_t)sv.m[s] ? t : (int64_t)sv.m[s];
@@ -821,12 +865,12 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         }
         rr[sd] = (int32_t)r;
         if (r == 0) continue;
-        if (r == st.tot[c]) {  // the whole list: no pass needed
+        if (r == lc[sd]) {  // the whole list: no pass needed
             thr[sd] = ~0ull;
             continue;
         }
-        int32_t gmax = st.gmax[c];
-        int T = bitlen_u32((uint32_t)((int64_t)gmax - st.gmin[c])) + idbits;
+        int32_t gmax = lmax[sd];
+        int T = bitlen_u32((uint32_t)((int64_t)gmax - lmin[sd])) + idbits;
         uint64_t pre = 0;
         int32_t rem = (int32_t)r;
         for (int p = 0;; p++) {
@@ -883,7 +927,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
             int sd = (sbits >> j) & 1;
             if (rr[sd] == 0) continue;
             uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
-            if (sel_key(st.gmax[2 * s + sd], g[j], lid, idbits) > thr[sd]) continue;
+            if (sel_key(lmax[sd], g[j], lid, idbits) > thr[sd]) continue;
             int32_t v = a0 + (int32_t)lid;
             int64_t w = nw[v];
             bf.side[v] = (uint8_t)(1 - sd);
@@ -906,7 +950,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         for (int j = 0; j < kSegItems; j++) {
             if (!((mine >> j) & 1)) continue;
             uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
-            if (sel_key(st.gmax[2 * s + h], g[j], lid, idbits) > thr[h]) continue;
+            if (sel_key(lmax[h], g[j], lid, idbits) > thr[h]) continue;
             keys[atomicAdd(&nkeys, 1)] = gain_order_key(g[j], (uint32_t)(a0 + (int32_t)lid));
         }
     }
