@@ -412,8 +412,14 @@ static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, co
     if (seg_path(cx, L, 0)) {
         BalFinish bf{};
         bf.side = L.side;
-        launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-               sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, go, (uint8_t *)nullptr);
+        if (L.maxseg_nodes <= seg_select_max<0, kSegThreadsSmall>())
+            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
+                   L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
+                   bf, go, (uint8_t *)nullptr);
+        else
+            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0>, L.S, kSegThreads, 0, L.S,
+                   sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
+                   bf, go, (uint8_t *)nullptr);
         return;
     }
     run_select(cx, L, sg, gain, go);
@@ -553,8 +559,14 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    ml.moved, ml.count, gc);
         }
         if (seg) {
-            launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1>, L.S, kSegThreads, 0, L.S, sel_view(L, sg, gain),
-                   sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf, gc, ml.moved);
+            if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsSmall>())
+                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
+                       L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
+                       (unsigned long long *)sg.w, bf, gc, ml.moved);
+            else
+                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1>, L.S, kSegThreads, 0, L.S,
+                       sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
+                       (unsigned long long *)sg.w, bf, gc, ml.moved);
             return;
         }
         run_select(cx, L, sg, gain, gc);
@@ -581,9 +593,19 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     uint8_t *sact_next = ar.get<uint8_t>(L0.S);
     int32_t active = active0;
     int32_t l = 0;
+    auto trace_ms = [&]() -> double {
+        // tracing only: wall time with the stream drained
+        BP_HIP(hipStreamSynchronize(lc.stream));
+        return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch())
+            .count();
+    };
     while (active > 0) {
         Level c;
+        double t0 = trace_on() ? trace_ms() : 0.0;
         coarsen_level(cx, lv[l], sg, sact, sact_next, l, c);
+        if (trace_on())
+            fprintf(stderr, "[bp] coarsen %d -> %d: N=%d P=%d  %.3f ms\n", l, l + 1, lv[l].N, lv[l].P,
+                    trace_ms() - t0);
         lv.push_back(c);
         int32_t now = cx.info_h->active;
         stops.push_back(active - now);
@@ -636,11 +658,12 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
         launch(lc, "side_weights", 5.0 * L.N, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
                (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
                (unsigned long long *)sg.w);
+        double t0 = trace_on() ? trace_ms() : 0.0;
         int64_t ir = stops[j] > 0 ? initial_rounds(cx, L, sg, j, gain) : 0;
         int64_t br = refine_level(cx, L, sg, j, gain);
         if (trace_on())
-            fprintf(stderr, "[bp] level %d: S=%d N=%d E=%d P=%d initial_rounds=%lld balance_rounds=%lld\n", j,
-                    L.S, L.N, L.E, L.P, (long long)ir, (long long)br);
+            fprintf(stderr, "[bp] level %d: S=%d N=%d E=%d P=%d initial_rounds=%lld balance_rounds=%lld  %.3f ms\n",
+                    j, L.S, L.N, L.E, L.P, (long long)ir, (long long)br, trace_ms() - t0);
     }
     L0.side = lv[0].side;
 }

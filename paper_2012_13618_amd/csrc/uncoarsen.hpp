@@ -764,8 +764,9 @@ __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const S
 constexpr int kSegThreads = 1024;
 // nodes per thread, kept in registers: the flipping kind holds both lists'
 // thresholds as well and fits half as many without spilling
-template <int KIND> constexpr int seg_items() { return KIND == 0 ? 16 : 32; }
-template <int KIND> constexpr int32_t seg_select_max() { return kSegThreads * seg_items<KIND>(); }
+template <int KIND, int TH> constexpr int seg_items() { return KIND == 0 ? 16 : 32; }
+template <int KIND, int TH = kSegThreads> constexpr int32_t seg_select_max() { return TH * seg_items<KIND, TH>(); }
+constexpr int kSegThreadsSmall = 256;  // segments this many times smaller use a quarter of the threads
 constexpr int32_t kSegSelectMax = kSegThreads * 32;      // largest segment either kind takes
 constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
 
@@ -776,13 +777,13 @@ constexpr int kSegKeys = 256;                           // balance candidates: c
 // (Algorithm 3 and the swap of Algorithm 5); kind 1 sorts the chosen nodes of
 // the over-weight side and takes the balance prefix (Algorithm 5).  The chosen
 // set is the one the multi-workgroup path chooses: the same keys, the same r.
-template <int KIND>
-__global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
+template <int KIND, int TH = kSegThreads>
+__global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
                                                            const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
                                                            const int32_t *go, uint8_t *moved)
 {
-    constexpr int kSegItems = seg_items<KIND>();
+    constexpr int kSegItems = seg_items<KIND, TH>();
     __shared__ uint32_t hist[kBins];
     __shared__ int64_t lds64[16];
     __shared__ int32_t sbin, sbefore, sin_;
@@ -793,7 +794,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
     int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
     // the previous round's move marks, in every segment (the gain update has used them)
     if (moved)
-        for (int32_t i = threadIdx.x; i < n; i += kSegThreads)
+        for (int32_t i = threadIdx.x; i < n; i += TH)
             if (moved[a0 + i]) moved[a0 + i] = 0;
     uint8_t md = sv.mode[s];
     if (!md) return;
@@ -803,7 +804,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
     int32_t lc[2] = {0, 0}, lmax[2] = {INT32_MIN, INT32_MIN}, lmin[2] = {INT32_MAX, INT32_MAX};
 #pragma unroll
     for (int j = 0; j < kSegItems; j++) {
-        int32_t i = j * kSegThreads + (int32_t)threadIdx.x;
+        int32_t i = j * TH + (int32_t)threadIdx.x;
         g[j] = 0;
         if (i < n) {
             int sd = sv.side[a0 + i];
@@ -818,7 +819,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         }
     }
     {
-        __shared__ int32_t red[kSegThreads / 64][6];
+        __shared__ int32_t red[TH / 64][6];
         int32_t x[6] = {lc[0], lc[1], lmax[0], lmax[1], lmin[0], lmin[1]};
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) {
@@ -838,7 +839,8 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
         lmax[1] = red[0][3];
         lmin[0] = red[0][4];
         lmin[1] = red[0][5];
-        for (int w = 1; w < kSegThreads / 64; w++) {
+#pragma unroll 1
+        for (int w = 1; w < TH / 64; w++) {
             lc[0] += red[w][0];
             lc[1] += red[w][1];
             lmax[0] = max(lmax[0], red[w][2]);
@@ -850,7 +852,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
     }
     uint64_t thr[2] = {0, 0};
     int32_t rr[2] = {0, 0};
-    int per = kBins / kSegThreads;
+    int per = kBins / TH;
     for (int sd = 0; sd < 2; sd++) {
         int32_t c = 2 * s + sd;
         int64_t r = 0;
@@ -881,7 +883,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
 #pragma unroll
             for (int j = 0; j < kSegItems; j++) {
                 if (!((mine >> j) & 1)) continue;
-                uint64_t k = sel_key(gmax, g[j], (uint32_t)(j * kSegThreads + threadIdx.x), idbits);
+                uint64_t k = sel_key(gmax, g[j], (uint32_t)(j * TH + threadIdx.x), idbits);
                 if (p > 0 && ((k ^ pre) >> hi) != 0) continue;
                 int dig = hi > 0 ? (int)((k >> lo) & ((1ull << (hi - lo)) - 1ull)) : 0;
                 atomicAdd(&hist[dig], 1u);
@@ -926,7 +928,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
             if (!((ebits >> j) & 1)) continue;
             int sd = (sbits >> j) & 1;
             if (rr[sd] == 0) continue;
-            uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
+            uint32_t lid = (uint32_t)(j * TH + threadIdx.x);
             if (sel_key(lmax[sd], g[j], lid, idbits) > thr[sd]) continue;
             int32_t v = a0 + (int32_t)lid;
             int64_t w = nw[v];
@@ -949,7 +951,7 @@ __global__ __launch_bounds__(kSegThreads) void k_seg_select(int32_t S, SelView s
 #pragma unroll
         for (int j = 0; j < kSegItems; j++) {
             if (!((mine >> j) & 1)) continue;
-            uint32_t lid = (uint32_t)(j * kSegThreads + threadIdx.x);
+            uint32_t lid = (uint32_t)(j * TH + threadIdx.x);
             if (sel_key(lmax[h], g[j], lid, idbits) > thr[h]) continue;
             keys[atomicAdd(&nkeys, 1)] = gain_order_key(g[j], (uint32_t)(a0 + (int32_t)lid));
         }
