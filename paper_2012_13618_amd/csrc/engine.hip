@@ -514,7 +514,9 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // the gains from the hyperedges of the nodes the previous round moved
     fill(lc, sg.go, 8, 0);
     fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
-    int32_t cap = sg.cand_stride <= 4096 ? sg.cand_stride : 0;
+    // LDS keys of the balance finish (32 KiB at most): room for a sorted
+    // copy behind the candidates when the lists are short
+    int32_t cap = sg.cand_stride <= 2048 ? 2 * sg.cand_stride : (sg.cand_stride <= 4096 ? sg.cand_stride : 0);
     Arena &ar = *cx.ar;
     // incremental gains pay off once a full recomputation is long against
     // the three short launches they take

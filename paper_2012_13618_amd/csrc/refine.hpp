@@ -175,8 +175,90 @@ __device__ void bal_take_prefix(int32_t s, const uint64_t *a, int32_t cnt, const
     }
 }
 
+// log_moves by one wavefront.
+__device__ void log_moves_wave(int32_t p, const uint64_t *a, const MoveLog &ml)
+{
+    int lane = threadIdx.x & 63;
+    for (int32_t base = 0; base < p; base += 64) {
+        int32_t i = base + lane;
+        int32_t v = 0, b = 0, c = 0;
+        if (i < p) {
+            v = (int32_t)(uint32_t)(a[i] & 0xffffffffu);
+            b = ml.noff[v];
+            c = (int32_t)ceil_div(ml.noff[v + 1] - b, kLogChunk);
+            ml.moved[v] = 1;
+        }
+        int32_t incl = wave_incl_scan(c);
+        int32_t tot = __shfl(incl, 63, 64);
+        int32_t o = 0;
+        if (lane == 0 && tot) o = atomicAdd(&ml.count[0], tot);
+        o = __shfl(o, 0, 64) + incl - c;
+        for (int32_t j = 0; j < c; j++) {
+            ml.cnode[o + j] = v;
+            ml.cbeg[o + j] = b + j * kLogChunk;
+        }
+    }
+}
+
+// bal_take_prefix by one wavefront (no workgroup barriers).  Node weights
+// are non-negative, so the prefix weights ascend: the shortest prefix
+// reaching the excess ends at the first chunk position that reaches it, and
+// the longest prefix within the room is min(that length, the number of
+// positions whose prefix weight fits).
+__device__ void bal_take_prefix_wave(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf)
+{
+    int lane = threadIdx.x & 63;
+    int h = (bf.mode[s] & kList1) ? 1 : 0;
+    int64_t nd = bf.need[s], rm = bf.room[s];
+    int32_t p1 = cnt, fit = 0;
+    int64_t carry = 0;
+    for (int32_t base = 0; base < cnt; base += 64) {
+        int32_t i = base + lane;
+        int64_t w = i < cnt ? (int64_t)bf.nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
+        int64_t incl = wave_incl_scan(w) + carry;
+        unsigned long long hit = __ballot(i < cnt && incl >= nd);
+        fit += __popcll(__ballot(i < cnt && incl <= rm));
+        if (hit) {
+            p1 = base + __ffsll((long long)hit);
+            break;
+        }
+        carry = __shfl(incl, 63, 64);
+    }
+    int32_t p = fit < p1 ? fit : p1;
+    int64_t moved = 0;
+    for (int32_t i = lane; i < p; i += 64) {
+        uint32_t v = (uint32_t)(a[i] & 0xffffffffu);
+        bf.side[v] = (uint8_t)(1 - h);
+        moved += bf.nw[v];
+    }
+    moved = wave_sum(moved);
+    if (bf.ml.cnode) log_moves_wave(p, a, bf.ml);
+    if (lane == 0) {
+        if (p == 0) {
+            bf.stuck[s] = 1;
+            bf.done[s] = 1;
+        } else {
+            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
+            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
+            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            bf.bal_moved[2 * s] = mw;
+            bf.bal_moved[2 * s + 1] = mr;
+            int64_t rest = nd - moved;
+            if (rest > 0) {
+                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
+                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
+            }
+        }
+    }
+}
+
+constexpr int32_t kRankSortMax = 1024;  // candidates ordered by counting up to this many
+
 // One workgroup per balancing segment: sort its gathered candidates, then
-// the prefix step.
+// the prefix step.  The launch reserves lds_cap keys of LDS (lds_cap may be
+// 0): short lists are ordered by counting from one LDS copy into a second
+// one behind it and finished by one wavefront, longer ones sorted by a
+// bitonic network in LDS, or in place when they do not fit.
 __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *ccount, uint64_t *cand,
                                                      int32_t stride, int32_t lds_cap, BalFinish bf)
 {
@@ -185,11 +267,18 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
     int32_t s = blockIdx.x;
     if (!bf.mode[s]) return;
     int32_t cnt = ccount[s];
+    const uint64_t *src = cand + (int64_t)s * stride;
+    if (cnt <= kRankSortMax && 2 * cnt <= lds_cap) {
+        for (int i = threadIdx.x; i < cnt; i += blockDim.x) keys_lds[i] = src[i];
+        __syncthreads();
+        block_rank_sort(keys_lds, keys_lds + cnt, cnt);
+        if (threadIdx.x < 64) bal_take_prefix_wave(s, keys_lds + cnt, cnt, bf);
+        return;
+    }
     int n2 = next_pow2(cnt > 0 ? cnt : 1);
-    // sort in LDS when the launch reserved room for it, else in place
     uint64_t *a = n2 <= lds_cap ? keys_lds : cand + (int64_t)s * stride;
     for (int i = threadIdx.x; i < n2; i += blockDim.x)
-        a[i] = i < cnt ? cand[(int64_t)s * stride + i] : kNoKey;
+        a[i] = i < cnt ? src[i] : kNoKey;
     __syncthreads();
     block_bitonic_sort(a, n2);
     bal_take_prefix(s, a, cnt, bf, lds64);

@@ -80,6 +80,20 @@ template <typename K> __device__ void block_bitonic_sort(K *a, int n)
     }
 }
 
+// Ascending order of cnt distinct keys by counting: key i goes to out[rank],
+// rank = the number of smaller keys.  One barrier instead of a bitonic
+// network's log^2 ones; O(cnt^2 / threads) comparisons, for short lists.
+template <typename K> __device__ void block_rank_sort(const K *in, K *out, int cnt)
+{
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
+        K x = in[i];
+        int r = 0;
+        for (int j = 0; j < cnt; j++) r += in[j] < x;
+        out[r] = x;
+    }
+    __syncthreads();
+}
+
 // Same, but each wavefront sorts its own n-key slice (n a power of two); the
 // loop shape is identical for every wave so a workgroup barrier can be used.
 template <typename K> __device__ void wave_bitonic_sort(K *a, int n)

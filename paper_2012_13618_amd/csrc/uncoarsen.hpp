@@ -787,7 +787,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     __shared__ uint32_t hist[kBins];
     __shared__ int64_t lds64[16];
     __shared__ int32_t sbin, sbefore, sin_;
-    __shared__ uint64_t keys[kSegKeys];
+    __shared__ uint64_t keys[kSegKeys], sorted[KIND == 1 ? kSegKeys : 1];
     __shared__ int32_t nkeys;
     if (go && *go == 0) return;
     int32_t s = blockIdx.x;
@@ -958,11 +958,8 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     }
     __syncthreads();
     int32_t cnt = nkeys;
-    int n2 = next_pow2(cnt > 0 ? cnt : 1);
-    for (int i = cnt + (int)threadIdx.x; i < n2; i += blockDim.x) keys[i] = kNoKey;
-    __syncthreads();
-    block_bitonic_sort(keys, n2);
-    bal_take_prefix(s, keys, cnt, bf, lds64);
+    block_rank_sort(keys, sorted, cnt);
+    if (threadIdx.x < 64) bal_take_prefix_wave(s, sorted, cnt, bf);
 }
 
 // ---- moves ---------------------------------------------------------------------------------
