@@ -199,6 +199,9 @@ typedef struct {
     int32_t fused_pick_lists;      /* up to this many lists the digit picks run in the histogram
                                       launch's last workgroup, above in per-segment ones,
                                       0..4096 (default 8) */
+    int32_t fuse_max_pins;         /* segments of at most 8192 nodes and this many pins run their
+                                      whole balance step in one workgroup, with no launch per
+                                      round; 0: never (default 131072) */
 } bp_schedule;
 
 /* Fills *s with the defaults above. */

@@ -500,13 +500,16 @@ __global__ void k_level_fixup(int32_t S, int32_t N, int32_t E, const int32_t *nb
     c_hbase[S] = Ec;
     for (int32_t s = S - 1; s >= 0; s--) c_hbase[s] = hbase[s] == hbase[s + 1] ? c_hbase[s + 1] : hb_tmp[s];
     c_nbase[S] = Nc;
-    int32_t active = 0, maxn = 0;
+    int32_t active = 0, maxn = 0, maxp = 0, maxe = 0;
     for (int32_t s = 0; s < S; s++) {
         c_nbase[s] = nbase[s] < N ? cid[nbase[s]] : Nc;
     }
     for (int32_t s = 0; s < S; s++) {
         int32_t ns = c_nbase[s + 1] - c_nbase[s], es = c_hbase[s + 1] - c_hbase[s];
+        int32_t ps = c_off[c_hbase[s + 1]] - c_off[c_hbase[s]];
         if (ns > maxn) maxn = ns;
+        if (ps > maxp) maxp = ps;
+        if (es > maxe) maxe = es;
         bool go = false;
         if (sact[s]) {
             coarsest[s] = level_next;
@@ -524,6 +527,8 @@ __global__ void k_level_fixup(int32_t S, int32_t N, int32_t E, const int32_t *nb
     info->unresolved = counters[0];
     info->active = active;
     info->maxseg_nodes = maxn;
+    info->maxseg_pins = maxp;
+    info->maxseg_hedges = maxe;
 }
 
 }  // namespace bp

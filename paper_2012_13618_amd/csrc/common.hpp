@@ -401,6 +401,40 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds /* >= 16 */, T *total)
     return before + inc - v;
 }
 
+// Slot of each taking lane in an LDS list with counter *ctr: one atomic per
+// wavefront; -1 for lanes not taking.  Lanes that do not call take nothing.
+__device__ __forceinline__ int32_t lds_wave_slot(bool take, int32_t *ctr)
+{
+    unsigned long long m = __ballot(take);
+    if (!m) return -1;
+    int lane = threadIdx.x & 63, leader = __ffsll((long long)m) - 1;
+    int32_t base = 0;
+    if (lane == leader) base = atomicAdd(ctr, __popcll(m));
+    base = __builtin_amdgcn_readlane(base, leader);
+    return take ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
+// Histogram count of bin dig for every lane with act set: lanes sharing the
+// bin of the first such lane (twice over) add with one atomic, the rest
+// alone.  Selection keys crowd into few bins, where per-lane atomics on one
+// LDS address serialize.  Lanes that do not call add nothing.
+__device__ __forceinline__ void lds_hist_add(bool act, uint32_t dig, uint32_t *hist)
+{
+    int lane = threadIdx.x & 63;
+    unsigned long long am = __ballot(act);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (!am) return;
+        int leader = __ffsll((long long)am) - 1;
+        uint32_t ld = (uint32_t)__builtin_amdgcn_readlane((int)dig, leader);
+        unsigned long long eq = __ballot(act && dig == ld);
+        if (lane == leader) atomicAdd(&hist[ld], (uint32_t)__popcll(eq));
+        act = act && dig != ld;
+        am &= ~eq;
+    }
+    if (act) atomicAdd(&hist[dig], 1u);
+}
+
 // Appends id to list for every active lane with take set, using one atomic
 // per wavefront.  Call from all active lanes (the ballot spans them).
 __device__ __forceinline__ void wave_append(bool take, int32_t id, int32_t *list, int32_t *counter)

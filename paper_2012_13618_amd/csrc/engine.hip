@@ -236,6 +236,8 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     c.nbig = inf.nbig;
     c.nhuge = inf.nhuge;
     c.maxseg_nodes = inf.maxseg_nodes;
+    c.maxseg_pins = inf.maxseg_pins;
+    c.maxseg_hedges = inf.maxseg_hedges;
     std::swap(sact, sact_next);
     build_incidence(cx, c);
 }
@@ -514,6 +516,20 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // the gains from the hyperedges of the nodes the previous round moved
     fill(lc, sg.go, 8, 0);
     fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
+    // small segments: the whole balance step in one workgroup each; when every
+    // segment is small that is all, else the rounds below run the others
+    if (L.maxseg_nodes <= kFuseNodes && cx.sched.fuse_max_pins > 0) {
+        FuseArgs fa{L.off, L.pins, L.hw, L.noff, L.inc, L.nw, L.nbase, L.hbase, L.side, sg.max0, sg.max1,
+                    (unsigned long long *)sg.w, sg.done, sg.stuck, sg.go + 2, cx.sched.fuse_max_pins};
+        launch(lc, "seg_balance", 8.0 * L.P, k_seg_balance, L.S, kFuseThreads, 0, L.S, fa);
+        if (L.maxseg_pins <= cx.sched.fuse_max_pins && L.maxseg_hedges <= kFuseHedges) {
+            if (!trace_on()) return 0;
+            int32_t r = 0;
+            BP_HIP(hipMemcpyAsync(&r, sg.go + 2, sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
+            lc.sync();
+            return r;
+        }
+    }
     // LDS keys of the balance finish (32 KiB at most): room for a sorted
     // copy behind the candidates when the lists are short
     int32_t cap = sg.cand_stride <= 2048 ? 2 * sg.cand_stride : (sg.cand_stride <= 4096 ? sg.cand_stride : 0);
@@ -691,7 +707,8 @@ static void seg_setup(Ctx &cx, TreeLevel &t, const int32_t *k0_fixed = nullptr)
     launch(lc, "seg_setup", 0.0, k_seg_setup, ceil_div(L.S, kBlock), kBlock, 0, L.S,
            (const int32_t *)t.ksub, k0_fixed, (const int64_t *)t.sg.W, (const uint64_t *)t.F,
            (const int32_t *)L.nbase,
-           (const int32_t *)L.hbase, cx.prm.max_levels, cx.prm.min_coarse_nodes, t.sg.k0, t.sg.k1,
+           (const int32_t *)L.hbase, (const int32_t *)L.off, cx.prm.max_levels, cx.prm.min_coarse_nodes,
+           t.sg.k0, t.sg.k1,
            t.sg.max0, t.sg.max1, t.sg.active, t.sg.coarsest, t.sg.stuck, cx.info_d);
 }
 
@@ -812,6 +829,8 @@ static void prepare_tree_level(Ctx &cx, TreeLevel &t)
     t.L.nbig = inf.nbig;
     t.L.nhuge = inf.nhuge;
     t.L.maxseg_nodes = inf.maxseg_nodes;
+    t.L.maxseg_pins = inf.maxseg_pins;
+    t.L.maxseg_hedges = inf.maxseg_hedges;
     t.active0 = inf.active;
 }
 
@@ -1545,6 +1564,7 @@ static Schedule to_schedule(const bp_schedule *s)
     r.seg_select_max_nodes = s->seg_select_max_nodes;
     r.round_chunk_max = s->round_chunk_max;
     r.fused_pick_lists = s->fused_pick_lists;
+    r.fuse_max_pins = s->fuse_max_pins;
     return r;
 }
 
@@ -1554,12 +1574,14 @@ static void from_schedule(const Schedule &r, bp_schedule *s)
     s->seg_select_max_nodes = r.seg_select_max_nodes;
     s->round_chunk_max = r.round_chunk_max;
     s->fused_pick_lists = r.fused_pick_lists;
+    s->fuse_max_pins = r.fuse_max_pins;
 }
 
 static bool schedule_ok(const bp_schedule *s)
 {
     return s && s->incremental_min_pins >= 0 && s->seg_select_max_nodes >= 0 && s->round_chunk_max >= 1 &&
-           s->round_chunk_max <= 64 && s->fused_pick_lists >= 0 && s->fused_pick_lists <= 4096;
+           s->round_chunk_max <= 64 && s->fused_pick_lists >= 0 && s->fused_pick_lists <= 4096 &&
+           s->fuse_max_pins >= 0;
 }
 
 void bp_schedule_default(bp_schedule *s)
@@ -1632,7 +1654,7 @@ bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const
     for (int32_t inc : {1 << 16, 1 << 18, 1 << 20, INT32_MAX})
         for (int32_t seg : {0, 4096, 16384, 32768})
             for (int32_t chunk : {16, 32})
-                cand.push_back(Schedule{inc, seg, chunk, base.fused_pick_lists});
+                cand.push_back(Schedule{inc, seg, chunk, base.fused_pick_lists, base.fuse_max_pins});
     double best_t = 1e300;
     Schedule best_s = base;
     for (const Schedule &sc : cand) {
@@ -1724,6 +1746,8 @@ static Level step_level(Ctx &cx, const bp_hypergraph *hg)
     L.nbig = ((int32_t *)cx.info_h)[2];
     L.nhuge = ((int32_t *)cx.info_h)[3];
     L.maxseg_nodes = L.N;
+    L.maxseg_pins = L.P;
+    L.maxseg_hedges = L.E;
     build_incidence(cx, L);
     return L;
 }

@@ -5,6 +5,7 @@
 #include "kway.hpp"
 #include "refine.hpp"
 #include "uncoarsen.hpp"
+#include "balance.hpp"
 #include "transpose.hpp"
 
 namespace bp {
@@ -20,6 +21,7 @@ struct Schedule {
     int32_t seg_select_max_nodes = 1 << 15;
     int32_t round_chunk_max = 32;
     int32_t fused_pick_lists = 8;
+    int32_t fuse_max_pins = 1 << 17;
 };
 
 Schedule current_schedule();  // the process-wide schedule (a copy, taken under a lock)
@@ -87,7 +89,7 @@ __global__ __launch_bounds__(kBlock) void k_seg_total(int32_t N, const int32_t *
 // per-bisection fixed-point factor of the graph the segment descends from.
 __global__ void k_seg_setup(int32_t S, const int32_t *ksub, const int32_t *k0_fixed,
                             const int64_t *W, const uint64_t *Fs,
-                            const int32_t *nbase, const int32_t *hbase, int32_t max_levels,
+                            const int32_t *nbase, const int32_t *hbase, const int32_t *off, int32_t max_levels,
                             int32_t min_nodes, int32_t *k0, int32_t *k1, int64_t *max0,
                             int64_t *max1, uint8_t *active, int32_t *coarsest, int32_t *stuck,
                             LevelInfo *info)
@@ -117,6 +119,8 @@ __global__ void k_seg_setup(int32_t S, const int32_t *ksub, const int32_t *k0_fi
     stuck[s] = 0;
     if (go) atomicAdd(&info->active, 1);
     atomicMax(&info->maxseg_nodes, ns);
+    atomicMax(&info->maxseg_pins, off[hbase[s + 1]] - off[hbase[s]]);
+    atomicMax(&info->maxseg_hedges, es);
 }
 
 // ---- level construction ----------------------------------------------------------

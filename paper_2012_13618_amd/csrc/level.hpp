@@ -26,6 +26,8 @@ struct Level {
     int32_t *lmid = nullptr, *lbig = nullptr, *lhuge = nullptr;
     int32_t nmid = 0, nbig = 0, nhuge = 0;
     int32_t maxseg_nodes = 0;   // largest segment node count
+    int32_t maxseg_pins = 0;    // largest segment pin count
+    int32_t maxseg_hedges = 0;  // largest segment hyperedge count
     int32_t *parent = nullptr;  // [N] -> ids of the next level, once coarsened
     uint8_t *side = nullptr;    // [N] bisection side
     // node-major incidence: hyperedges of node v are inc[noff[v] .. noff[v+1])
@@ -53,7 +55,8 @@ struct LevelInfo {
     int32_t active;         // segments that keep coarsening
     int32_t maxseg_nodes;   // largest segment
     int32_t flag;           // general-purpose count (rounds still running)
-    int32_t pad[6];
+    int32_t maxseg_pins, maxseg_hedges;
+    int32_t pad[4];
 };
 
 // Per-list selection state (device arrays of 2S unless noted).

@@ -88,6 +88,7 @@ template <typename K> __device__ void block_rank_sort(const K *in, K *out, int c
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
         K x = in[i];
         int r = 0;
+#pragma unroll 8
         for (int j = 0; j < cnt; j++) r += in[j] < x;
         out[r] = x;
     }

@@ -156,6 +156,40 @@ def test_refine(bp, h):
         assert stuck == rstuck
 
 
+@pytest.mark.parametrize("fuse", [0, 1 << 30], ids=["rounds", "one-workgroup"])
+def test_balance_paths(bp, fuse):
+    """Both forms of the balance step (a launch per round, or every round of
+    a segment in one workgroup) against the oracle, whichever the default
+    schedule picks."""
+    import torch
+    old = bp.schedule_get()
+    try:
+        s = bp.schedule_default()
+        s.fuse_max_pins = fuse
+        bp.schedule_set(s)
+        say("balance paths", s.as_dict())
+        rng = np.random.default_rng(17)
+        for h in CASES[3:]:
+            dh = _dev(bp, h)
+            total = int(h.node_w.sum())
+            for frac, iters in [(0.9, 0), (0.12, 1)]:
+                side = (rng.random(h.num_nodes) < frac).astype(np.uint8)
+                m0, m1 = oracle.bounds(total, 1, 1, F105)
+                ref, rstuck = oracle.refine(h.num_nodes, h.offsets, h.pins, side, m0, m1, iters=iters,
+                                            nw=h.node_w, hw=h.hedge_w)
+                ds = torch.as_tensor(side).cuda()
+                stuck = bp.step_refine(dh, ds, m0, m1, iters=iters)
+                assert np.array_equal(ds.cpu().numpy(), ref), (h.name, frac)
+                assert stuck == rstuck
+        for name, make, k, eps in [PARTITION_CASES[1], PARTITION_CASES[4]]:
+            h = make()
+            ref_part, ref_cut = oracle.partition(h.num_nodes, h.offsets, h.pins, k, eps, h.node_w, h.hedge_w)
+            part, cut, _, _ = bp.partition_device(_dev(bp, h), k, eps)
+            assert np.array_equal(part.cpu().numpy(), ref_part) and cut == ref_cut, name
+    finally:
+        bp.schedule_set(old)
+
+
 @pytest.mark.parametrize("h", CASES, ids=IDS)
 def test_bisect(bp, h):
     say("bisect", h.name)
