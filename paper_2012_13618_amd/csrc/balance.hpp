@@ -45,6 +45,168 @@ struct FuseArgs {
     int32_t max_pins;   // segments with more pins are left to the multi-launch rounds
 };
 
+// LDS the selection of a list's best nodes works in.
+struct PickLds {
+    uint32_t *hist;         // kFuseBins
+    uint64_t *cand;         // kFuseCand
+    int32_t *tcnt;          // ITEMS * TH / 64
+    uint64_t *keys;         // KCAP (a power of two): the chosen nodes' order keys
+    int32_t *ncand, *nkeys; // zero on entry
+    int32_t *sbin;          // [3]
+};
+
+// Appends to pl.keys the order keys (gain desc, id asc) of the r nodes of
+// smallest (u, id) among a list's c nodes, u = gmax - gain.  uat(j, u) tells
+// whether item j of this thread (node id j * TH + threadIdx.x) is in the list
+// and sets its u; T is the bit length of the largest u.  Every thread calls;
+// the keys are complete after the caller's next barrier.
+//
+// Nodes with u < ulo are chosen, and the rem smallest of "the bin", u in
+// [ulo, ulo + 2^lo): by rank when the bin is small (bmode 1), by id when its
+// u are all equal (bmode 2).  Radix passes over u (8-bit digits from the top)
+// narrow the bin down.
+template <int TH, int ITEMS, int KCAP, typename UAt>
+__device__ __forceinline__ void pick_best(UAt uat, int32_t gmax, int32_t a0, int32_t r, int32_t c, int T,
+                                          const PickLds &pl)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    uint64_t ulo = r == c ? ~0ull : 0ull;
+    int lo = 0, bmode = 0;
+    int32_t rem = 0;
+    if (r > 0 && r < c) {
+        uint32_t pre = 0;
+        rem = r;
+        for (int p = 0;; p++) {
+            int hi = T - kFuseDigit * p;
+            lo = hi - kFuseDigit > 0 ? hi - kFuseDigit : 0;
+            if (tid < kFuseBins) pl.hist[tid] = 0;
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < ITEMS; j++) {
+                uint32_t u = 0;
+                bool in = uat(j, u);  // hi <= 24 when p > 0
+                bool act = in && (p == 0 || ((u ^ pre) >> hi) == 0);
+                lds_hist_add(act, (u >> lo) & ((1u << (hi - lo)) - 1u), pl.hist);
+            }
+            __syncthreads();
+            if (wv == 0) {  // the bin holding the rem-th key: one wavefront
+                constexpr int per = kFuseBins / 64;
+                int32_t x[per], loc = 0;
+#pragma unroll
+                for (int j = 0; j < per; j++) {
+                    x[j] = (int32_t)pl.hist[lane * per + j];
+                    loc += x[j];
+                }
+                int32_t ex = wave_incl_scan(loc) - loc;
+                if (ex < rem && rem <= ex + loc) {
+                    int32_t acc = ex;
+#pragma unroll
+                    for (int j = 0; j < per; j++) {
+                        if (acc < rem && rem <= acc + x[j]) {
+                            pl.sbin[0] = lane * per + j;
+                            pl.sbin[1] = acc;
+                            pl.sbin[2] = x[j];
+                        }
+                        acc += x[j];
+                    }
+                }
+            }
+            __syncthreads();
+            int32_t bin = pl.sbin[0], left = rem - pl.sbin[1], inb = pl.sbin[2];
+            pre |= (uint32_t)bin << lo;
+            rem = left;
+            ulo = pre;
+            if (left == inb) {  // the whole bin
+                ulo = (uint64_t)pre + (1ull << lo);
+                break;
+            }
+            if (inb <= kFuseCand) {
+                bmode = 1;
+                break;
+            }
+            if (lo == 0) {
+                bmode = 2;
+                break;
+            }
+        }
+    }
+
+    if (bmode == 1) {
+        // the bin's nodes as (u, id) keys; each chosen iff fewer than rem of
+        // them are smaller (TH / kFuseCand threads per key)
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t u = 0;
+            bool in = uat(j, u);
+            int32_t k = lds_wave_slot(in && (u >> lo) == (uint32_t)(ulo >> lo), pl.ncand);
+            if (k >= 0) pl.cand[k] = ((uint64_t)u << 32) | (uint32_t)(j * TH + tid);
+        }
+        __syncthreads();
+        constexpr int tpc = TH / kFuseCand;
+        int32_t nc = *pl.ncand, ci = tid / tpc, part = tid % tpc;
+        uint64_t x = ci < nc ? pl.cand[ci] : 0ull;
+        int32_t rk = 0;
+        if (ci < nc) {
+#pragma unroll 8
+            for (int32_t q = part; q < nc; q += tpc) rk += pl.cand[q] < x;
+        }
+#pragma unroll
+        for (int o = 1; o < tpc; o <<= 1) rk += __shfl_xor(rk, o, 64);
+        int32_t k = lds_wave_slot(ci < nc && part == 0 && rk < rem, pl.nkeys);
+        if (k >= 0)
+            pl.keys[k & (KCAP - 1)] = gain_order_key((int32_t)((int64_t)gmax - (uint32_t)(x >> 32)),
+                                                     (uint32_t)(a0 + (int32_t)(x & 0xffffffffu)));
+    } else if (bmode == 2) {
+        // the bin's nodes all have u == ulo: the first rem by id (ids ascend
+        // with (item j, wavefront, lane))
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t u = 0;
+            bool t = uat(j, u) && u == (uint32_t)ulo;
+            unsigned long long b = __ballot(t);
+            if (lane == 0) pl.tcnt[j * (TH / 64) + wv] = __popcll(b);
+        }
+        __syncthreads();
+        if (wv == 0) {
+            constexpr int nc = ITEMS * (TH / 64), per = nc / 64;
+            int32_t v[per], sum = 0;
+#pragma unroll
+            for (int q = 0; q < per; q++) {
+                v[q] = pl.tcnt[lane * per + q];
+                sum += v[q];
+            }
+            int32_t base = wave_incl_scan(sum) - sum;
+#pragma unroll
+            for (int q = 0; q < per; q++) {
+                pl.tcnt[lane * per + q] = base;
+                base += v[q];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t u = 0;
+            bool t = uat(j, u) && u == (uint32_t)ulo;
+            unsigned long long b = __ballot(t);
+            int32_t k = lds_wave_slot(
+                t && pl.tcnt[j * (TH / 64) + wv] + __popcll(b & ((1ull << lane) - 1ull)) < rem, pl.nkeys);
+            if (k >= 0)
+                pl.keys[k & (KCAP - 1)] = gain_order_key((int32_t)((int64_t)gmax - u), (uint32_t)(a0 + j * TH + tid));
+        }
+    }
+    // and the nodes below the bin
+    if (r > 0) {
+#pragma unroll
+        for (int j = 0; j < ITEMS; j++) {
+            uint32_t u = 0;
+            bool in = uat(j, u);
+            int32_t k = lds_wave_slot(in && (uint64_t)u < ulo, pl.nkeys);
+            if (k >= 0)
+                pl.keys[k & (KCAP - 1)] = gain_order_key((int32_t)((int64_t)gmax - u), (uint32_t)(a0 + j * TH + tid));
+        }
+    }
+}
+
 // Whether segment s is balanced here (nodes, hyperedges and pins in range).
 __device__ __forceinline__ bool fuse_fits(const FuseArgs &fa, int32_t s)
 {
@@ -103,7 +265,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
     __shared__ int32_t red[kFuseThreads / 64][3];
     __shared__ int64_t w01[2];
     __shared__ uint64_t cand[kFuseCand];
-    __shared__ int32_t qn, nkeys, ncand, sbin, sbefore, sin_, np_s;
+    __shared__ int32_t qn, nkeys, ncand, sbin[3], np_s;
 
     int32_t s = blockIdx.x;
     if (s >= S || fa.done[s] || !fuse_fits(fa, s)) return;
@@ -209,144 +371,13 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
 #pragma unroll
         for (int j = 0; j < kFuseItems; j++) gi[j] = (int32_t)(uint32_t)((int64_t)gmax - gi[j]);
 
-        // The r smallest keys (u, id), u = gmax - gain: nodes with u < ulo,
-        // and the rem smallest of "the bin", u in [ulo, ulo + 2^lo) - by
-        // rank when the bin is small (bmode 1), by id when its u are all equal
-        // (bmode 2).  Radix passes over u (12-bit digits from the top) narrow
-        // the bin down.
-        uint64_t ulo = r == c ? ~0ull : 0ull;
-        int lo = 0, bmode = 0;
-        int32_t rem = 0;
-        if (r > 0 && r < c) {
-            int T = bitlen_u32((uint32_t)((int64_t)gmax - gmin));
-            uint32_t pre = 0;
-            rem = r;
-            for (int p = 0;; p++) {
-                int hi = T - kFuseDigit * p;
-                lo = hi - kFuseDigit > 0 ? hi - kFuseDigit : 0;
-                if (tid < kFuseBins) work[tid] = 0;
-                __syncthreads();
-#pragma unroll
-                for (int j = 0; j < kFuseItems; j++) {
-                    uint32_t u = (uint32_t)gi[j];  // hi <= 24 when p > 0
-                    bool act = ((on >> j) & 1) && (p == 0 || ((u ^ pre) >> hi) == 0);
-                    lds_hist_add(act, (u >> lo) & ((1u << (hi - lo)) - 1u), work);
-                }
-                __syncthreads();
-                if (wv == 0) {  // the bin holding the rem-th key: one wavefront
-                    constexpr int per = kFuseBins / 64;
-                    int32_t x[per], loc = 0;
-#pragma unroll
-                    for (int j = 0; j < per; j++) {
-                        x[j] = (int32_t)work[lane * per + j];
-                        loc += x[j];
-                    }
-                    int32_t ex = wave_incl_scan(loc) - loc;
-                    if (ex < rem && rem <= ex + loc) {
-                        int32_t acc = ex;
-#pragma unroll
-                        for (int j = 0; j < per; j++) {
-                            if (acc < rem && rem <= acc + x[j]) {
-                                sbin = lane * per + j;
-                                sbefore = acc;
-                                sin_ = x[j];
-                            }
-                            acc += x[j];
-                        }
-                    }
-                }
-                __syncthreads();
-                int32_t bin = sbin, left = rem - sbefore, inb = sin_;
-                pre |= (uint32_t)bin << lo;
-                rem = left;
-                ulo = pre;
-                if (left == inb) {  // the whole bin
-                    ulo = (uint64_t)pre + (1ull << lo);
-                    break;
-                }
-                if (inb <= kFuseCand) {
-                    bmode = 1;
-                    break;
-                }
-                if (lo == 0) {
-                    bmode = 2;
-                    break;
-                }
-            }
-        }
-
-        if (bmode == 1) {
-            // the bin's nodes as (u, id) keys; each chosen iff fewer than rem
-            // of them are smaller (kFuseThreads / kFuseCand threads per key)
-#pragma unroll
-            for (int j = 0; j < kFuseItems; j++) {
-                uint32_t u = (uint32_t)gi[j];
-                int32_t k = lds_wave_slot(((on >> j) & 1) && (u >> lo) == (uint32_t)(ulo >> lo), &ncand);
-                if (k >= 0) cand[k] = ((uint64_t)u << 32) | (uint32_t)(j * kFuseThreads + tid);
-            }
-            __syncthreads();
-            constexpr int tpc = kFuseThreads / kFuseCand;
-            int32_t nc = ncand, ci = tid / tpc, part = tid % tpc;
-            uint64_t x = ci < nc ? cand[ci] : 0ull;
-            int32_t rk = 0;
-            if (ci < nc) {
-#pragma unroll 8
-                for (int32_t q = part; q < nc; q += tpc) rk += cand[q] < x;
-            }
-#pragma unroll
-            for (int o = 1; o < tpc; o <<= 1) rk += __shfl_xor(rk, o, 64);
-            int32_t k = lds_wave_slot(ci < nc && part == 0 && rk < rem, &nkeys);
-            if (k >= 0) {
-                int32_t lid = (int32_t)(x & 0xffffffffu);
-                keys[k & (kFuseKeys - 1)] = gain_order_key(g[lid], (uint32_t)(a0 + lid));
-            }
-        } else if (bmode == 2) {
-            // the bin's nodes all have u == ulo: the first rem by id (ids
-            // ascend with (item j, wavefront, lane))
-#pragma unroll
-            for (int j = 0; j < kFuseItems; j++) {
-                bool t = ((on >> j) & 1) && (uint32_t)gi[j] == (uint32_t)ulo;
-                unsigned long long b = __ballot(t);
-                if (lane == 0) tcnt[j * (kFuseThreads / 64) + wv] = __popcll(b);
-            }
-            __syncthreads();
-            if (wv == 0) {
-                constexpr int nc = kFuseItems * (kFuseThreads / 64), pl = nc / 64;
-                int32_t v[pl], sum = 0;
-#pragma unroll
-                for (int q = 0; q < pl; q++) {
-                    v[q] = tcnt[lane * pl + q];
-                    sum += v[q];
-                }
-                int32_t base = wave_incl_scan(sum) - sum;
-#pragma unroll
-                for (int q = 0; q < pl; q++) {
-                    tcnt[lane * pl + q] = base;
-                    base += v[q];
-                }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int j = 0; j < kFuseItems; j++) {
-                bool t = ((on >> j) & 1) && (uint32_t)gi[j] == (uint32_t)ulo;
-                unsigned long long b = __ballot(t);
-                int32_t k = lds_wave_slot(
-                    t && tcnt[j * (kFuseThreads / 64) + wv] + __popcll(b & ((1ull << lane) - 1ull)) < rem, &nkeys);
-                if (k >= 0)
-                    keys[k & (kFuseKeys - 1)] = gain_order_key(
-                        (int32_t)((int64_t)gmax - (uint32_t)gi[j]), (uint32_t)(a0 + j * kFuseThreads + tid));
-            }
-        }
-        // and the nodes below the bin
-        if (r > 0) {
-#pragma unroll
-            for (int j = 0; j < kFuseItems; j++) {
-                int32_t k = lds_wave_slot(((on >> j) & 1) && (uint64_t)(uint32_t)gi[j] < ulo, &nkeys);
-                if (k >= 0)
-                    keys[k & (kFuseKeys - 1)] = gain_order_key(
-                        (int32_t)((int64_t)gmax - (uint32_t)gi[j]), (uint32_t)(a0 + j * kFuseThreads + tid));
-            }
-        }
+        PickLds pl{work, cand, tcnt, keys, &ncand, &nkeys, sbin};
+        pick_best<kFuseThreads, kFuseItems, kFuseKeys>(
+            [=](int j, uint32_t &u) -> bool {
+                u = (uint32_t)gi[j];
+                return (on >> j) & 1;
+            },
+            gmax, a0, r, c, bitlen_u32((uint32_t)((int64_t)gmax - gmin)), pl);
         __syncthreads();
         int32_t cnt = min(nkeys, kFuseKeys);  // r of them
         block_rank_sort(keys, sorted, cnt);
