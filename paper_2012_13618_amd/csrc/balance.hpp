@@ -1,4 +1,5 @@
-// Balance step of Algorithm 5 for small segments, every round in one launch.
+// Balance step of Algorithm 5 (and the rounds of Algorithm 3) for small
+// segments, every round in one launch.
 //
 // One workgroup per segment keeps the segment's gains and sides in LDS and
 // runs the rounds itself: the over-weight side, the ceil(sqrt n) best nodes
@@ -33,7 +34,7 @@ constexpr int kFuseSmallDeg = 16;                    // larger hyperedges: one w
 constexpr int kFuseQueue = 1024;
 constexpr int kFuseCand = 256;                       // bins this small are ranked directly
 
-// Level arrays the balance rounds read, and the per-segment state they change.
+// Level arrays the rounds read, and the per-segment state they change.
 struct FuseArgs {
     const int32_t *off, *pins, *hw, *noff, *inc, *nw, *nbase, *hbase;
     uint8_t *side;
@@ -43,6 +44,11 @@ struct FuseArgs {
     int32_t *stuck;
     int32_t *rounds;    // atomicMax of the rounds any segment ran (may be null)
     int32_t max_pins;   // segments with more pins are left to the multi-launch rounds
+    // initial bisection only: segments whose coarsest level is `level`, their
+    // part counts and total weight
+    const int32_t *coarsest, *k0, *k1;
+    const int64_t *W;
+    int32_t level;
 };
 
 // LDS the selection of a list's best nodes works in.
@@ -252,7 +258,13 @@ __device__ __forceinline__ void fuse_hedge(int32_t e, bool full, int h, int lane
     }
 }
 
-__global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArgs fa)
+// INIT: the rounds of Algorithm 3 instead (segments at their coarsest
+// level, all nodes starting on side 1): while side 0 is below its share
+// W k0 / (k0 + k1) and side 1 has nodes, move the ceil(sqrt n) best nodes of
+// side 1 to side 0 (all of them, no prefix).  The gains follow the moves in
+// the same way.
+template <bool INIT>
+__global__ __launch_bounds__(kFuseThreads) void k_seg_fused(int32_t S, FuseArgs fa)
 {
     __shared__ int32_t g[kFuseNodes], nwl[kFuseNodes], noffl[kFuseNodes + 1];
     __shared__ uint8_t sd[kFuseNodes];
@@ -268,12 +280,13 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
     __shared__ int32_t qn, nkeys, ncand, sbin[3], np_s;
 
     int32_t s = blockIdx.x;
-    if (s >= S || fa.done[s] || !fuse_fits(fa, s)) return;
+    if (s >= S || (INIT ? fa.coarsest[s] != fa.level : fa.done[s] != 0) || !fuse_fits(fa, s)) return;
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int32_t a0 = fa.nbase[s], n = fa.nbase[s + 1] - a0;
     const int32_t e0 = fa.hbase[s], ne = fa.hbase[s + 1] - e0;
     const int32_t m = (int32_t)ceil_sqrt_i64(n);
-    const int64_t mx0 = fa.max0[s], mx1 = fa.max1[s];
+    const int64_t mx0 = INIT ? 0 : fa.max0[s], mx1 = INIT ? 0 : fa.max1[s];
+    const int64_t ks = INIT ? (int64_t)fa.k0[s] + fa.k1[s] : 0, Wk0 = INIT ? fa.W[s] * (int64_t)fa.k0[s] : 0;
 
     for (int32_t i = tid; i < n; i += kFuseThreads) {
         g[i] = 0;
@@ -311,13 +324,12 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
     for (;;) {
         // the side over its bound, the excess and the room
         int64_t w0 = w01[0], w1 = w01[1];
-        int h = w0 > mx0 ? 0 : (w1 > mx1 ? 1 : -1);
+        int h = INIT ? 1 : (w0 > mx0 ? 0 : (w1 > mx1 ? 1 : -1));
         if (h < 0) break;
         if (rounds > n) {  // never: each round moves a node for good, so <= n rounds
-            if (tid == 0) fa.stuck[s] = 1;
+            if (tid == 0 && !INIT) fa.stuck[s] = 1;
             break;
         }
-        rounds++;
 
         // this thread's nodes (ids j * kFuseThreads + tid): gains in registers,
         // bit j of `on` = node on side h
@@ -366,6 +378,8 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
             gmax = max(gmax, red[w][1]);
             gmin = min(gmin, red[w][2]);
         }
+        if (INIT && !(w0 * ks < Wk0 && c > 0)) break;  // Algorithm 3's loop test
+        rounds++;
         int32_t r = c < m ? c : m;
         // from here on the registers hold u = gmax - gain
 #pragma unroll
@@ -380,15 +394,16 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
             gmax, a0, r, c, bitlen_u32((uint32_t)((int64_t)gmax - gmin)), pl);
         __syncthreads();
         int32_t cnt = min(nkeys, kFuseKeys);  // r of them
-        block_rank_sort(keys, sorted, cnt);
+        // the moving nodes: all chosen ones (INIT), else a prefix in order
+        const uint64_t *mlist = INIT ? keys : sorted;
+        if (!INIT) block_rank_sort(keys, sorted, cnt);
 
         // prefix, moves and side weights (one wavefront)
         if (wv == 0) {
-            int64_t w0 = w01[0], w1 = w01[1];
             int64_t need = h ? w1 - mx1 : w0 - mx0, room = h ? mx0 - w0 : mx1 - w1;
-            int32_t p1 = cnt, fit = 0;
+            int32_t p1 = cnt, fit = INIT ? cnt : 0;
             int64_t carry = 0;
-            for (int32_t base = 0; base < cnt; base += 64) {
+            for (int32_t base = 0; !INIT && base < cnt; base += 64) {
                 int32_t i = base + lane;
                 int64_t w = i < cnt ? (int64_t)nwl[(uint32_t)(sorted[i] & 0xffffffffu) - a0] : 0;
                 int64_t incl = wave_incl_scan(w) + carry;
@@ -407,7 +422,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
                 int32_t i = base + lane;
                 int32_t deg = 0;
                 if (i < p) {
-                    int32_t v = (int32_t)(uint32_t)(sorted[i] & 0xffffffffu), u = v - a0;
+                    int32_t v = (int32_t)(uint32_t)(mlist[i] & 0xffffffffu), u = v - a0;
                     sd[u] = (uint8_t)(1 - h);
                     fa.side[v] = (uint8_t)(1 - h);
                     atomicOr(&mv[u >> 5], 1u << (u & 31));
@@ -431,7 +446,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
         __syncthreads();
         int32_t p = np_s;
         if (p == 0) {
-            if (tid == 0) fa.stuck[s] = 1;
+            if (tid == 0 && !INIT) fa.stuck[s] = 1;
             break;
         }
 
@@ -450,7 +465,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
                 if (dpre[mid] <= t) lo = mid;
                 else hi = mid;
             }
-            int32_t u = (int32_t)(uint32_t)(sorted[lo] & 0xffffffffu) - a0;
+            int32_t u = (int32_t)(uint32_t)(mlist[lo] & 0xffffffffu) - a0;
             int32_t x = fa.inc[noffl[u] + (t - dpre[lo])] - e0;
             uint32_t bit = 1u << (x & 31);
             if (atomicOr(&work[x >> 5], bit) & bit) continue;
@@ -470,7 +485,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
         __syncthreads();
         // the move marks are spent
         for (int32_t i = tid; i < p; i += kFuseThreads) {
-            int32_t u = (int32_t)(uint32_t)(sorted[i] & 0xffffffffu) - a0;
+            int32_t u = (int32_t)(uint32_t)(mlist[i] & 0xffffffffu) - a0;
             atomicAnd(&mv[u >> 5], ~(1u << (u & 31)));
         }
         __syncthreads();
@@ -478,7 +493,7 @@ __global__ __launch_bounds__(kFuseThreads) void k_seg_balance(int32_t S, FuseArg
     if (tid == 0) {
         fa.segw[2 * s] = (unsigned long long)w01[0];
         fa.segw[2 * s + 1] = (unsigned long long)w01[1];
-        fa.done[s] = 1;
+        if (!INIT) fa.done[s] = 1;
         if (fa.rounds) atomicMax(fa.rounds, rounds);
     }
 }

@@ -486,30 +486,60 @@ __global__ __launch_bounds__(kBlock) void k_copy_pins(int32_t count, const int32
 }
 
 // Sizes of the coarse level, its segment tables and which segments continue.
-__global__ void k_level_fixup(int32_t S, int32_t N, int32_t E, const int32_t *nbase,
-                              const int32_t *hbase, const int32_t *cid, const int32_t *hb_tmp,
-                              const int32_t *totN, const uint64_t *totEP, int32_t level_next,
-                              int32_t max_levels, int32_t min_nodes, const uint8_t *sact,
-                              uint8_t *sact_next, int32_t *coarsest, int32_t *c_nbase, int32_t *c_hbase,
-                              int32_t *c_off, const int32_t *counters, LevelInfo *info)
+// One workgroup (kFixupThreads); each thread owns a contiguous run of
+// segments.  A segment with no hyperedges starts its coarse hyperedges where
+// the next segment that had some starts (suffix minimum of the starts).
+constexpr int kFixupThreads = 1024;
+
+__global__ __launch_bounds__(kFixupThreads) void k_level_fixup(
+    int32_t S, int32_t N, int32_t E, const int32_t *nbase, const int32_t *hbase, const int32_t *cid,
+    const int32_t *hb_tmp, const int32_t *totN, const uint64_t *totEP, int32_t level_next, int32_t max_levels,
+    int32_t min_nodes, const uint8_t *sact, uint8_t *sact_next, int32_t *coarsest, int32_t *c_nbase,
+    int32_t *c_hbase, int32_t *c_off, const int32_t *counters, LevelInfo *info)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ int32_t rmin[kFixupThreads / 64];
+    __shared__ int32_t red[kFixupThreads / 64][4];
+    const int tid = threadIdx.x;
     int32_t Nc = *totN;
     int32_t Ec = (int32_t)(*totEP >> 32), Pc = (int32_t)(*totEP & 0xffffffffu);
-    c_off[Ec] = Pc;
-    c_hbase[S] = Ec;
-    for (int32_t s = S - 1; s >= 0; s--) c_hbase[s] = hbase[s] == hbase[s + 1] ? c_hbase[s + 1] : hb_tmp[s];
-    c_nbase[S] = Nc;
-    int32_t active = 0, maxn = 0, maxp = 0, maxe = 0;
-    for (int32_t s = 0; s < S; s++) {
-        c_nbase[s] = nbase[s] < N ? cid[nbase[s]] : Nc;
+    int32_t q = (S + kFixupThreads - 1) / kFixupThreads;
+    int32_t s0 = min(S, tid * q), s1 = min(S, s0 + q);
+    // own run: suffix minimum of the starts of segments that had hyperedges
+    int32_t m = INT32_MAX;
+    for (int32_t s = s1 - 1; s >= s0; s--) {
+        if (hbase[s] != hbase[s + 1]) m = min(m, hb_tmp[s]);
+        c_hbase[s] = m;
     }
-    for (int32_t s = 0; s < S; s++) {
+    for (int32_t s = s0; s < s1; s++) c_nbase[s] = nbase[s] < N ? cid[nbase[s]] : Nc;
+    if (tid == 0) {
+        c_off[Ec] = Pc;
+        c_hbase[S] = Ec;
+        c_nbase[S] = Nc;
+    }
+    // the runs after this one: suffix minimum over the threads (wavefront
+    // shuffles, then the wavefronts after this one)
+    int lane = tid & 63, wv = tid >> 6;
+    int32_t incl = m;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        int32_t y = __shfl_down(incl, o, 64);
+        if (lane + o < 64) incl = min(incl, y);
+    }
+    int32_t after = __shfl_down(incl, 1, 64);
+    if (lane == 63) after = INT32_MAX;
+    if (lane == 0) rmin[wv] = incl;
+    __syncthreads();
+    after = min(after, Ec);
+    for (int w = wv + 1; w < kFixupThreads / 64; w++) after = min(after, rmin[w]);
+    for (int32_t s = s0; s < s1; s++) c_hbase[s] = min(c_hbase[s], after);
+    __syncthreads();
+    int32_t active = 0, maxn = 0, maxp = 0, maxe = 0;
+    for (int32_t s = s0; s < s1; s++) {
         int32_t ns = c_nbase[s + 1] - c_nbase[s], es = c_hbase[s + 1] - c_hbase[s];
         int32_t ps = c_off[c_hbase[s + 1]] - c_off[c_hbase[s]];
-        if (ns > maxn) maxn = ns;
-        if (ps > maxp) maxp = ps;
-        if (es > maxe) maxe = es;
+        maxn = max(maxn, ns);
+        maxp = max(maxp, ps);
+        maxe = max(maxe, es);
         bool go = false;
         if (sact[s]) {
             coarsest[s] = level_next;
@@ -518,17 +548,36 @@ __global__ void k_level_fixup(int32_t S, int32_t N, int32_t E, const int32_t *nb
         }
         sact_next[s] = go ? 1 : 0;
     }
-    info->N = Nc;
-    info->E = Ec;
-    info->P = Pc;
-    info->nmid = counters[1];
-    info->nbig = counters[2];
-    info->nhuge = counters[3];
-    info->unresolved = counters[0];
-    info->active = active;
-    info->maxseg_nodes = maxn;
-    info->maxseg_pins = maxp;
-    info->maxseg_hedges = maxe;
+    active = wave_sum(active);
+    maxn = wave_max(maxn);
+    maxp = wave_max(maxp);
+    maxe = wave_max(maxe);
+    if ((tid & 63) == 0) {
+        red[tid >> 6][0] = active;
+        red[tid >> 6][1] = maxn;
+        red[tid >> 6][2] = maxp;
+        red[tid >> 6][3] = maxe;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < kFixupThreads / 64; w++) {
+            active += red[w][0];
+            maxn = max(maxn, red[w][1]);
+            maxp = max(maxp, red[w][2]);
+            maxe = max(maxe, red[w][3]);
+        }
+        info->N = Nc;
+        info->E = Ec;
+        info->P = Pc;
+        info->nmid = counters[1];
+        info->nbig = counters[2];
+        info->nhuge = counters[3];
+        info->unresolved = counters[0];
+        info->active = active;
+        info->maxseg_nodes = maxn;
+        info->maxseg_pins = maxp;
+        info->maxseg_hedges = maxe;
+    }
 }
 
 }  // namespace bp

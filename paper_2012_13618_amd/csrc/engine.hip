@@ -193,7 +193,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
         launch(lc, "copy_pins_block", 0.0, k_copy_pins<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0,
                f.nbig, (const int32_t *)f.lbig, (const int32_t *)f.off, rep, qlen,
                (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
-        launch(lc, "level_fixup", 0.0, k_level_fixup, 1, 1, 0, S, N, E, (const int32_t *)f.nbase,
+        launch(lc, "level_fixup", 0.0, k_level_fixup, 1, kFixupThreads, 0, S, N, E, (const int32_t *)f.nbase,
                (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
                (const int32_t *)b.totN, (const uint64_t *)b.totEP, l + 1, cx.prm.max_levels,
                cx.prm.min_coarse_nodes, (const uint8_t *)sact, sact_next, sg.coarsest, c.nbase,
@@ -218,7 +218,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
                    (const int32_t *)f.off, (const int32_t *)b.qpins, (const int32_t *)b.qlen,
                    (const int32_t *)f.hw, (const int32_t *)b.hslot, (const int32_t *)b.tmin, 1,
                    b.rep, b.wsum, b.counters);
-            launch(lc, "dedup", 0.0, k_level_fixup, 1, 1, 0, S, N, E, (const int32_t *)f.nbase,
+            launch(lc, "dedup", 0.0, k_level_fixup, 1, kFixupThreads, 0, S, N, E, (const int32_t *)f.nbase,
                    (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
                    (const int32_t *)b.totN, (const uint64_t *)b.totEP, l + 1, cx.prm.max_levels,
                    cx.prm.min_coarse_nodes, (const uint8_t *)sact, sact_next, sg.coarsest,
@@ -484,11 +484,37 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, R
     }
 }
 
+// Whether every segment of the level runs its rounds in one workgroup.
+static bool fuse_all(const Ctx &cx, const Level &L)
+{
+    return cx.sched.fuse_max_pins > 0 && L.maxseg_nodes <= kFuseNodes && L.maxseg_pins <= cx.sched.fuse_max_pins &&
+           L.maxseg_hedges <= kFuseHedges;
+}
+
+static int64_t fused_rounds_run(Ctx &cx, const int32_t *ctr)
+{
+    if (!trace_on()) return 0;
+    int32_t r = 0;
+    BP_HIP(hipMemcpyAsync(&r, ctr, sizeof(int32_t), hipMemcpyDeviceToHost, cx.lc.stream));
+    cx.lc.sync();
+    return r;
+}
+
 static int64_t initial_rounds(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gain)
 {
     LaunchCtx &lc = cx.lc;
     int64_t gs = ceil_div(L.S, kBlock);
     fill(lc, sg.go, 8, 0);
+    if (cx.sched.fuse_max_pins > 0) {
+        // small segments: all rounds of Algorithm 3 in one workgroup each.  They
+        // end with the loop test false, so the rounds below pass them by.
+        FuseArgs fa{L.off, L.pins, L.hw, L.noff, L.inc, L.nw, L.nbase, L.hbase, L.side, sg.max0, sg.max1,
+                    (unsigned long long *)sg.w, sg.done, sg.stuck, sg.go + 2, cx.sched.fuse_max_pins,
+                    sg.coarsest, sg.k0, sg.k1, sg.W, j};
+        launch(lc, "seg_initial", 8.0 * L.P, k_seg_fused<true>, L.S, kFuseThreads, 0, L.S, fa);
+        if (fuse_all(cx, L)) return fused_rounds_run(cx, sg.go + 2);
+        fill(lc, sg.go, 8, 0);
+    }
     return chunked_rounds(cx, sg, (int64_t)L.N + 2, false, [&](int32_t ri, const int32_t *gc) {
         launch(lc, "round", 0.0, k_round_initial, gs, kBlock, 0, L.S, j, (const int32_t *)L.nbase,
                (const int32_t *)sg.coarsest, (const int32_t *)sg.k0, (const int32_t *)sg.k1,
@@ -518,17 +544,12 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
     // small segments: the whole balance step in one workgroup each; when every
     // segment is small that is all, else the rounds below run the others
-    if (L.maxseg_nodes <= kFuseNodes && cx.sched.fuse_max_pins > 0) {
+    if (cx.sched.fuse_max_pins > 0) {
         FuseArgs fa{L.off, L.pins, L.hw, L.noff, L.inc, L.nw, L.nbase, L.hbase, L.side, sg.max0, sg.max1,
-                    (unsigned long long *)sg.w, sg.done, sg.stuck, sg.go + 2, cx.sched.fuse_max_pins};
-        launch(lc, "seg_balance", 8.0 * L.P, k_seg_balance, L.S, kFuseThreads, 0, L.S, fa);
-        if (L.maxseg_pins <= cx.sched.fuse_max_pins && L.maxseg_hedges <= kFuseHedges) {
-            if (!trace_on()) return 0;
-            int32_t r = 0;
-            BP_HIP(hipMemcpyAsync(&r, sg.go + 2, sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
-            lc.sync();
-            return r;
-        }
+                    (unsigned long long *)sg.w, sg.done, sg.stuck, sg.go + 2, cx.sched.fuse_max_pins,
+                    nullptr, nullptr, nullptr, nullptr, 0};
+        launch(lc, "seg_balance", 8.0 * L.P, k_seg_fused<false>, L.S, kFuseThreads, 0, L.S, fa);
+        if (fuse_all(cx, L)) return fused_rounds_run(cx, sg.go + 2);
     }
     // LDS keys of the balance finish (32 KiB at most): room for a sorted
     // copy behind the candidates when the lists are short
