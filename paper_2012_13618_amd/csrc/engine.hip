@@ -402,7 +402,7 @@ static void flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t
 // extremes itself, so the gain passes need not.
 static bool seg_path(const Ctx &cx, const Level &L, int kind)
 {
-    int32_t cap = kind == 0 ? seg_select_max<0>() : seg_select_max<1>();
+    int32_t cap = kind == 0 ? seg_select_max<0, kSegThreads>() : seg_select_max<1, kSegThreads>();
     return L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, cap);
 }
 
@@ -419,7 +419,7 @@ static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, co
                    L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
                    bf, go, (uint8_t *)nullptr);
         else
-            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0>, L.S, kSegThreads, 0, L.S,
+            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreads>, L.S, kSegThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
                    bf, go, (uint8_t *)nullptr);
         return;
@@ -602,8 +602,12 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                 launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                        L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
                        (unsigned long long *)sg.w, bf, gc, ml.moved);
+            else if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsBal>())
+                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsBal>, L.S, kSegThreadsBal, 0, L.S,
+                       sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
+                       (unsigned long long *)sg.w, bf, gc, ml.moved);
             else
-                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1>, L.S, kSegThreads, 0, L.S,
+                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreads>, L.S, kSegThreads, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
                        (unsigned long long *)sg.w, bf, gc, ml.moved);
             return;

@@ -66,7 +66,7 @@ struct MoveLog {
 };
 
 // Logs the moves of the first p keys' nodes (one workgroup).
-__device__ void log_moves(int32_t p, const uint64_t *a, const MoveLog &ml, int64_t *lds64)
+__device__ __forceinline__ void log_moves(int32_t p, const uint64_t *a, const MoveLog &ml, int64_t *lds64)
 {
     __shared__ int32_t base_s;
     for (int32_t base = 0; base < p; base += blockDim.x) {
@@ -108,7 +108,7 @@ struct BalFinish {
 // Balance step of segment s given its candidates a[0..cnt) in ascending
 // (gain desc, id asc) order: take the shortest prefix covering the excess,
 // cut back to what the other side can take, move it.  One workgroup.
-__device__ void bal_take_prefix(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf, int64_t *lds64)
+__device__ __forceinline__ void bal_take_prefix(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf, int64_t *lds64)
 {
     __shared__ int64_t carry;
     __shared__ int32_t p1s, ps;
@@ -176,7 +176,7 @@ __device__ void bal_take_prefix(int32_t s, const uint64_t *a, int32_t cnt, const
 }
 
 // log_moves by one wavefront.
-__device__ void log_moves_wave(int32_t p, const uint64_t *a, const MoveLog &ml)
+__device__ __forceinline__ void log_moves_wave(int32_t p, const uint64_t *a, const MoveLog &ml)
 {
     int lane = threadIdx.x & 63;
     for (int32_t base = 0; base < p; base += 64) {
@@ -205,7 +205,7 @@ __device__ void log_moves_wave(int32_t p, const uint64_t *a, const MoveLog &ml)
 // reaching the excess ends at the first chunk position that reaches it, and
 // the longest prefix within the room is min(that length, the number of
 // positions whose prefix weight fits).
-__device__ void bal_take_prefix_wave(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf)
+__device__ __forceinline__ void bal_take_prefix_wave(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf)
 {
     int lane = threadIdx.x & 63;
     int h = (bf.mode[s] & kList1) ? 1 : 0;

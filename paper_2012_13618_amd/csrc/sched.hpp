@@ -83,7 +83,7 @@ template <typename K> __device__ void block_bitonic_sort(K *a, int n)
 // Ascending order of cnt distinct keys by counting: key i goes to out[rank],
 // rank = the number of smaller keys.  One barrier instead of a bitonic
 // network's log^2 ones; O(cnt^2 / threads) comparisons, for short lists.
-template <typename K> __device__ void block_rank_sort(const K *in, K *out, int cnt)
+template <typename K> __device__ __forceinline__ void block_rank_sort(const K *in, K *out, int cnt)
 {
     for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
         K x = in[i];

@@ -761,13 +761,15 @@ __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const S
 
 // ---- small segments: the whole selection and the moves in one workgroup --------------------
 
-constexpr int kSegThreads = 1024;
+constexpr int kSegThreads = 1024;     // flips above 4 K nodes
+constexpr int kSegThreadsBal = 768;   // balance from 8 K to 24 K nodes
+constexpr int kSegThreadsSmall = 256; // flips up to 4 K nodes, balance up to 8 K
 // nodes per thread, kept in registers: the flipping kind holds both lists'
-// thresholds as well and fits half as many without spilling
+// thresholds as well.  1024 threads leave 128 registers per thread, 768
+// threads 170: 32 balance nodes each without spilling
 template <int KIND, int TH> constexpr int seg_items() { return KIND == 0 ? 16 : 32; }
-template <int KIND, int TH = kSegThreads> constexpr int32_t seg_select_max() { return TH * seg_items<KIND, TH>(); }
-constexpr int kSegThreadsSmall = 256;  // segments this many times smaller use a quarter of the threads
-constexpr int32_t kSegSelectMax = kSegThreads * 32;      // largest segment either kind takes
+template <int KIND, int TH> constexpr int32_t seg_select_max() { return TH * seg_items<KIND, TH>(); }
+constexpr int32_t kSegSelectMax = 32768;  // largest segment either kind takes
 constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
 
 // One workgroup per segment of at most kSegSelectMax nodes: each list's
@@ -777,7 +779,7 @@ constexpr int kSegKeys = 256;                           // balance candidates: c
 // (Algorithm 3 and the swap of Algorithm 5); kind 1 sorts the chosen nodes of
 // the over-weight side and takes the balance prefix (Algorithm 5).  The chosen
 // set is the one the multi-workgroup path chooses: the same keys, the same r.
-template <int KIND, int TH = kSegThreads>
+template <int KIND, int TH>
 __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
                                                            const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
@@ -788,34 +790,57 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     __shared__ int64_t lds64[16];
     __shared__ int32_t sbin, sbefore, sin_;
     __shared__ uint64_t keys[kSegKeys], sorted[KIND == 1 ? kSegKeys : 1];
+    __shared__ uint8_t sdl[seg_select_max<KIND, TH>()];  // the segment's sides
     __shared__ int32_t nkeys;
     if (go && *go == 0) return;
     int32_t s = blockIdx.x;
     int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
     // the previous round's move marks, in every segment (the gain update has used them)
     if (moved)
-        for (int32_t i = threadIdx.x; i < n; i += TH)
-            if (moved[a0 + i]) moved[a0 + i] = 0;
+        for (int32_t i = threadIdx.x; i < n; i += TH) moved[a0 + i] = 0;
     uint8_t md = sv.mode[s];
     if (!md) return;
     int32_t g[kSegItems];
-    uint32_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
+    uint64_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
     // per list: size and gain extremes, from the gains just loaded
     int32_t lc[2] = {0, 0}, lmax[2] = {INT32_MIN, INT32_MIN}, lmin[2] = {INT32_MAX, INT32_MAX};
+    if (n > 0) {
+        // the segment's sides staged in LDS by aligned 4-byte words (a word
+        // never leaves the memory page of the bytes it covers), then the gains
+        // (indices past the segment read its node 0): loads in flight together
+        const uint8_t *sp = sv.side + a0;
+        int32_t off0 = (int32_t)((uintptr_t)sp & 3), nw = (off0 + n + 3) >> 2;
+        const uint32_t *wp = (const uint32_t *)(sp - off0);
+        constexpr int kW = seg_select_max<KIND, TH>() / 4 / TH + 1;
+        uint32_t xw[kW];
+#pragma unroll
+        for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nw - 1)];
+#pragma unroll
+        for (int q = 0; q < kW; q++) {
+            int32_t w = q * TH + (int32_t)threadIdx.x;
+#pragma unroll
+            for (int b = 0; b < 4; b++) {
+                int32_t i = 4 * w + b - off0;
+                if (w < nw && i >= 0 && i < n) sdl[i] = (uint8_t)(xw[q] >> (8 * b));
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kSegItems; j++) {
+            int32_t i = j * TH + (int32_t)threadIdx.x;
+            g[j] = sv.gain[a0 + (i < n ? i : 0)];
+        }
+    }
+    __syncthreads();
 #pragma unroll
     for (int j = 0; j < kSegItems; j++) {
         int32_t i = j * TH + (int32_t)threadIdx.x;
-        g[j] = 0;
-        if (i < n) {
-            int sd = sv.side[a0 + i];
-            g[j] = sv.gain[a0 + i];
-            sbits |= (uint32_t)sd << j;
-            if (sel_list(s, sd, g[j], sv.mode)) {
-                ebits |= 1u << j;
-                lc[sd]++;
-                lmax[sd] = max(lmax[sd], g[j]);
-                lmin[sd] = min(lmin[sd], g[j]);
-            }
+        int sd = i < n ? sdl[i] : 0;
+        sbits |= (uint64_t)sd << j;
+        if (i < n && ((md >> sd) & 1) && !((md & kGainNonNeg) && g[j] < 0)) {  // sel_list
+            ebits |= 1ull << j;
+            lc[sd]++;
+            lmax[sd] = max(lmax[sd], g[j]);
+            lmin[sd] = min(lmin[sd], g[j]);
         }
     }
     {
@@ -852,7 +877,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     }
     uint64_t thr[2] = {0, 0};
     int32_t rr[2] = {0, 0};
-    int per = kBins / TH;
+    constexpr int per = (kBins + TH - 1) / TH;  // bins per thread (the last ones may run past kBins)
     for (int sd = 0; sd < 2; sd++) {
         int32_t c = 2 * s + sd;
         int64_t r = 0;
@@ -877,9 +902,10 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         int32_t rem = (int32_t)r;
         for (int p = 0;; p++) {
             int hi = T - kDigit * p, lo = hi - kDigit > 0 ? hi - kDigit : 0;
-            for (int j = 0; j < per; j++) hist[threadIdx.x * per + j] = 0;
+            for (int j = 0; j < per; j++)
+                if (threadIdx.x * per + j < kBins) hist[threadIdx.x * per + j] = 0;
             __syncthreads();
-            uint32_t mine = ebits & (sd ? sbits : ~sbits);
+            uint64_t mine = ebits & (sd ? sbits : ~sbits);
 #pragma unroll
             for (int j = 0; j < kSegItems; j++) {
                 if (!((mine >> j) & 1)) continue;
@@ -890,12 +916,13 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
             }
             __syncthreads();
             int64_t loc = 0, tot;
-            for (int j = 0; j < per; j++) loc += hist[threadIdx.x * per + j];
+            for (int j = 0; j < per; j++)
+                if (threadIdx.x * per + j < kBins) loc += hist[threadIdx.x * per + j];
             int64_t ex = block_excl_scan(loc, lds64, &tot);
             if (ex < rem && rem <= ex + loc) {
                 int64_t acc = ex;
                 for (int j = 0; j < per; j++) {
-                    int64_t x = hist[threadIdx.x * per + j];
+                    int64_t x = threadIdx.x * per + j < kBins ? hist[threadIdx.x * per + j] : 0;
                     if (acc + x >= rem) {
                         sbin = threadIdx.x * per + j;
                         sbefore = (int32_t)acc;
@@ -947,7 +974,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     if (threadIdx.x == 0) nkeys = 0;
     __syncthreads();
     if (rr[h] > 0) {
-        uint32_t mine = ebits & (h ? sbits : ~sbits);
+        uint64_t mine = ebits & (h ? sbits : ~sbits);
 #pragma unroll
         for (int j = 0; j < kSegItems; j++) {
             if (!((mine >> j) & 1)) continue;
