@@ -233,6 +233,7 @@ __device__ __forceinline__ void fuse_hedge(int32_t e, bool full, int h, int lane
 {
     int32_t b = fa.off[e], d = fa.off[e + 1] - b;
     int32_t n1 = 0, km = 0;
+#pragma unroll 4
     for (int32_t i = lane; i < d; i += stride) {
         int32_t u = fa.pins[b + i] - a0;
         n1 += sd[u];
@@ -249,6 +250,7 @@ __device__ __forceinline__ void fuse_hedge(int32_t e, bool full, int h, int lane
         if (km == 0) return;
         co = hedge_contrib_value(w, d, h ? n1 + km : n1 - km);
     }
+#pragma unroll 4
     for (int32_t i = lane; i < d; i += stride) {
         int32_t u = fa.pins[b + i] - a0;
         int sn = sd[u];

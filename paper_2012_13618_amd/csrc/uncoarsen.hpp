@@ -43,10 +43,17 @@ __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int strid
     if (!gmask[hseg[e]]) return;
     int32_t n1 = 0;
     if (S == SMALL) {
+        // straight-line loads (past the degree: pin 0 again), in flight together
+        int32_t u[kSmallMax];
 #pragma unroll
-        for (int i = 0; i < kSmallMax; i++)
-            if (i < d) n1 += side[pins[b + i]];
+        for (int i = 0; i < kSmallMax; i++) u[i] = pins[b + (i < d ? i : 0)];
+#pragma unroll
+        for (int i = 0; i < kSmallMax; i++) {
+            int32_t x = side[u[i]];
+            if (i < d) n1 += x;
+        }
     } else {
+#pragma unroll 4
         for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
         n1 = group_sum<S>(n1, lds);
     }
@@ -154,23 +161,28 @@ __device__ __forceinline__ void add_gain(int32_t u, int32_t delta, const int32_t
 constexpr int kUpdWords = 64;                // bitmap words a workgroup sweeps per step
 constexpr int kUpdQueue = kUpdWords * 32;  // hyperedges those words can hold
 
-// recount of hyperedge e's sides: its new contribution
-__device__ __forceinline__ int2 recount_small(int32_t e, const int32_t *off, const int32_t *pins,
+// recount of hyperedge e (pins b .. b + d, d <= kSmallMax) after a round:
+// its new contribution, with each pin's gain change added
+__device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, const int32_t *pins,
                                               const int32_t *hw, const uint8_t *side, const uint8_t *moved,
                                               int2 oc, const int32_t *bigslot, int32_t *slot, int32_t *gain)
 {
-    int32_t b = off[e], d = off[e + 1] - b;
+    // straight-line loads (past the degree: pin 0 again), so that they fly together
     int32_t u[kSmallMax];
-    uint8_t sn[kSmallMax], so[kSmallMax];
+    uint32_t sn[kSmallMax], so[kSmallMax];
     int32_t n1 = 0;
 #pragma unroll
-    for (int j = 0; j < kSmallMax; j++)
-        if (j < d) {
-            u[j] = pins[b + j];
-            sn[j] = side[u[j]];
-            so[j] = sn[j] ^ moved[u[j]];
-            n1 += sn[j];
-        }
+    for (int j = 0; j < kSmallMax; j++) u[j] = pins[b + (j < d ? j : 0)];
+#pragma unroll
+    for (int j = 0; j < kSmallMax; j++) {
+        sn[j] = side[u[j]];
+        so[j] = moved[u[j]];
+    }
+#pragma unroll
+    for (int j = 0; j < kSmallMax; j++) {
+        so[j] ^= sn[j];
+        if (j < d) n1 += sn[j];
+    }
     int2 nc = hedge_contrib_value(hw[e], d, n1);
 #pragma unroll
     for (int j = 0; j < kSmallMax; j++)
@@ -184,10 +196,11 @@ __device__ __forceinline__ int2 recount_small(int32_t e, const int32_t *off, con
 // Marked hyperedges, found by sweeping the bitmap (64 words per step):
 // recount the sides, replace the contribution, and add the change to every
 // pin's gain (a pin that moved trades its old side's contribution for its new
-// side's).  Each sweep step queues its hyperedges in LDS - degree <= 8 from
-// the front, taken one per thread, larger ones from the back, taken one per
-// wavefront.  Integer sums, so the result equals a recomputation.  The sweep
-// clears the bitmap.
+// side's).  Each step, one wavefront lists the step's marked hyperedges in
+// LDS (a popcount scan over its 64 words); then every thread takes listed
+// ones - degree <= 8 alone, larger ones queued for a wavefront each.
+// Integer sums, so the result equals a recomputation.  The sweep clears the
+// bitmap.
 __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t *bits, const int32_t *off,
                                                         const int32_t *pins, const int32_t *hw,
                                                         const uint8_t *side, const uint8_t *moved, int2 *cc,
@@ -196,44 +209,48 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                                                         const int32_t *go, int32_t *logcount)
 {
     __shared__ int32_t slot[kUpdSlots];
-    __shared__ int32_t queue[kUpdQueue];
-    __shared__ int32_t qs, qb;
+    __shared__ int32_t queue[kUpdQueue], bigq[kUpdQueue];
+    __shared__ int32_t nq, nbq;
     if (go && *go == 0) return;
     // the move log was read by the previous launch: empty it for this round's moves
     if (logcount && blockIdx.x == 0 && threadIdx.x == 0) *logcount = 0;
     int32_t nb = min(ncount[1], kUpdSlots);
     for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
-    if (threadIdx.x == 0) {
-        qs = 0;
-        qb = 0;
-    }
-    __syncthreads();
     int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int64_t base = (int64_t)blockIdx.x * kUpdWords; base < nwords; base += (int64_t)gridDim.x * kUpdWords) {
-        int64_t wi = base + threadIdx.x;
-        uint32_t word = (threadIdx.x < kUpdWords && wi < nwords) ? bits[wi] : 0u;
-        if (word) bits[wi] = 0;
-        while (word) {
-            int k = __ffs((int)word) - 1;
-            word &= word - 1;
-            int32_t e = (int32_t)(wi * 32 + k);
-            // front and back never meet: a step holds at most kUpdQueue hyperedges
-            if (off[e + 1] - off[e] <= kSmallMax) queue[atomicAdd(&qs, 1)] = e;
-            else queue[kUpdQueue - 1 - atomicAdd(&qb, 1)] = e;
+        if (wv == 0) {
+            int64_t wi = base + lane;
+            uint32_t word = wi < nwords ? bits[wi] : 0u;
+            if (word) bits[wi] = 0;
+            int32_t c = __popc(word);
+            int32_t at = wave_incl_scan(c) - c;
+            while (word) {
+                int k = __ffs((int)word) - 1;
+                word &= word - 1;
+                queue[at++] = (int32_t)(wi * 32 + k);
+            }
+            if (lane == 63) nq = at;
+            if (lane == 0) nbq = 0;
         }
         __syncthreads();
-        int32_t ns = qs, nbq = qb;
-        for (int32_t q = threadIdx.x; q < ns; q += blockDim.x) {
+        int32_t n = nq;
+        for (int32_t q = threadIdx.x; q < n; q += blockDim.x) {
             int32_t e = queue[q];
-            cc[e] = recount_small(e, off, pins, hw, side, moved, cc[e], bigslot, slot, gain);
+            int32_t b = off[e], d = off[e + 1] - b;
+            if (d <= kSmallMax) cc[e] = recount_small(e, b, d, pins, hw, side, moved, cc[e], bigslot, slot, gain);
+            else bigq[atomicAdd(&nbq, 1)] = e;
         }
-        for (int32_t q = wv; q < nbq; q += blockDim.x >> 6) {
-            int32_t e = queue[kUpdQueue - 1 - q];
+        __syncthreads();
+        int32_t nbig = nbq;
+        for (int32_t q = wv; q < nbig; q += blockDim.x >> 6) {
+            int32_t e = bigq[q];
             int32_t b = off[e], d = off[e + 1] - b;
             int32_t n1 = 0;
+#pragma unroll 4
             for (int j = lane; j < d; j += 64) n1 += side[pins[b + j]];
             n1 = wave_sum(n1);
             int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+#pragma unroll 4
             for (int j = lane; j < d; j += 64) {
                 int32_t u = pins[b + j];
                 int sn = side[u], so = sn ^ moved[u];
@@ -241,11 +258,6 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                 if (delta) add_gain(u, delta, bigslot, slot, gain);
             }
             if (lane == 0) cc[e] = nc;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            qs = 0;
-            qb = 0;
         }
         __syncthreads();
     }
@@ -275,9 +287,25 @@ __device__ __forceinline__ void node_gain_one(int32_t v, int lane, int stride, c
     if (!gmask[s]) return;
     int sd = side[v];
     int32_t g = 0;
-    for (int i = lane; i < d; i += stride) {
-        int2 c = cc[inc[b + i]];
-        g += sd ? c.y : c.x;
+    if (S == SMALL) {
+        // eight incidences at a time, straight-line loads (past the degree: the
+        // last incidence again), in flight together
+        for (int i0 = 0; i0 < d; i0 += 8) {
+            int32_t e8[8];
+#pragma unroll
+            for (int k = 0; k < 8; k++) e8[k] = inc[b + min(i0 + k, d - 1)];
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                int2 c = cc[e8[k]];
+                if (i0 + k < d) g += sd ? c.y : c.x;
+            }
+        }
+    } else {
+#pragma unroll 4
+        for (int i = lane; i < d; i += stride) {
+            int2 c = cc[inc[b + i]];
+            g += sd ? c.y : c.x;
+        }
     }
     g = group_sum<S>(g, lds);
     if (lane == 0) {
@@ -375,6 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
             int32_t b = noff[v], d = noff[v + 1] - b;
             int sd = side[v];
             int32_t g = 0;
+#pragma unroll 4
             for (int j = lane; j < d; j += 64) {
                 int2 c = cc[inc[b + j]];
                 g += sd ? c.y : c.x;
