@@ -87,7 +87,8 @@ def cpu_baseline(h, k, eps, budget_s):
 # Kernel families and the device functions that implement them (for matching
 # hardware-counter summaries, which name device functions).
 FAMILY_KERNEL = {"gain_nodes": "k_gain_nodes", "gain_hedges": "k_gain_hedges", "select": "k_select_pass",
-                 "seg_select": "k_seg_select", "gain_update": "k_gain_update"}
+                 "seg_select": "k_seg_select", "gain_update": "k_gain_update", "seg_balance": "k_seg_fused",
+                 "seg_initial": "k_seg_fused"}
 
 
 def sources_sha256(files):
