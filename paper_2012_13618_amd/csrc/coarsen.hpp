@@ -416,6 +416,32 @@ __global__ void k_refingerprint(int32_t E, const int32_t *off, const int32_t *qp
     fp[e] = fp_finish(sum, len);
 }
 
+// Slot of fingerprint f in the open-addressing table (inserted if new), with
+// hyperedge e offered as its smallest id.
+__device__ __forceinline__ int32_t dd_slot(unsigned long long f, int32_t e, unsigned long long *tkeys,
+                                           int32_t *tmin, int32_t tmask)
+{
+    uint32_t h = (uint32_t)(f ^ (f >> 32)) & (uint32_t)tmask;
+    for (;;) {
+        unsigned long long prev = atomicCAS(&tkeys[h], kEmptySlot, f);
+        if (prev == kEmptySlot || prev == f) break;
+        h = (h + 1) & (uint32_t)tmask;
+    }
+    atomicMin(&tmin[h], e);
+    return (int32_t)h;
+}
+
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long v, int src)
+{
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+    return ((unsigned long long)hi << 32) | lo;
+}
+
+// Duplicates share a fingerprint and so one slot, where per-hyperedge atomics
+// serialize on coarse levels (many hyperedges over the same few nodes): the
+// lanes sharing the first active lane's fingerprint (twice over) insert once,
+// with the first lane's id - the smallest, ids ascend with the lane.
 __global__ __launch_bounds__(kBlock) void k_dd_insert(int32_t E, const int32_t *qlen,
                                                       const uint64_t *fp, const int32_t *rep,
                                                       int only_unresolved,
@@ -423,19 +449,31 @@ __global__ __launch_bounds__(kBlock) void k_dd_insert(int32_t E, const int32_t *
                                                       int32_t tmask, int32_t *hslot)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E || qlen[e] < 2) return;
-    if (only_unresolved && rep[e] != -2) return;
-    unsigned long long f = fp[e];
-    uint32_t h = (uint32_t)(f ^ (f >> 32)) & (uint32_t)tmask;
-    for (;;) {
-        unsigned long long prev = atomicCAS(&tkeys[h], kEmptySlot, f);
-        if (prev == kEmptySlot || prev == f) break;
-        h = (h + 1) & (uint32_t)tmask;
+    bool act = e < E && qlen[e] >= 2 && !(only_unresolved && rep[e] != -2);
+    unsigned long long f = act ? fp[e] : 0ull;
+    int lane = threadIdx.x & 63;
+    unsigned long long am = __ballot(act);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (!am) break;
+        int leader = __ffsll((long long)am) - 1;
+        unsigned long long lf = readlane_u64(f, leader);
+        unsigned long long eq = __ballot(act && f == lf);
+        int32_t h = 0;
+        if (lane == leader) h = dd_slot(f, (int32_t)e, tkeys, tmin, tmask);
+        h = __builtin_amdgcn_readlane(h, leader);
+        if ((eq >> lane) & 1) {
+            hslot[e] = h;
+            act = false;
+        }
+        am &= ~eq;
     }
-    atomicMin(&tmin[h], (int32_t)e);
-    hslot[e] = (int32_t)h;
+    if (act) hslot[e] = dd_slot(f, (int32_t)e, tkeys, tmin, tmask);
 }
 
+// Representative of each hyperedge (the smallest id with the same pin set) and
+// the weight sums.  Lanes adding to the first adding lane's representative
+// (twice over) add with one atomic.
 __global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t *off,
                                                        const int32_t *qpins, const int32_t *qlen,
                                                        const int32_t *hw, const int32_t *hslot,
@@ -444,28 +482,49 @@ __global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t 
                                                        int32_t *unresolved)
 {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int32_t len = qlen[e];
-    if (only_unresolved) {
-        if (rep[e] != -2) return;
-    } else if (len < 2) {
-        rep[e] = -1;
-        return;
+    bool act = e < E;
+    int32_t len = act ? qlen[e] : 0;
+    if (act) {
+        if (only_unresolved) {
+            act = rep[e] == -2;
+        } else if (len < 2) {
+            rep[e] = -1;
+            act = false;
+        }
     }
-    int32_t r = tmin[hslot[e]];
-    bool same = true;
-    if (r != e) {
-        same = qlen[r] == len;
-        const int32_t *a = qpins + off[e], *c = qpins + off[r];
-        for (int i = 0; same && i < len; i++) same = a[i] == c[i];
+    int32_t r = 0;
+    bool add = false;
+    if (act) {
+        r = tmin[hslot[e]];
+        bool same = true;
+        if (r != e) {
+            same = qlen[r] == len;
+            const int32_t *a = qpins + off[e], *c = qpins + off[r];
+            for (int i = 0; same && i < len; i++) same = a[i] == c[i];
+        }
+        if (same) {
+            rep[e] = r;
+            add = true;
+        } else {
+            rep[e] = -2;
+            atomicAdd(unresolved, 1);
+        }
     }
-    if (same) {
-        rep[e] = r;
-        atomicAdd(&wsum[r], hw[e]);
-    } else {
-        rep[e] = -2;
-        atomicAdd(unresolved, 1);
+    int32_t w = add ? hw[e] : 0;
+    int lane = threadIdx.x & 63;
+    unsigned long long am = __ballot(add);
+#pragma unroll
+    for (int k = 0; k < 2; k++) {
+        if (!am) break;
+        int leader = __ffsll((long long)am) - 1;
+        int32_t lr = __builtin_amdgcn_readlane(r, leader);
+        unsigned long long eq = __ballot(add && r == lr);
+        int32_t sum = wave_sum(((eq >> lane) & 1) ? w : 0);
+        if (lane == leader) atomicAdd(&wsum[lr], sum);
+        if ((eq >> lane) & 1) add = false;
+        am &= ~eq;
     }
+    if (add) atomicAdd(&wsum[r], w);
 }
 
 
