@@ -153,8 +153,9 @@ def profiled_step(step, workload=None):
     tr = measured_traffic(workload, dom["name"]) if workload else None
     return {"bound": "hbm", "kernel": dom["name"], "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if tr is None else round(tr / avg_s / 1e9, 1),
-            "traffic_bytes_per_launch": None if tr is None else round(tr),
+            # HBM bytes per launch from the hardware counters, and as a rate
+            "traffic": None if tr is None else round(tr),
+            "traffic_gbs": None if tr is None else round(tr / avg_s / 1e9, 1),
             "algorithmic_bytes_per_launch": round(per_launch),
             "avg_launch_us": round(1e6 * avg_s, 3), "event_floor_us": round(1000 * floor_ms, 3),
             "launches_per_step": dom["launches"],
