@@ -85,6 +85,17 @@ struct Profiler {
             }
         acc.push_back({name, 1, ms, bytes});
     }
+    // bytes a family's kernels counted on the device (no launch, no time)
+    void add_bytes(const char *name, double bytes)
+    {
+        std::lock_guard<std::mutex> g(mu);
+        for (auto &a : acc)
+            if (a.name == name) {
+                a.bytes += bytes;
+                return;
+            }
+        acc.push_back({name, 0, 0.0, bytes});
+    }
 };
 
 // Launch bookkeeping for one call: counts launches, and when profiling is on

@@ -576,7 +576,13 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                  sg.go, sg.bal_moved};
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
     int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
-    return chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](int32_t ri, const int32_t *gc) {
+    // profiling: the gain update counts its data-dependent bytes on the device
+    unsigned long long *ubytes = nullptr;
+    if (incr && lc.prof) {
+        ubytes = ar.get<unsigned long long>(1);
+        fill(lc, ubytes, 1, 0ull);
+    }
+    int64_t rounds = chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](int32_t ri, const int32_t *gc) {
         launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
                (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
                sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go, ri);
@@ -587,10 +593,10 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
             launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
                    (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
                    (const int32_t *)L.inc, bits, gc);
-            launch(lc, "gain_update", 4.0 * nbits, k_gain_update, ugrid, kBlock, 0, nbits, bits,
+            launch(lc, "gain_update", 0.0, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
                    (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
-                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count);
+                   (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count, ubytes);
             if (!seg)
                 launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
@@ -618,6 +624,13 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S, (const int32_t *)sg.ccount,
                sg.cand, sg.cand_stride, cap, bf);
     });
+    if (ubytes) {
+        unsigned long long v = 0;
+        BP_HIP(hipMemcpyAsync(&v, ubytes, sizeof(v), hipMemcpyDeviceToHost, lc.stream));
+        lc.sync(false);
+        Profiler::get().add_bytes("gain_update", (double)v);
+    }
+    return rounds;
 }
 
 

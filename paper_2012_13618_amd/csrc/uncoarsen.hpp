@@ -159,7 +159,9 @@ __device__ __forceinline__ void add_gain(int32_t u, int32_t delta, const int32_t
 }
 
 constexpr int kUpdWords = 64;                // bitmap words a workgroup sweeps per step
+constexpr int kUpdChunk = 8;                 // ... as 8 chunks of this many words
 constexpr int kUpdQueue = kUpdWords * 32;  // hyperedges those words can hold
+constexpr int kUpdWaveMax = 512;           // larger marked hyperedges: the whole workgroup
 
 // recount of hyperedge e (pins b .. b + d, d <= kSmallMax) after a round:
 // its new contribution, with each pin's gain change added
@@ -193,33 +195,44 @@ __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, c
     return nc;
 }
 
-// Marked hyperedges, found by sweeping the bitmap (64 words per step):
-// recount the sides, replace the contribution, and add the change to every
-// pin's gain (a pin that moved trades its old side's contribution for its new
-// side's).  Each step, one wavefront lists the step's marked hyperedges in
-// LDS (a popcount scan over its 64 words); then every thread takes listed
-// ones - degree <= 8 alone, larger ones queued for a wavefront each.
-// Integer sums, so the result equals a recomputation.  The sweep clears the
-// bitmap.
+// Marked hyperedges, found by sweeping the bitmap: recount the sides, replace
+// the contribution, and add the change to every pin's gain (a pin that moved
+// trades its old side's contribution for its new side's).  Integer sums, so
+// the result equals a recomputation.  The sweep clears the bitmap.
+//
+// The bitmap is dealt out in chunks of 8 words (256 hyperedges, in id order),
+// chunk c to workgroup c mod G: a moved node's hyperedges crowd into a few
+// chunks (ids follow locality), and consecutive chunks go to different
+// workgroups.  Each step a workgroup takes 8 of its chunks; one wavefront
+// lists their marked hyperedges in LDS (popcount scan), then degree <= 8 go
+// one per thread, up to 512 one per wavefront, larger ones to the whole
+// workgroup.  When abytes is set (profiling), adds the algorithmic bytes it
+// moved: 4 per bitmap word, 28 per hyperedge (offsets, weight, contribution
+// in and out), 10 per pin (id, side, move flag, gain).
 __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t *bits, const int32_t *off,
                                                         const int32_t *pins, const int32_t *hw,
                                                         const uint8_t *side, const uint8_t *moved, int2 *cc,
                                                         int32_t *gain, const int32_t *bigslot,
                                                         const int32_t *lnbig, const int32_t *ncount,
-                                                        const int32_t *go, int32_t *logcount)
+                                                        const int32_t *go, int32_t *logcount,
+                                                        unsigned long long *abytes)
 {
     __shared__ int32_t slot[kUpdSlots];
-    __shared__ int32_t queue[kUpdQueue], bigq[kUpdQueue];
-    __shared__ int32_t nq, nbq;
+    __shared__ int32_t queue[kUpdQueue], bigq[kUpdQueue];  // bigq: wavefront ones from the front, workgroup ones from the back
+    __shared__ int32_t nq, nbq, nhq, npins;
+    __shared__ int32_t lds[16];
     if (go && *go == 0) return;
     // the move log was read by the previous launch: empty it for this round's moves
     if (logcount && blockIdx.x == 0 && threadIdx.x == 0) *logcount = 0;
     int32_t nb = min(ncount[1], kUpdSlots);
     for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
     int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int64_t base = (int64_t)blockIdx.x * kUpdWords; base < nwords; base += (int64_t)gridDim.x * kUpdWords) {
+    const int64_t G = gridDim.x;
+    int64_t words_done = 0, hedges_done = 0, pins_done = 0;  // thread 0's tally (profiling)
+    for (int64_t step = 0; step * 8 * G * kUpdChunk < nwords; step++) {
         if (wv == 0) {
-            int64_t wi = base + lane;
+            int64_t chunk = step * 8 * G + (lane / kUpdChunk) * G + blockIdx.x;
+            int64_t wi = chunk * kUpdChunk + (lane % kUpdChunk);
             uint32_t word = wi < nwords ? bits[wi] : 0u;
             if (word) bits[wi] = 0;
             int32_t c = __popc(word);
@@ -230,18 +243,24 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                 queue[at++] = (int32_t)(wi * 32 + k);
             }
             if (lane == 63) nq = at;
-            if (lane == 0) nbq = 0;
+            if (lane == 0) {
+                nbq = 0;
+                nhq = 0;
+                npins = 0;
+            }
         }
         __syncthreads();
         int32_t n = nq;
         for (int32_t q = threadIdx.x; q < n; q += blockDim.x) {
             int32_t e = queue[q];
             int32_t b = off[e], d = off[e + 1] - b;
+            if (abytes) atomicAdd(&npins, d);
             if (d <= kSmallMax) cc[e] = recount_small(e, b, d, pins, hw, side, moved, cc[e], bigslot, slot, gain);
-            else bigq[atomicAdd(&nbq, 1)] = e;
+            else if (d <= kUpdWaveMax) bigq[atomicAdd(&nbq, 1)] = e;
+            else bigq[kUpdQueue - 1 - atomicAdd(&nhq, 1)] = e;  // front and back never meet
         }
         __syncthreads();
-        int32_t nbig = nbq;
+        int32_t nbig = nbq, nhuge = nhq;
         for (int32_t q = wv; q < nbig; q += blockDim.x >> 6) {
             int32_t e = bigq[q];
             int32_t b = off[e], d = off[e + 1] - b;
@@ -259,10 +278,37 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             }
             if (lane == 0) cc[e] = nc;
         }
+        // the largest ones by the whole workgroup, one after another
+        for (int32_t q = 0; q < nhuge; q++) {
+            int32_t e = bigq[kUpdQueue - 1 - q];
+            int32_t b = off[e], d = off[e + 1] - b;
+            int32_t n1 = 0;
+#pragma unroll 4
+            for (int j = threadIdx.x; j < d; j += blockDim.x) n1 += side[pins[b + j]];
+            n1 = block_sum(n1, lds);
+            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+#pragma unroll 4
+            for (int j = threadIdx.x; j < d; j += blockDim.x) {
+                int32_t u = pins[b + j];
+                int sn = side[u], so = sn ^ moved[u];
+                int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
+                if (delta) add_gain(u, delta, bigslot, slot, gain);
+            }
+            __syncthreads();  // every thread has read the old contribution
+            if (threadIdx.x == 0) cc[e] = nc;
+        }
         __syncthreads();
+        if (threadIdx.x == 0) {
+            words_done += 64;
+            hedges_done += n;
+            pins_done += npins;
+        }
     }
+    __syncthreads();
     for (int i = threadIdx.x; i < nb; i += blockDim.x)
         if (slot[i]) atomicAdd(&gain[lnbig[i]], slot[i]);
+    if (abytes && threadIdx.x == 0 && words_done)
+        atomicAdd(abytes, (unsigned long long)(4 * words_done + 28 * hedges_done + 10 * pins_done));
 }
 
 // eligibility of a node for its list under the segment's selection mode
