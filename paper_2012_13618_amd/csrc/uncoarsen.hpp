@@ -844,16 +844,16 @@ constexpr int kSegThreadsSmall = 256; // flips up to 4 K nodes, balance up to 8 
 // threads 170: 32 balance nodes each without spilling
 template <int KIND, int TH> constexpr int seg_items() { return KIND == 0 ? 16 : 32; }
 template <int KIND, int TH> constexpr int32_t seg_select_max() { return TH * seg_items<KIND, TH>(); }
-constexpr int32_t kSegSelectMax = 32768;  // largest segment either kind takes
 constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
 
-// One workgroup per segment of at most kSegSelectMax nodes: each list's
+// One workgroup per segment of at most seg_select_max<KIND, TH>() nodes: each list's
 // r-th key by the same 12-bit radix select as the multi-workgroup passes,
 // with the segment's gains in registers and the histogram in LDS, then the
 // moves (bf.side is written): kind 0 flips the chosen nodes of both lists
-// (Algorithm 3 and the swap of Algorithm 5); kind 1 sorts the chosen nodes of
-// the over-weight side and takes the balance prefix (Algorithm 5).  The chosen
-// set is the one the multi-workgroup path chooses: the same keys, the same r.
+// (Algorithm 3 and the swap of Algorithm 5); kind 1 orders the chosen nodes
+// of the over-weight side (by counting) and one wavefront takes the balance
+// prefix (Algorithm 5).  The chosen set is the one the multi-workgroup path
+// chooses: the same keys, the same r.
 template <int KIND, int TH>
 __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
                                                            const int32_t *nw,
