@@ -287,3 +287,44 @@ def test_degenerate_inputs(bp):
         ref = oracle.partition(h.num_nodes, h.offsets, h.pins, k, eps)
         got = bp.partition(h.num_nodes, h.offsets, h.pins, k, eps)
         assert np.array_equal(got[0], ref[0]) and got[1] == ref[1], (k, eps)
+
+
+def _zero_weights(h, every=3):
+    """Same hypergraph with every `every`-th node weighing 0 (the balance
+    prefix then has steps of zero weight)."""
+    nw = h.node_w.copy()
+    nw[::every] = 0
+    return I.Hypergraph(h.num_nodes, h.offsets, h.pins, nw, h.hedge_w, name=h.name + "-w0")
+
+
+@pytest.mark.parametrize("n,fuse", [(8192, 1 << 30), (8193, 1 << 30), (20000, 0), (30000, 0), (6000, 1 << 30)],
+                         ids=["fused-at-limit", "fused-over-limit", "select-768", "select-1024", "fused-zero-w"])
+def test_balance_size_limits(bp, n, fuse):
+    """Balance steps at the size limits of the one-workgroup kernels (the fused
+    rounds at 8192 nodes, the 768- and 1024-thread selections), and with
+    zero-weight nodes, against the oracle."""
+    import torch
+    h = I.random_small(n, int(1.1 * n), 2, 12, 40 + n % 97, weighted_nodes=True, weighted_hedges=True)
+    if n == 6000:
+        h = _zero_weights(h)
+    old = bp.schedule_get()
+    try:
+        s = bp.schedule_default()
+        s.fuse_max_pins = fuse
+        s.incremental_min_pins = 0  # the later rounds update their gains from the moves
+        bp.schedule_set(s)
+        say("balance limits", h.name, s.as_dict())
+        dh = _dev(bp, h)
+        total = int(h.node_w.sum())
+        rng = np.random.default_rng(n)
+        for frac, iters in [(0.93, 0), (0.08, 2), (0.6, 1)]:
+            side = (rng.random(n) < frac).astype(np.uint8)
+            m0, m1 = oracle.bounds(total, 1, 1, F105)
+            ref, rstuck = oracle.refine(n, h.offsets, h.pins, side, m0, m1, iters=iters, nw=h.node_w,
+                                        hw=h.hedge_w)
+            ds = torch.as_tensor(side).cuda()
+            stuck = bp.step_refine(dh, ds, m0, m1, iters=iters)
+            assert np.array_equal(ds.cpu().numpy(), ref), (frac, iters)
+            assert stuck == rstuck
+    finally:
+        bp.schedule_set(old)
