@@ -412,8 +412,9 @@ __device__ __forceinline__ T block_excl_scan(T v, T *lds /* >= 16 */, T *total)
     return before + inc - v;
 }
 
-// Slot of each taking lane in an LDS list with counter *ctr: one atomic per
-// wavefront; -1 for lanes not taking.  Lanes that do not call take nothing.
+// Slot of each taking lane in a list with counter *ctr (LDS or global): one
+// atomic per wavefront; -1 for lanes not taking.  Lanes that do not call take
+// nothing.
 __device__ __forceinline__ int32_t lds_wave_slot(bool take, int32_t *ctr)
 {
     unsigned long long m = __ballot(take);

@@ -763,8 +763,38 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
         if (use_lds) {
             for (int i = threadIdx.x; i < 2 * kBins; i += blockDim.x) h[i] = 0;
             __syncthreads();
+            // one segment: its two lists' state once per workgroup, then only
+            // each node's side and gain
+            int32_t s = cbase / 2, nb0 = sv.nbase[s];
+            uint8_t md = sv.mode[s];
+            bool on0 = md & 1, on1 = (md >> 1) & 1;
+            if (p > 0) {
+                on0 = on0 && !st.done[cbase];
+                on1 = on1 && !st.done[cbase + 1];
+            } else {  // a list taken whole needs no histogram
+                int64_t t0 = st.tot[cbase], t1 = st.tot[cbase + 1], ms = sv.m[s];
+                bool pair = md & kMinPair;
+                on0 = on0 && (pair ? min(t0, t1) : min(t0, ms)) != t0;
+                on1 = on1 && (pair ? min(t1, t0) : min(t1, ms)) != t1;
+            }
+            int32_t gx0 = st.gmax[cbase], gx1 = st.gmax[cbase + 1];
+            int T0 = p == 0 ? sel_kbits(gx0, st.gmin[cbase], idbits) : st.kbits[cbase];
+            int T1 = p == 0 ? sel_kbits(gx1, st.gmin[cbase + 1], idbits) : st.kbits[cbase + 1];
+            uint64_t pr0 = p == 0 ? 0ull : st.kpre[cbase], pr1 = p == 0 ? 0ull : st.kpre[cbase + 1];
+            bool nonneg = md & kGainNonNeg;
+            if (on0 || on1) {
+#pragma unroll 4
+                for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+                    int sd = sv.side[v];
+                    int32_t g = sv.gain[v];
+                    if (!(sd ? on1 : on0) || (nonneg && g < 0)) continue;
+                    uint64_t k = sel_key(sd ? gx1 : gx0, g, (uint32_t)(v - nb0), idbits);
+                    int dig = sel_digit_k(k, sd ? T1 : T0, p, sd ? pr1 : pr0);
+                    if (dig >= 0) atomicAdd(&h[sd * kBins + dig], 1u);
+                }
+            }
         }
-        for (int64_t v = v0 + threadIdx.x; v < v1; v += blockDim.x) {
+        for (int64_t v = v0 + threadIdx.x; !use_lds && v < v1; v += blockDim.x) {
             int32_t s = sv.nseg[v];
             int sd = sv.side[v];
             int32_t g = sv.gain[v];
@@ -782,8 +812,7 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
             int T = p == 0 ? sel_kbits(st.gmax[c], st.gmin[c], idbits) : st.kbits[c];
             int dig = sel_digit_k(k, T, p, p == 0 ? 0ull : st.kpre[c]);
             if (dig < 0) continue;
-            if (use_lds) atomicAdd(&h[(c - cbase) * kBins + dig], 1u);
-            else atomicAdd(&st.hist[(int64_t)c * kBins + dig], 1u);
+            atomicAdd(&st.hist[(int64_t)c * kBins + dig], 1u);
         }
         if (use_lds) {
             __syncthreads();
@@ -1106,11 +1135,30 @@ __global__ __launch_bounds__(kBlock) void k_gather(int32_t N, SelView sv, SelSta
                                                    uint64_t *cand, int32_t stride, const int32_t *go)
 {
     if (go && *go == 0) return;
-    int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= N || !sel_chosen(v, sv, st)) return;
-    int32_t s = sv.nseg[v];
-    int32_t at = atomicAdd(&ccount[s], 1);
-    cand[(int64_t)s * stride + at] = gain_order_key(sv.gain[v], (uint32_t)v);
+    int64_t v0 = (int64_t)blockIdx.x * blockDim.x, v = v0 + threadIdx.x;
+    int64_t vl = min(v0 + (int64_t)blockDim.x, (int64_t)N) - 1;
+    int32_t s0 = sv.nseg[v0];
+    if (s0 != sv.nseg[vl]) {  // workgroup over several segments: node by node
+        if (v >= N || !sel_chosen(v, sv, st)) return;
+        int32_t s = sv.nseg[v];
+        int32_t at = atomicAdd(&ccount[s], 1);
+        cand[(int64_t)s * stride + at] = gain_order_key(sv.gain[v], (uint32_t)v);
+        return;
+    }
+    // one segment: its lists' state once, one append atomic per wavefront
+    uint8_t md = sv.mode[s0];
+    int32_t nb0 = sv.nbase[s0];
+    bool chosen = false;
+    int32_t g = 0;
+    if (v < N) {
+        int sd = sv.side[v];
+        g = sv.gain[v];
+        int32_t c = 2 * s0 + sd;
+        chosen = ((md >> sd) & 1) && !((md & kGainNonNeg) && g < 0) && st.rsel[c] > 0 &&
+                 sel_key(st.gmax[c], g, (uint32_t)(v - nb0), sv.idbits) <= st.kthr[c];
+    }
+    int32_t at = lds_wave_slot(chosen, &ccount[s0]);
+    if (at >= 0) cand[(int64_t)s0 * stride + at] = gain_order_key(g, (uint32_t)v);
 }
 
 // ---- per-round modes: also reset the selection state of the lists --------------------------
