@@ -53,12 +53,22 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, cons
     run[t] = 0;
     unsigned long long below = (1ull << lane) - 1;
     int64_t tile = (int64_t)blockIdx.x * kRsTile;
+    // the whole tile in registers first: its loads in flight together
+    uint32_t keys[kRsItems];
+    int32_t vals[kRsItems];
+#pragma unroll
+    for (int r = 0; r < kRsItems; r++) {
+        int64_t i = tile + r * kBlock + t;
+        keys[r] = i < n ? kin[i] : 0u;
+        vals[r] = i < n ? vin[i] : 0;
+    }
+#pragma unroll
     for (int r = 0; r < kRsItems; r++) {
         for (int j = t; j < (kBlock / 64) * 256; j += kBlock) (&wcnt[0][0])[j] = 0;
         int64_t i = tile + r * kBlock + t;
         bool valid = i < n;
-        uint32_t key = valid ? kin[i] : 0u;
-        int32_t val = valid ? vin[i] : 0;
+        uint32_t key = keys[r];
+        int32_t val = vals[r];
         uint32_t dig = (key >> shift) & 255u;
         // lanes holding the same digit
         unsigned long long same = __ballot(valid);

@@ -406,9 +406,16 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
             if (d > kNodeSmallMax || !gmask[s]) continue;
             int sd = side[v];
             int32_t g = 0;
-            for (int i = 0; i < d; i++) {
-                int2 c = cc[inc[b + i]];
-                g += sd ? c.y : c.x;
+            // eight incidences at a time, straight-line loads in flight together
+            for (int i0 = 0; i0 < d; i0 += 8) {
+                int32_t e8[8];
+#pragma unroll
+                for (int k = 0; k < 8; k++) e8[k] = inc[b + min(i0 + k, d - 1)];
+#pragma unroll
+                for (int k = 0; k < 8; k++) {
+                    int2 c = cc[e8[k]];
+                    if (i0 + k < d) g += sd ? c.y : c.x;
+                }
             }
             gain[v] = g;
             if (!stats || !sel_list(s, sd, g, mode)) continue;
