@@ -47,6 +47,16 @@ __host__ __device__ inline int64_t reduce_grid(int64_t n)
     int64_t g = ceil_div(n, 256);
     return g < kReduceBlocks ? g : kReduceBlocks;
 }
+// Workgroups of a launch go to the 8 XCDs in turn (workgroup b to XCD b mod 8),
+// and each XCD has its own L2.  xcd_block renumbers workgroups 0 .. n-1 so
+// that each XCD takes one contiguous run of the n logical blocks: chunks
+// that gather from the same neighbourhood (one graph of a batch) share an L2.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t n)
+{
+    constexpr int64_t X = 8;
+    int64_t q = n / X, r = n % X, x = b % X, k = b / X;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
 // lists (two per segment) a chunk aggregates in LDS before its atomics
 constexpr int kAggLists = 64;
 // [lo, hi): chunk of workgroup b of g over n items, in tiles of 256

@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
     int64_t ns = ceil_div(E, kBlock), nw = ceil_div(nmid, kBlock / 64);
     int64_t vb = blockIdx.x;
     if (vb < ns) {
-        int64_t e = vb * kBlock + threadIdx.x;
+        int64_t e = xcd_block(vb, ns) * kBlock + threadIdx.x;
         if (e < E) hedge_contrib_one<SMALL>((int32_t)e, 0, 1, off, pins, hw, hseg, gmask, side, cc, lds);
     } else if (vb < ns + nw) {
         int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6);
@@ -390,7 +390,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
     if (vb < ns) {
         // nodes of degree <= 32, one per thread, over a contiguous chunk
         int64_t lo, hi;
-        reduce_chunk(N, ns, vb, lo, hi);
+        reduce_chunk(N, ns, xcd_block(vb, ns), lo, hi);
         if (lo >= hi) return;
         int32_t c0 = 2 * nseg[lo], nl = 2 * nseg[hi - 1] + 2 - c0;
         bool local = nl <= kAggLists;
