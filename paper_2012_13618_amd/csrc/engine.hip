@@ -375,7 +375,9 @@ static SelView sel_view(Level &L, Segs &sg, const int32_t *gain)
 // The first r nodes of every list in (gain desc, id asc) order: up to three
 // digit passes over the gain span and then over the node id; passes that no
 // list needs return at once.
-void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go)
+// clip > 0: a balance round, whose finish orders the gathered nodes and
+// keeps the first r, so a list may stop at a whole bin of at most clip keys
+void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go, int32_t clip)
 {
     LaunchCtx &lc = cx.lc;
     int idb = id_bits(L);
@@ -389,9 +391,9 @@ void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t 
     int64_t grid = std::max<int64_t>(1, ceil_div(L.N, kSelNodes));
     for (int p = 0; p < passes; p++) {
         launch(lc, "select", 10.0 * L.N, k_select_pass, grid, kBlock, 0, L.N, p, nl, idb, sv, sg.st,
-               fused, go);
+               fused, go, clip);
         if (!fused)
-            launch(lc, "select_pick", 0.0, k_select_pick, nl, kBlock, 0, nl, p, idb, sv, sg.st, go);
+            launch(lc, "select_pick", 0.0, k_select_pick, nl, kBlock, 0, nl, p, idb, sv, sg.st, go, clip);
     }
 }
 
@@ -573,7 +575,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         fill(lc, ml.count, 4, 0);
     }
     BalFinish bf{sg.mode, L.nw, sg.need, sg.room, L.side, (unsigned long long *)sg.w, sg.done, sg.stuck, ml,
-                 sg.go, sg.bal_moved};
+                 sg.go, sg.bal_moved, sg.st.rsel};
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
     int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
     // profiling: the gain update counts its data-dependent bytes on the device
@@ -618,7 +620,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                        (unsigned long long *)sg.w, bf, gc, ml.moved);
             return;
         }
-        run_select(cx, L, sg, gain, gc);
+        run_select(cx, L, sg, gain, gc, sg.cand_stride);
         launch(lc, "balance", 10.0 * L.N, k_gather, ceil_div(L.N, kBlock), kBlock, 0, L.N,
                sel_view(L, sg, gain), sg.st, sg.ccount, sg.cand, sg.cand_stride, gc);
         launch(lc, "balance", 0.0, k_bal_finish, L.S, 1024, (size_t)cap * 8, L.S, (const int32_t *)sg.ccount,
@@ -695,7 +697,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     int32_t maxn = 1;
     for (auto &x : lv) maxn = std::max(maxn, x.maxseg_nodes);
     int32_t mmax = (int32_t)ceil_sqrt_i64(maxn);
-    sg.cand_stride = next_pow2(std::max(mmax, 1));
+    sg.cand_stride = next_pow2(std::max(mmax, kBalGather));
     sg.cand = ar.get<uint64_t>((int64_t)sg.S * sg.cand_stride);
     int32_t *gain = ar.get<int32_t>(lv[0].N);
     fill(lc, sg.st.hist, (int64_t)2 * sg.S * kBins, 0u);
@@ -1885,7 +1887,7 @@ static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, i
     launch(cx.lc, "seg_setup", 0.0, k_seg_total, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const int32_t *)L.nw, (unsigned long long *)sg.W);
     int32_t mm = (int32_t)ceil_sqrt_i64(L.N);
-    sg.cand_stride = next_pow2(std::max(mm, 1));
+    sg.cand_stride = next_pow2(std::max(mm, kBalGather));
     sg.cand = cx.ar->get<uint64_t>(sg.cand_stride);
     return sg;
 }

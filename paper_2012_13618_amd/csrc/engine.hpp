@@ -284,6 +284,6 @@ void build_incidence(Ctx &cx, Level &L);
 void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key);
 void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0);
 void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int32_t *go);
-void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go);
+void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go, int32_t clip = 0);
 
 }  // namespace bp

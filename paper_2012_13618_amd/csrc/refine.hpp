@@ -103,6 +103,7 @@ struct BalFinish {
     MoveLog ml;
     int32_t *go;          // go[3]: most further rounds a segment is estimated to need
     int64_t *bal_moved;   // [2S] weight moved and rounds run this level
+    const int32_t *rsel;  // [2S] nodes each list chose (multi-workgroup rounds; else null)
 };
 
 // Balance step of segment s given its candidates a[0..cnt) in ascending
@@ -253,6 +254,7 @@ __device__ __forceinline__ void bal_take_prefix_wave(int32_t s, const uint64_t *
 }
 
 constexpr int32_t kRankSortMax = 1024;  // candidates ordered by counting up to this many
+constexpr int32_t kBalGather = 512;     // balance candidates a segment may gather, at least
 
 // One workgroup per balancing segment: sort its gathered candidates, then
 // the prefix step.  The launch reserves lds_cap keys of LDS (lds_cap may be
@@ -267,12 +269,19 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
     int32_t s = blockIdx.x;
     if (!bf.mode[s]) return;
     int32_t cnt = ccount[s];
+    // a selection that stopped at a whole bin gathered more nodes than the
+    // list chose: the chosen ones are the first rsel in order
+    int32_t take = cnt;
+    if (bf.rsel) {
+        int32_t r = bf.rsel[2 * s + ((bf.mode[s] & kList1) ? 1 : 0)];
+        take = r < cnt ? r : cnt;
+    }
     const uint64_t *src = cand + (int64_t)s * stride;
     if (cnt <= kRankSortMax && 2 * cnt <= lds_cap) {
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) keys_lds[i] = src[i];
         __syncthreads();
         block_rank_sort(keys_lds, keys_lds + cnt, cnt);
-        if (threadIdx.x < 64) bal_take_prefix_wave(s, keys_lds + cnt, cnt, bf);
+        if (threadIdx.x < 64) bal_take_prefix_wave(s, keys_lds + cnt, take, bf);
         return;
     }
     int n2 = next_pow2(cnt > 0 ? cnt : 1);
@@ -281,7 +290,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
         a[i] = i < cnt ? src[i] : kNoKey;
     __syncthreads();
     block_bitonic_sort(a, n2);
-    bal_take_prefix(s, a, cnt, bf, lds64);
+    bal_take_prefix(s, a, take, bf, lds64);
 }
 
 }  // namespace bp

@@ -15,6 +15,9 @@
 // first over the significant bits of u (1 digit when the list's gains span
 // < 4096 values), then over the bits of lid - each list follows its own digit
 // schedule and stops as soon as the remaining count equals a bin's count.
+// In balance rounds a list also stops at the bin holding its r-th key when
+// the keys through that bin fit the candidate buffer: the balance finish
+// orders what it gathers and keeps the first r.
 // Each pass is one launch: blocks build their histograms and the workgroup
 // that finishes last (atomic ticket) picks the digit of every list.
 #pragma once
@@ -603,9 +606,11 @@ __device__ __forceinline__ int sel_digit_k(uint64_t k, int T, int p, uint64_t pr
 }
 
 // Pick of list c after pass p: the digit holding the rem-th key.  One
-// workgroup.  Clears the bins it read.
+// workgroup.  Clears the bins it read.  clip > 0 (balance rounds): the list
+// may also stop at a whole bin once the keys up to its end are at most clip;
+// the balance finish then orders them and keeps the first rsel.
 __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, const uint8_t *mode,
-                              const int32_t *m, int64_t *lds)
+                              const int32_t *m, int64_t *lds, int32_t clip)
 {
     __shared__ int sbin;
     __shared__ int32_t sbefore, sin_;
@@ -674,8 +679,9 @@ __device__ void sel_pick_list(const SelState &st, int32_t c, int p, int idbits, 
         uint64_t pre = st.kpre[c] | ((uint64_t)sbin << lo);
         st.kpre[c] = pre;
         st.rem[c] = left;
-        // done when the whole bin is taken or the bin is a single key
-        if (left == sin_ || lo == 0) {
+        // done when the whole bin is taken or the bin is a single key, or
+        // (clip) when the keys through the end of the bin fit the finish
+        if (left == sin_ || lo == 0 || (clip > 0 && (int64_t)st.rsel[c] - left + sin_ <= clip)) {
             st.kthr[c] = pre | (lo ? ((1ull << lo) - 1ull) : 0ull);
             st.done[c] = 1;
             atomicSub(&st.ctl[0], 1);
@@ -701,7 +707,7 @@ __device__ __forceinline__ void empty_segment_done(const SelState &st, int32_t s
 // the picks of the segment's two lists.  Segments without nodes are settled
 // in pass 0 by the workgroup holding their position.
 __device__ void seg_tickets_pick(int32_t N, int p, int32_t nlists, int idbits, const SelView &sv,
-                                 const SelState &st, int64_t v0, int64_t *lds)
+                                 const SelState &st, int64_t v0, int64_t *lds, int32_t clip)
 {
     __shared__ int32_t picks[kBlock];
     __shared__ int npick;
@@ -741,8 +747,8 @@ __device__ void seg_tickets_pick(int32_t N, int p, int32_t nlists, int idbits, c
             if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             __syncthreads();
             for (int i = 0; i < np; i++) {
-                sel_pick_list(st, 2 * picks[i], p, idbits, sv.mode, sv.m, lds);
-                sel_pick_list(st, 2 * picks[i] + 1, p, idbits, sv.mode, sv.m, lds);
+                sel_pick_list(st, 2 * picks[i], p, idbits, sv.mode, sv.m, lds, clip);
+                sel_pick_list(st, 2 * picks[i] + 1, p, idbits, sv.mode, sv.m, lds, clip);
             }
         }
         __syncthreads();
@@ -755,7 +761,7 @@ __device__ void seg_tickets_pick(int32_t N, int p, int32_t nlists, int idbits, c
 // when there are few lists, the last one of each segment when there are many.
 __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_t nlists, int idbits,
                                                         SelView sv, SelState st, int fused,
-                                                        const int32_t *go)
+                                                        const int32_t *go, int32_t clip)
 {
     __shared__ uint32_t h[2 * kBins];
     __shared__ int64_t lds[16];
@@ -831,7 +837,7 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
     }
     if (!fused) return;
     if (fused == 2) {
-        seg_tickets_pick(N, p, nlists, idbits, sv, st, v0, lds);
+        seg_tickets_pick(N, p, nlists, idbits, sv, st, v0, lds, clip);
         return;
     }
     // ticket: the last workgroup sees every histogram
@@ -844,19 +850,19 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
     }
     __syncthreads();
     if (!last) return;
-    for (int32_t c = 0; c < nlists; c++) sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds);
+    for (int32_t c = 0; c < nlists; c++) sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds, clip);
     if (threadIdx.x == 0) st.ctl[1] = 0;
 }
 
 __global__ __launch_bounds__(kBlock) void k_select_pick(int32_t nlists, int p, int idbits, SelView sv,
-                                                        SelState st, const int32_t *go)
+                                                        SelState st, const int32_t *go, int32_t clip)
 {
     __shared__ int64_t lds[16];
     if (go && *go == 0) return;
     if (p > 0 && st.ctl[0] <= 0) return;
     int32_t c = blockIdx.x;
     if (c >= nlists) return;
-    sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds);
+    sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds, clip);
 }
 
 __device__ __forceinline__ bool sel_chosen(int64_t v, const SelView &sv, const SelState &st)
@@ -1149,7 +1155,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(int32_t N, SelView sv, SelSta
         if (v >= N || !sel_chosen(v, sv, st)) return;
         int32_t s = sv.nseg[v];
         int32_t at = atomicAdd(&ccount[s], 1);
-        cand[(int64_t)s * stride + at] = gain_order_key(sv.gain[v], (uint32_t)v);
+        if (at < stride) cand[(int64_t)s * stride + at] = gain_order_key(sv.gain[v], (uint32_t)v);
         return;
     }
     // one segment: its lists' state once, one append atomic per wavefront
@@ -1165,7 +1171,7 @@ __global__ __launch_bounds__(kBlock) void k_gather(int32_t N, SelView sv, SelSta
                  sel_key(st.gmax[c], g, (uint32_t)(v - nb0), sv.idbits) <= st.kthr[c];
     }
     int32_t at = lds_wave_slot(chosen, &ccount[s0]);
-    if (at >= 0) cand[(int64_t)s0 * stride + at] = gain_order_key(g, (uint32_t)v);
+    if (at >= 0 && at < stride) cand[(int64_t)s0 * stride + at] = gain_order_key(g, (uint32_t)v);
 }
 
 // ---- per-round modes: also reset the selection state of the lists --------------------------
