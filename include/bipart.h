@@ -202,6 +202,11 @@ typedef struct {
     int32_t fuse_max_pins;         /* segments of at most 8192 nodes and this many pins run their
                                       whole balance step in one workgroup, with no launch per
                                       round; 0: never (default 131072) */
+    int32_t chunk_select_max_nodes; /* levels too large for the one-workgroup selection whose
+                                      segments all have at most this many nodes (capped at
+                                      131072) select each balance round's nodes in chunks of
+                                      16384 nodes, one workgroup each, merged per segment;
+                                      0: never (default 131072) */
 } bp_schedule;
 
 /* Fills *s with the defaults above. */

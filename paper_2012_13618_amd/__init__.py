@@ -85,7 +85,7 @@ class ReqStats(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("incremental_min_pins", ctypes.c_int32), ("seg_select_max_nodes", ctypes.c_int32),
                 ("round_chunk_max", ctypes.c_int32), ("fused_pick_lists", ctypes.c_int32),
-                ("fuse_max_pins", ctypes.c_int32)]
+                ("fuse_max_pins", ctypes.c_int32), ("chunk_select_max_nodes", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

@@ -408,6 +408,15 @@ static bool seg_path(const Ctx &cx, const Level &L, int kind)
     return L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, cap);
 }
 
+// Whether a level's balance selections run in chunks (k_seg_select in chunk
+// mode, then k_bal_merge): segments too large for one workgroup, but of at
+// most kChunkMax chunks.
+static bool chunk_path(const Ctx &cx, const Level &L)
+{
+    return !seg_path(cx, L, 1) && cx.sched.chunk_select_max_nodes > 0 &&
+           L.maxseg_nodes <= std::min<int64_t>(cx.sched.chunk_select_max_nodes, (int64_t)kChunkMax * kChunkNodes);
+}
+
 // Selection and flip of the chosen nodes (Algorithm 3 rounds, Algorithm 5
 // swaps): one workgroup per segment when every segment is small, else the
 // multi-workgroup passes and a flip launch.
@@ -419,11 +428,11 @@ static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, co
         if (L.maxseg_nodes <= seg_select_max<0, kSegThreadsSmall>())
             launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                    L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
-                   bf, go, (uint8_t *)nullptr);
+                   bf, go, (uint8_t *)nullptr, ChunkArgs{});
         else
             launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreads>, L.S, kSegThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
-                   bf, go, (uint8_t *)nullptr);
+                   bf, go, (uint8_t *)nullptr, ChunkArgs{});
         return;
     }
     run_select(cx, L, sg, gain, go);
@@ -576,6 +585,17 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     }
     BalFinish bf{sg.mode, L.nw, sg.need, sg.room, L.side, (unsigned long long *)sg.w, sg.done, sg.stuck, ml,
                  sg.go, sg.bal_moved, sg.st.rsel};
+    // chunked selections: the level's chunk table and the chunks' lists
+    bool chunk = chunk_path(cx, L);
+    ChunkArgs ca{};
+    int64_t nct = 0;
+    if (chunk) {
+        nct = ceil_div(L.N, kChunkNodes) + L.S;
+        int32_t *tseg = ar.get<int32_t>(nct), *tbeg = ar.get<int32_t>(nct), *tcnt = ar.get<int32_t>(1);
+        ca = ChunkArgs{tseg, tbeg, tcnt, ar.get<uint64_t>((int64_t)L.S * kChunkMax * kChunkKeys),
+                       ar.get<int32_t>((int64_t)L.S * kChunkMax)};
+        launch(lc, "balance", 0.0, k_chunk_table, 1, 1024, 0, L.S, (const int32_t *)L.nbase, tseg, tbeg, tcnt);
+    }
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
     int64_t ugrid = std::max<int64_t>(1, std::min<int64_t>(ceil_div(nbits, kUpdWords), 2048));
     // profiling: the gain update counts its data-dependent bytes on the device
@@ -590,7 +610,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go, ri);
         bool seg = seg_path(cx, L, 1);
         if (ri == 0 || !incr) {
-            run_gains(cx, L, sg, gain, !seg, gc);
+            run_gains(cx, L, sg, gain, !seg && !chunk, gc);
         } else {
             launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
                    (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
@@ -599,7 +619,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
                    (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
                    (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count, ubytes);
-            if (!seg)
+            if (!seg && !chunk)
                 launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
@@ -609,15 +629,23 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
             if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsSmall>())
                 launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                        L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved);
+                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
             else if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsBal>())
                 launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsBal>, L.S, kSegThreadsBal, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved);
+                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
             else
                 launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreads>, L.S, kSegThreads, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved);
+                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
+            return;
+        }
+        if (chunk) {
+            launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kChunkThreads, true>, nct, kChunkThreads, 0, L.S,
+                   sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf,
+                   gc, ml.moved, ca);
+            launch(lc, "balance", 0.0, k_bal_merge, L.S, 1024, 0, L.S, (const int32_t *)L.nbase,
+                   (const int32_t *)sg.m, ca, bf, gc);
             return;
         }
         run_select(cx, L, sg, gain, gc, sg.cand_stride);
@@ -1605,6 +1633,7 @@ static Schedule to_schedule(const bp_schedule *s)
     r.round_chunk_max = s->round_chunk_max;
     r.fused_pick_lists = s->fused_pick_lists;
     r.fuse_max_pins = s->fuse_max_pins;
+    r.chunk_select_max_nodes = s->chunk_select_max_nodes;
     return r;
 }
 
@@ -1615,13 +1644,14 @@ static void from_schedule(const Schedule &r, bp_schedule *s)
     s->round_chunk_max = r.round_chunk_max;
     s->fused_pick_lists = r.fused_pick_lists;
     s->fuse_max_pins = r.fuse_max_pins;
+    s->chunk_select_max_nodes = r.chunk_select_max_nodes;
 }
 
 static bool schedule_ok(const bp_schedule *s)
 {
     return s && s->incremental_min_pins >= 0 && s->seg_select_max_nodes >= 0 && s->round_chunk_max >= 1 &&
            s->round_chunk_max <= 64 && s->fused_pick_lists >= 0 && s->fused_pick_lists <= 4096 &&
-           s->fuse_max_pins >= 0;
+           s->fuse_max_pins >= 0 && s->chunk_select_max_nodes >= 0;
 }
 
 void bp_schedule_default(bp_schedule *s)
@@ -1694,7 +1724,8 @@ bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const
     for (int32_t inc : {1 << 16, 1 << 18, 1 << 20, INT32_MAX})
         for (int32_t seg : {0, 4096, 16384, 32768})
             for (int32_t chunk : {16, 32})
-                cand.push_back(Schedule{inc, seg, chunk, base.fused_pick_lists, base.fuse_max_pins});
+                cand.push_back(
+                    Schedule{inc, seg, chunk, base.fused_pick_lists, base.fuse_max_pins, base.chunk_select_max_nodes});
     double best_t = 1e300;
     Schedule best_s = base;
     for (const Schedule &sc : cand) {

@@ -888,6 +888,21 @@ template <int KIND, int TH> constexpr int seg_items() { return KIND == 0 ? 16 : 
 template <int KIND, int TH> constexpr int32_t seg_select_max() { return TH * seg_items<KIND, TH>(); }
 constexpr int kSegKeys = 256;                           // balance candidates: ceil(sqrt n) <= 182
 
+// Balance selection of mid-size segments in chunks: each chunk of up to
+// kChunkNodes nodes of a segment (1024 threads, 16 nodes each) orders its
+// best ceil(sqrt n) nodes, then one workgroup per segment merges the chunks'
+// lists.  The union holds the segment's best ceil(sqrt n), so the merge's
+// first ones are those of the whole segment.
+constexpr int kChunkThreads = 1024;
+constexpr int32_t kChunkNodes = 16384;
+constexpr int kChunkMax = 8;       // chunks per segment: segments up to 131072 nodes
+constexpr int kChunkKeys = 512;    // per chunk: ceil(sqrt 131072) = 363 at most
+struct ChunkArgs {
+    const int32_t *seg, *beg, *count;  // chunk table: segment, first node; count[0] chunks
+    uint64_t *cand;                    // [S][kChunkMax][kChunkKeys]: each chunk's best, ascending
+    int32_t *ccnt;                     // [S][kChunkMax]: how many
+};
+
 // One workgroup per segment of at most seg_select_max<KIND, TH>() nodes: each list's
 // r-th key by the same 12-bit radix select as the multi-workgroup passes,
 // with the segment's gains in registers and the histogram in LDS, then the
@@ -896,22 +911,40 @@ constexpr int kSegKeys = 256;                           // balance candidates: c
 // of the over-weight side (by counting) and one wavefront takes the balance
 // prefix (Algorithm 5).  The chosen set is the one the multi-workgroup path
 // chooses: the same keys, the same r.
-template <int KIND, int TH>
-__global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits,
+//
+// CH (kind 1 only): one workgroup per chunk of the chunk table instead, whose
+// ordered best nodes go to ca for k_bal_merge; node ids are then local to the
+// chunk, which keeps the keys short.
+template <int KIND, int TH, bool CH = false>
+__global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits_lv,
                                                            const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
-                                                           const int32_t *go, uint8_t *moved)
+                                                           const int32_t *go, uint8_t *moved, ChunkArgs ca)
 {
-    constexpr int kSegItems = seg_items<KIND, TH>();
+    static_assert(!CH || (KIND == 1 && TH * 16 == kChunkNodes), "chunks: balance, 16 nodes a thread");
+    constexpr int kSegItems = CH ? 16 : seg_items<KIND, TH>();
+    constexpr int32_t kCap = TH * kSegItems;
+    constexpr int kKeys = CH ? kChunkKeys : kSegKeys;
     __shared__ uint32_t hist[kBins];
     __shared__ int64_t lds64[16];
     __shared__ int32_t sbin, sbefore, sin_;
-    __shared__ uint64_t keys[kSegKeys], sorted[KIND == 1 ? kSegKeys : 1];
-    __shared__ uint8_t sdl[seg_select_max<KIND, TH>()];  // the segment's sides
+    __shared__ uint64_t keys[kKeys], sorted[KIND == 1 ? kKeys : 1];
+    __shared__ uint8_t sdl[kCap];  // the segment's sides
     __shared__ int32_t nkeys;
     if (go && *go == 0) return;
-    int32_t s = blockIdx.x;
-    int32_t a0 = sv.nbase[s], n = sv.nbase[s + 1] - a0;
+    int32_t s, a0, n;
+    if (CH) {
+        int32_t ci = blockIdx.x;
+        if (ci >= ca.count[0]) return;
+        s = ca.seg[ci];
+        a0 = ca.beg[ci];
+        n = min(sv.nbase[s + 1] - a0, kChunkNodes);
+    } else {
+        s = blockIdx.x;
+        a0 = sv.nbase[s];
+        n = sv.nbase[s + 1] - a0;
+    }
+    const int idbits = CH ? bitlen_u32((uint32_t)max(n - 1, 0)) : idbits_lv;
     // the previous round's move marks, in every segment (the gain update has used them)
     if (moved)
         for (int32_t i = threadIdx.x; i < n; i += TH) moved[a0 + i] = 0;
@@ -928,7 +961,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         const uint8_t *sp = sv.side + a0;
         int32_t off0 = (int32_t)((uintptr_t)sp & 3), nw = (off0 + n + 3) >> 2;
         const uint32_t *wp = (const uint32_t *)(sp - off0);
-        constexpr int kW = seg_select_max<KIND, TH>() / 4 / TH + 1;
+        constexpr int kW = kCap / 4 / TH + 1;
         uint32_t xw[kW];
 #pragma unroll
         for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nw - 1)];
@@ -1060,7 +1093,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
             }
         }
     }
-    if (threadIdx.x == 0) {
+    if (!CH && threadIdx.x == 0) {
         st.rsel[2 * s] = rr[0];
         st.rsel[2 * s + 1] = rr[1];
     }
@@ -1103,7 +1136,131 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     __syncthreads();
     int32_t cnt = nkeys;
     block_rank_sort(keys, sorted, cnt);
+    if (CH) {
+        int32_t gi = (a0 - sv.nbase[s]) / kChunkNodes;
+        uint64_t *dst = ca.cand + ((int64_t)s * kChunkMax + gi) * kChunkKeys;
+        for (int32_t i = threadIdx.x; i < cnt; i += TH) dst[i] = sorted[i];
+        if (threadIdx.x == 0) ca.ccnt[s * kChunkMax + gi] = cnt;
+        return;
+    }
     if (threadIdx.x < 64) bal_take_prefix_wave(s, sorted, cnt, bf);
+}
+
+// The chunk table of a level: segment s gets ceil(n_s / kChunkNodes)
+// consecutive entries (its segment and first node).  One workgroup.
+__global__ __launch_bounds__(1024) void k_chunk_table(int32_t S, const int32_t *nbase, int32_t *seg,
+                                                      int32_t *beg, int32_t *count)
+{
+    __shared__ int32_t lds[16];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (int32_t base = 0; base < S; base += blockDim.x) {
+        int32_t s = base + (int32_t)threadIdx.x;
+        int32_t a = s < S ? nbase[s] : 0, n = s < S ? nbase[s + 1] - a : 0;
+        int32_t c = (n + kChunkNodes - 1) / kChunkNodes, tot;
+        int32_t at = block_excl_scan(c, lds, &tot) + carry;
+        for (int32_t i = 0; i < c; i++) {
+            seg[at + i] = s;
+            beg[at + i] = a + i * kChunkNodes;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry += tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) count[0] = carry;
+}
+
+// One workgroup per balancing segment of the chunked selection: each node of
+// the chunks' ascending lists is ranked among all of them (its index in its
+// own list plus, by binary search, the smaller keys of every other list); the
+// first min(total, m) in order are the segment's chosen nodes.  Then the
+// balance prefix (Algorithm 5) over them, with their weights staged in LDS by
+// the ranking threads: one scan, as the chosen nodes fit the workgroup.
+__global__ __launch_bounds__(1024) void k_bal_merge(int32_t S, const int32_t *nbase, const int32_t *m,
+                                                    ChunkArgs ca, BalFinish bf, const int32_t *go)
+{
+    static_assert(kChunkKeys <= 1024, "the chosen nodes fit the workgroup");
+    __shared__ uint64_t a[kChunkMax * kChunkKeys];
+    __shared__ uint64_t out[kChunkKeys];
+    __shared__ int64_t wts[kChunkKeys];
+    __shared__ int64_t lds64[16];
+    __shared__ int32_t cnt[kChunkMax], p1s, fits;
+    __shared__ int64_t movedw;
+    if (go && *go == 0) return;
+    int32_t s = blockIdx.x;
+    if (!bf.mode[s]) return;
+    int32_t n = nbase[s + 1] - nbase[s];
+    int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
+    const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
+    // every slot of the segment's lists (past a list's count: unused), with the counts
+    const uint64_t *src = ca.cand + (int64_t)s * kChunkMax * kChunkKeys;
+    for (int32_t f = tid; f < nslot; f += 1024) a[f] = src[f];
+    if (tid < kChunkMax) cnt[tid] = tid < ng ? ca.ccnt[s * kChunkMax + tid] : 0;
+    if (tid == 0) movedw = 0;
+    __syncthreads();
+    int32_t tot = 0;
+    for (int q = 0; q < ng; q++) tot += cnt[q];
+    int32_t take = min(tot, m[s]);
+    for (int32_t f = tid; f < nslot; f += 1024) {
+        int q = f / kChunkKeys;
+        int32_t i = f % kChunkKeys;
+        if (i >= cnt[q]) continue;
+        uint64_t x = a[f];
+        int32_t rank = i;
+        for (int o = 0; o < ng && rank < take; o++) {
+            if (o == q) continue;
+            const uint64_t *b = a + o * kChunkKeys;
+            int32_t lo = 0, hi = cnt[o];
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (b[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            rank += lo;
+        }
+        if (rank < take) {
+            out[rank] = x;
+            wts[rank] = bf.nw[(uint32_t)(x & 0xffffffffu)];
+        }
+    }
+    if (tid == 0) {
+        p1s = take;
+        fits = 0;
+    }
+    __syncthreads();
+    // the shortest prefix reaching the excess, cut to what fits the room
+    // (weights are non-negative: prefix weights ascend)
+    int h = (bf.mode[s] & kList1) ? 1 : 0;
+    int64_t nd = bf.need[s], rm = bf.room[s];
+    int64_t w = tid < take ? wts[tid] : 0, wt;
+    int64_t incl = block_excl_scan(w, lds64, &wt) + w;
+    if (tid < take && incl >= nd) atomicMin(&p1s, tid + 1);
+    if (tid < take && incl <= rm) atomicAdd(&fits, 1);
+    __syncthreads();
+    int32_t p = min(p1s, fits);
+    if (tid < p) bf.side[(uint32_t)(out[tid] & 0xffffffffu)] = (uint8_t)(1 - h);
+    if (p > 0 && tid == p - 1) movedw = incl;
+    if (bf.ml.cnode) log_moves(p, out, bf.ml, lds64);
+    __syncthreads();
+    if (tid == 0) {
+        int64_t moved = movedw;
+        if (p == 0) {
+            bf.stuck[s] = 1;
+            bf.done[s] = 1;
+        } else {
+            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
+            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
+            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            bf.bal_moved[2 * s] = mw;
+            bf.bal_moved[2 * s + 1] = mr;
+            int64_t rest = nd - moved;
+            if (rest > 0) {
+                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
+                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
+            }
+        }
+    }
 }
 
 // ---- moves ---------------------------------------------------------------------------------

@@ -168,13 +168,18 @@ def test_schedules_never_change_results(bp):
     old = bp.schedule_get()
     try:
         # fuse_max_pins 0: no segment balances in one workgroup; 1 << 30: every
-        # segment of <= 8192 nodes does; 5000: a mix within one level
-        for inc, seg, chunk, fused, fuse in [(0, 0, 1, 0, 0), (1 << 30, 16384, 64, 4096, 1 << 30),
-                                             (1 << 16, 4096, 7, 2, 5000), (2 ** 31 - 1, 100, 3, 64, 1 << 17)]:
+        # segment of <= 8192 nodes does; 5000: a mix within one level.
+        # chunk_select_max_nodes 0: balance selections of large segments on the
+        # multi-workgroup passes; else in chunks up to that size
+        for inc, seg, chunk, fused, fuse, csel in [(0, 0, 1, 0, 0, 0),
+                                                   (1 << 30, 16384, 64, 4096, 1 << 30, 1 << 17),
+                                                   (1 << 16, 4096, 7, 2, 5000, 50000),
+                                                   (2 ** 31 - 1, 100, 3, 64, 1 << 17, 20000)]:
             s = bp.schedule_default()
             s.incremental_min_pins, s.seg_select_max_nodes, s.round_chunk_max, s.fused_pick_lists = \
                 inc, seg, chunk, fused
             s.fuse_max_pins = fuse
+            s.chunk_select_max_nodes = csel
             bp.schedule_set(s)
             say("schedule", s.as_dict())
             parts, cuts, _, _ = bp.partition_batch_device(dev, ks, es)
