@@ -204,9 +204,9 @@ typedef struct {
                                       round; 0: never (default 131072) */
     int32_t chunk_select_max_nodes; /* levels too large for the one-workgroup selection whose
                                       segments all have at most this many nodes (capped at
-                                      131072) select each balance round's nodes in chunks of
+                                      262144) select each balance round's nodes in chunks of
                                       16384 nodes, one workgroup each, merged per segment;
-                                      0: never (default 131072) */
+                                      0: never (default 262144) */
 } bp_schedule;
 
 /* Fills *s with the defaults above. */

@@ -408,6 +408,18 @@ static bool seg_path(const Ctx &cx, const Level &L, int kind)
     return L.maxseg_nodes <= std::min(cx.sched.seg_select_max_nodes, cap);
 }
 
+// Buffers of the chunked balance selection for levels of at most tab_n
+// chunk table entries (none when tab_n is 0).
+static void alloc_chunk_bufs(Arena &ar, Segs &sg, int64_t tab_n)
+{
+    sg.chunk_cand = nullptr;
+    sg.chunk_tab_n = tab_n;
+    if (tab_n == 0) return;
+    sg.chunk_cand = ar.get<uint64_t>((int64_t)sg.S * kChunkMax * kChunkKeys);
+    sg.chunk_ccnt = ar.get<int32_t>((int64_t)sg.S * kChunkMax);
+    sg.chunk_tab = ar.get<int32_t>(2 * tab_n + 1);
+}
+
 // Whether a level's balance selections run in chunks (k_seg_select in chunk
 // mode, then k_bal_merge): segments too large for one workgroup, but of at
 // most kChunkMax chunks.
@@ -585,15 +597,17 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     }
     BalFinish bf{sg.mode, L.nw, sg.need, sg.room, L.side, (unsigned long long *)sg.w, sg.done, sg.stuck, ml,
                  sg.go, sg.bal_moved, sg.st.rsel};
-    // chunked selections: the level's chunk table and the chunks' lists
+    // chunked selections: the level's chunk table (buffers of the whole
+    // bisection, sized for its largest level)
     bool chunk = chunk_path(cx, L);
     ChunkArgs ca{};
     int64_t nct = 0;
     if (chunk) {
         nct = ceil_div(L.N, kChunkNodes) + L.S;
-        int32_t *tseg = ar.get<int32_t>(nct), *tbeg = ar.get<int32_t>(nct), *tcnt = ar.get<int32_t>(1);
-        ca = ChunkArgs{tseg, tbeg, tcnt, ar.get<uint64_t>((int64_t)L.S * kChunkMax * kChunkKeys),
-                       ar.get<int32_t>((int64_t)L.S * kChunkMax)};
+        if (!sg.chunk_cand || nct > sg.chunk_tab_n)
+            throw Error(BP_ERR_DEVICE, "chunked selection buffers missing");
+        int32_t *tseg = sg.chunk_tab, *tbeg = sg.chunk_tab + sg.chunk_tab_n, *tcnt = sg.chunk_tab + 2 * sg.chunk_tab_n;
+        ca = ChunkArgs{tseg, tbeg, tcnt, sg.chunk_cand, sg.chunk_ccnt};
         launch(lc, "balance", 0.0, k_chunk_table, 1, 1024, 0, L.S, (const int32_t *)L.nbase, tseg, tbeg, tcnt);
     }
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));
@@ -727,6 +741,11 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     int32_t mmax = (int32_t)ceil_sqrt_i64(maxn);
     sg.cand_stride = next_pow2(std::max(mmax, kBalGather));
     sg.cand = ar.get<uint64_t>((int64_t)sg.S * sg.cand_stride);
+    // chunked balance selections, when some level takes them
+    int64_t tab_n = 0;
+    for (auto &x : lv)
+        if (chunk_path(cx, x)) tab_n = std::max<int64_t>(tab_n, ceil_div(x.N, kChunkNodes) + x.S);
+    alloc_chunk_bufs(ar, sg, tab_n);
     int32_t *gain = ar.get<int32_t>(lv[0].N);
     fill(lc, sg.st.hist, (int64_t)2 * sg.S * kBins, 0u);
     fill(lc, sg.st.ctl, 4, 0);
@@ -1920,6 +1939,7 @@ static Segs step_segs(Ctx &cx, Level &L, int32_t k0, int32_t k1, int64_t max0, i
     int32_t mm = (int32_t)ceil_sqrt_i64(L.N);
     sg.cand_stride = next_pow2(std::max(mm, kBalGather));
     sg.cand = cx.ar->get<uint64_t>(sg.cand_stride);
+    alloc_chunk_bufs(*cx.ar, sg, chunk_path(cx, L) ? ceil_div(L.N, kChunkNodes) + L.S : 0);
     return sg;
 }
 

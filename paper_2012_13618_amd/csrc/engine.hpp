@@ -22,7 +22,7 @@ struct Schedule {
     int32_t round_chunk_max = 32;
     int32_t fused_pick_lists = 8;
     int32_t fuse_max_pins = 1 << 17;
-    int32_t chunk_select_max_nodes = 1 << 17;
+    int32_t chunk_select_max_nodes = 1 << 18;
 };
 
 Schedule current_schedule();  // the process-wide schedule (a copy, taken under a lock)

@@ -96,6 +96,10 @@ struct Segs {
     int32_t *ccount;          // balance candidates per segment
     uint64_t *cand;           // [S * cand_stride]
     int32_t cand_stride = 0;
+    uint64_t *chunk_cand = nullptr;  // chunked balance selection: [S][kChunkMax][kChunkKeys], or null
+    int32_t *chunk_ccnt = nullptr;   // [S][kChunkMax]
+    int32_t *chunk_tab = nullptr;    // chunk table: segment, first node ([2][chunk_tab_n]), count
+    int64_t chunk_tab_n = 0;
     int32_t *go;              // [8] round counters: [1] last count, [2] rounds run, [3] estimate,
                               // [4..6] per-round active counts (round i uses slot 4 + i % 3)
     SelState st;              // selection state of the 2S lists

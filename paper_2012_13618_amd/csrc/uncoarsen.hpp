@@ -895,8 +895,8 @@ constexpr int kSegKeys = 256;                           // balance candidates: c
 // first ones are those of the whole segment.
 constexpr int kChunkThreads = 1024;
 constexpr int32_t kChunkNodes = 16384;
-constexpr int kChunkMax = 8;       // chunks per segment: segments up to 131072 nodes
-constexpr int kChunkKeys = 512;    // per chunk: ceil(sqrt 131072) = 363 at most
+constexpr int kChunkMax = 16;      // chunks per segment: segments up to 262144 nodes
+constexpr int kChunkKeys = 512;    // per chunk: ceil(sqrt 262144) = 512 at most
 struct ChunkArgs {
     const int32_t *seg, *beg, *count;  // chunk table: segment, first node; count[0] chunks
     uint64_t *cand;                    // [S][kChunkMax][kChunkKeys]: each chunk's best, ascending

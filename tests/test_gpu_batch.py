@@ -172,7 +172,7 @@ def test_schedules_never_change_results(bp):
         # chunk_select_max_nodes 0: balance selections of large segments on the
         # multi-workgroup passes; else in chunks up to that size
         for inc, seg, chunk, fused, fuse, csel in [(0, 0, 1, 0, 0, 0),
-                                                   (1 << 30, 16384, 64, 4096, 1 << 30, 1 << 17),
+                                                   (1 << 30, 16384, 64, 4096, 1 << 30, 1 << 18),
                                                    (1 << 16, 4096, 7, 2, 5000, 50000),
                                                    (2 ** 31 - 1, 100, 3, 64, 1 << 17, 20000)]:
             s = bp.schedule_default()

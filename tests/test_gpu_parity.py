@@ -297,19 +297,19 @@ def _zero_weights(h, every=3):
     return I.Hypergraph(h.num_nodes, h.offsets, h.pins, nw, h.hedge_w, name=h.name + "-w0")
 
 
-CHUNKS = 1 << 17  # the chunked selection's default (and largest) segment size
+CHUNKS = 1 << 18  # the chunked selection's default (and largest) segment size
 
 
 @pytest.mark.parametrize("n,fuse,chunk,zw", [
     (8192, 1 << 30, CHUNKS, False), (8193, 1 << 30, CHUNKS, False), (20000, 0, CHUNKS, False),
     (30000, 0, CHUNKS, False), (6000, 1 << 30, CHUNKS, True), (40000, 0, CHUNKS, False),
-    (40000, 0, 0, False), (131072, 0, CHUNKS, False), (131073, 0, CHUNKS, False), (50000, 0, CHUNKS, True)],
+    (40000, 0, 0, False), (CHUNKS, 0, CHUNKS, False), (CHUNKS + 1, 0, CHUNKS, False), (50000, 0, CHUNKS, True)],
     ids=["fused-at-limit", "fused-over-limit", "select-768", "select-1024", "fused-zero-w", "chunked",
          "multi-workgroup", "chunked-at-limit", "chunked-over-limit", "chunked-zero-w"])
 def test_balance_size_limits(bp, n, fuse, chunk, zw):
     """Balance steps at the size limits of the one-workgroup kernels (the fused
     rounds at 8192 nodes, the 768- and 1024-thread selections, the chunked
-    selection at 8 chunks of 16384 nodes), on the multi-workgroup passes, and
+    selection at 16 chunks of 16384 nodes), on the multi-workgroup passes, and
     with zero-weight nodes, against the oracle."""
     import torch
     h = I.random_small(n, int(1.1 * n), 2, 12, 40 + n % 97, weighted_nodes=True, weighted_hedges=True)
