@@ -267,17 +267,33 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
         for (int32_t q = wv; q < nbig; q += blockDim.x >> 6) {
             int32_t e = bigq[q];
             int32_t b = off[e], d = off[e + 1] - b;
+            int32_t w = hw[e];
+            int2 oc = cc[e];
+            // up to kUpdWaveMax / 64 pins a lane, held in registers: their ids,
+            // then their sides and move flags, each group of loads in flight
+            // together, and used by both the count and the deltas
+            constexpr int kR = kUpdWaveMax / 64;
+            int32_t u[kR];
+            uint32_t sn[kR], so[kR];
+#pragma unroll
+            for (int k = 0; k < kR; k++) u[k] = pins[b + min(lane + 64 * k, d - 1)];
+#pragma unroll
+            for (int k = 0; k < kR; k++) {
+                sn[k] = side[u[k]];
+                so[k] = moved[u[k]];
+            }
             int32_t n1 = 0;
-#pragma unroll 4
-            for (int j = lane; j < d; j += 64) n1 += side[pins[b + j]];
+#pragma unroll
+            for (int k = 0; k < kR; k++)
+                if (lane + 64 * k < d) n1 += sn[k];
             n1 = wave_sum(n1);
-            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
-#pragma unroll 4
-            for (int j = lane; j < d; j += 64) {
-                int32_t u = pins[b + j];
-                int sn = side[u], so = sn ^ moved[u];
-                int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
-                if (delta) add_gain(u, delta, bigslot, slot, gain);
+            int2 nc = hedge_contrib_value(w, d, n1);
+#pragma unroll
+            for (int k = 0; k < kR; k++) {
+                if (lane + 64 * k >= d) continue;
+                uint32_t o = sn[k] ^ so[k];
+                int32_t delta = (sn[k] ? nc.y : nc.x) - (o ? oc.y : oc.x);
+                if (delta) add_gain(u[k], delta, bigslot, slot, gain);
             }
             if (lane == 0) cc[e] = nc;
         }
