@@ -227,11 +227,60 @@ __device__ __forceinline__ bool fuse_fits(const FuseArgs &fa, int32_t s)
 // from side h to 1 - h in the last round: add new minus old contribution.
 // Lanes lane, lane + stride, ... of the hyperedge's pins (stride 1: a thread
 // alone, 64: a wavefront).
+// The same for d <= R * stride: the pins are loaded once, all in flight
+// together, and kept in registers for both the count and the deltas.
+template <int R>
+__device__ __forceinline__ void fuse_hedge_regs(int32_t e, int32_t b, int32_t d, bool full, int h, int lane,
+                                                int stride, int32_t a0, const FuseArgs &fa, const uint8_t *sd,
+                                                const uint32_t *mv, int32_t *g)
+{
+    int32_t u[R];
+#pragma unroll
+    for (int k = 0; k < R; k++) u[k] = fa.pins[b + min(lane + k * stride, d - 1)] - a0;
+    int32_t n1 = 0, km = 0;
+#pragma unroll
+    for (int k = 0; k < R; k++)
+        if (lane + k * stride < d) {
+            n1 += sd[u[k]];
+            if (!full) km += (mv[u[k] >> 5] >> (u[k] & 31)) & 1;
+        }
+    if (stride > 1) {
+        n1 = wave_sum(n1);
+        km = wave_sum(km);
+    }
+    int32_t w = fa.hw[e];
+    int2 cn = hedge_contrib_value(w, d, n1);
+    int2 co = make_int2(0, 0);
+    if (!full) {
+        if (km == 0) return;
+        co = hedge_contrib_value(w, d, h ? n1 + km : n1 - km);
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        if (lane + k * stride >= d) continue;
+        int sn = sd[u[k]];
+        int so = full ? sn : (sn ^ (int)((mv[u[k] >> 5] >> (u[k] & 31)) & 1));
+        int32_t delta = (sn ? cn.y : cn.x) - (full ? 0 : (so ? co.y : co.x));
+        if (delta) atomicAdd(&g[u[k]], delta);
+    }
+}
+
 __device__ __forceinline__ void fuse_hedge(int32_t e, bool full, int h, int lane, int stride, int32_t a0,
                                            const FuseArgs &fa, const uint8_t *sd, const uint32_t *mv,
                                            int32_t *g)
 {
     int32_t b = fa.off[e], d = fa.off[e + 1] - b;
+    // pins in registers when few (a thread: up to 4, or up to kFuseSmallDeg;
+    // a wavefront: up to 512)
+    if (stride == 1 && d <= kFuseSmallDeg) {
+        if (__ballot(d > 4) == 0) fuse_hedge_regs<4>(e, b, d, full, h, lane, 1, a0, fa, sd, mv, g);
+        else fuse_hedge_regs<kFuseSmallDeg>(e, b, d, full, h, lane, 1, a0, fa, sd, mv, g);
+        return;
+    }
+    if (stride == 64 && d <= 512) {
+        fuse_hedge_regs<8>(e, b, d, full, h, lane, 64, a0, fa, sd, mv, g);
+        return;
+    }
     int32_t n1 = 0, km = 0;
 #pragma unroll 4
     for (int32_t i = lane; i < d; i += stride) {
