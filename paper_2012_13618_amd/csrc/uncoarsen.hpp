@@ -165,6 +165,7 @@ constexpr int kUpdWords = 64;                // bitmap words a workgroup sweeps 
 constexpr int kUpdChunk = 8;                 // ... as 8 chunks of this many words
 constexpr int kUpdQueue = kUpdWords * 32;  // hyperedges those words can hold
 constexpr int kUpdWaveMax = 512;           // larger marked hyperedges: the whole workgroup
+constexpr int kUpdHugeRegs = 8;            // ... whose pins fit kUpdHugeRegs a thread in registers
 
 // recount of hyperedge e (pins b .. b + d, d <= kSmallMax) after a round:
 // its new contribution, with each pin's gain change added
@@ -301,11 +302,41 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
         for (int32_t q = 0; q < nhuge; q++) {
             int32_t e = bigq[kUpdQueue - 1 - q];
             int32_t b = off[e], d = off[e + 1] - b;
+            int2 oc = cc[e];
+            int32_t w = hw[e];
+            if (d <= kUpdHugeRegs * kBlock) {
+                // up to kUpdHugeRegs pins a thread in registers (loaded once, in
+                // flight together) for both the count and the deltas
+                int32_t u[kUpdHugeRegs];
+                uint32_t sn[kUpdHugeRegs], so[kUpdHugeRegs];
+#pragma unroll
+                for (int k = 0; k < kUpdHugeRegs; k++) u[k] = pins[b + min((int32_t)threadIdx.x + kBlock * k, d - 1)];
+#pragma unroll
+                for (int k = 0; k < kUpdHugeRegs; k++) {
+                    sn[k] = side[u[k]];
+                    so[k] = moved[u[k]];
+                }
+                int32_t n1 = 0;
+#pragma unroll
+                for (int k = 0; k < kUpdHugeRegs; k++)
+                    if ((int32_t)threadIdx.x + kBlock * k < d) n1 += sn[k];
+                n1 = block_sum(n1, lds);
+                int2 nc = hedge_contrib_value(w, d, n1);
+#pragma unroll
+                for (int k = 0; k < kUpdHugeRegs; k++) {
+                    if ((int32_t)threadIdx.x + kBlock * k >= d) continue;
+                    int32_t delta = (sn[k] ? nc.y : nc.x) - ((sn[k] ^ so[k]) ? oc.y : oc.x);
+                    if (delta) add_gain(u[k], delta, bigslot, slot, gain);
+                }
+                __syncthreads();  // every thread has read the old contribution
+                if (threadIdx.x == 0) cc[e] = nc;
+                continue;
+            }
             int32_t n1 = 0;
 #pragma unroll 4
             for (int j = threadIdx.x; j < d; j += blockDim.x) n1 += side[pins[b + j]];
             n1 = block_sum(n1, lds);
-            int2 nc = hedge_contrib_value(hw[e], d, n1), oc = cc[e];
+            int2 nc = hedge_contrib_value(w, d, n1);
 #pragma unroll 4
             for (int j = threadIdx.x; j < d; j += blockDim.x) {
                 int32_t u = pins[b + j];
