@@ -950,6 +950,21 @@ struct ChunkArgs {
     int32_t *ccnt;                     // [S][kChunkMax]: how many
 };
 
+// Zeroes p[0, n) with 16-byte stores (byte stores at the unaligned ends); the
+// threads of one workgroup, TH of them.
+template <int TH> __device__ __forceinline__ void clear_bytes(uint8_t *p, int32_t n)
+{
+    int32_t t = threadIdx.x;
+    int32_t head = (int32_t)((16 - ((uintptr_t)p & 15)) & 15);
+    head = head < n ? head : n;
+    if (t < head) p[t] = 0;
+    int32_t nv = (n - head) >> 4;
+    uint4 *q = (uint4 *)(p + head);
+    for (int32_t i = t; i < nv; i += TH) q[i] = make_uint4(0u, 0u, 0u, 0u);
+    int32_t t0 = head + (nv << 4);
+    if (t < n - t0) p[t0 + t] = 0;
+}
+
 // One workgroup per segment of at most seg_select_max<KIND, TH>() nodes: each list's
 // r-th key by the same 12-bit radix select as the multi-workgroup passes,
 // with the segment's gains in registers and the histogram in LDS, then the
@@ -992,39 +1007,42 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         n = sv.nbase[s + 1] - a0;
     }
     const int idbits = CH ? bitlen_u32((uint32_t)max(n - 1, 0)) : idbits_lv;
-    // the previous round's move marks, in every segment (the gain update has used them)
-    if (moved)
-        for (int32_t i = threadIdx.x; i < n; i += TH) moved[a0 + i] = 0;
     uint8_t md = sv.mode[s];
-    if (!md) return;
     int32_t g[kSegItems];
     uint64_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
     // per list: size and gain extremes, from the gains just loaded
     int32_t lc[2] = {0, 0}, lmax[2] = {INT32_MIN, INT32_MIN}, lmin[2] = {INT32_MAX, INT32_MAX};
-    if (n > 0) {
-        // the segment's sides staged in LDS by aligned 4-byte words (a word
-        // never leaves the memory page of the bytes it covers), then the gains
-        // (indices past the segment read its node 0): loads in flight together
-        const uint8_t *sp = sv.side + a0;
-        int32_t off0 = (int32_t)((uintptr_t)sp & 3), nw = (off0 + n + 3) >> 2;
-        const uint32_t *wp = (const uint32_t *)(sp - off0);
-        constexpr int kW = kCap / 4 / TH + 1;
-        uint32_t xw[kW];
+    // the segment's sides by aligned 4-byte words (a word never leaves the
+    // memory page of the bytes it covers) and its gains (indices past the
+    // segment read its node 0): loads in flight together
+    const uint8_t *sp = sv.side + a0;
+    int32_t off0 = (int32_t)((uintptr_t)sp & 3), nwd = (off0 + n + 3) >> 2;
+    const uint32_t *wp = (const uint32_t *)(sp - off0);
+    constexpr int kW = kCap / 4 / TH + 1;
+    uint32_t xw[kW];
+    if (md && n > 0) {
 #pragma unroll
-        for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nw - 1)];
+        for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nwd - 1)];
+#pragma unroll
+        for (int j = 0; j < kSegItems; j++) {
+            int32_t i = j * TH + (int32_t)threadIdx.x;
+            g[j] = sv.gain[a0 + (i < n ? i : 0)];
+        }
+    }
+    // the previous round's move marks, in every segment (the gain update has
+    // used them); stored after the loads are issued, so that none waits for them
+    if (moved) clear_bytes<TH>(moved + a0, n);
+    if (!md) return;
+    if (n > 0) {
+        // the sides staged in LDS
 #pragma unroll
         for (int q = 0; q < kW; q++) {
             int32_t w = q * TH + (int32_t)threadIdx.x;
 #pragma unroll
             for (int b = 0; b < 4; b++) {
                 int32_t i = 4 * w + b - off0;
-                if (w < nw && i >= 0 && i < n) sdl[i] = (uint8_t)(xw[q] >> (8 * b));
+                if (w < nwd && i >= 0 && i < n) sdl[i] = (uint8_t)(xw[q] >> (8 * b));
             }
-        }
-#pragma unroll
-        for (int j = 0; j < kSegItems; j++) {
-            int32_t i = j * TH + (int32_t)threadIdx.x;
-            g[j] = sv.gain[a0 + (i < n ? i : 0)];
         }
     }
     __syncthreads();
