@@ -303,9 +303,10 @@ CHUNKS = 1 << 18  # the chunked selection's default (and largest) segment size
 @pytest.mark.parametrize("n,fuse,chunk,zw", [
     (8192, 1 << 30, CHUNKS, False), (8193, 1 << 30, CHUNKS, False), (20000, 0, CHUNKS, False),
     (30000, 0, CHUNKS, False), (6000, 1 << 30, CHUNKS, True), (40000, 0, CHUNKS, False),
-    (40000, 0, 0, False), (CHUNKS, 0, CHUNKS, False), (CHUNKS + 1, 0, CHUNKS, False), (50000, 0, CHUNKS, True)],
+    (40000, 0, 0, False), (CHUNKS, 0, CHUNKS, False), (CHUNKS + 1, 0, CHUNKS, False), (50000, 0, CHUNKS, True),
+    (32769, 0, CHUNKS, False)],
     ids=["fused-at-limit", "fused-over-limit", "select-768", "select-1024", "fused-zero-w", "chunked",
-         "multi-workgroup", "chunked-at-limit", "chunked-over-limit", "chunked-zero-w"])
+         "multi-workgroup", "chunked-at-limit", "chunked-over-limit", "chunked-zero-w", "chunked-one-node-tail"])
 def test_balance_size_limits(bp, n, fuse, chunk, zw):
     """Balance steps at the size limits of the one-workgroup kernels (the fused
     rounds at 8192 nodes, the 768- and 1024-thread selections, the chunked
