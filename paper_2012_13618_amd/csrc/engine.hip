@@ -618,17 +618,18 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         ubytes = ar.get<unsigned long long>(1);
         fill(lc, ubytes, 1, 0ull);
     }
+    RoundBal rb{L.S, (const int32_t *)L.nbase, (const unsigned long long *)sg.w, (const int64_t *)sg.max0,
+                (const int64_t *)sg.max1, sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount};
     int64_t rounds = chunked_rounds(cx, sg, (int64_t)L.N + L.S + 2, true, [&](int32_t ri, const int32_t *gc) {
-        launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, L.S, (const int32_t *)L.nbase,
-               (const unsigned long long *)sg.w, (const int64_t *)sg.max0, (const int64_t *)sg.max1,
-               sg.done, sg.mode, sg.gmask, sg.m, sg.need, sg.room, sg.ccount, sg.st, sg.go, ri);
         bool seg = seg_path(cx, L, 1);
         if (ri == 0 || !incr) {
+            launch(lc, "round", 0.0, k_round_balance, gs, kBlock, 0, rb, sg.st, sg.go, ri);
             run_gains(cx, L, sg, gain, !seg && !chunk, gc);
         } else {
-            launch(lc, "log_hedges", 0.0, k_log_hedges, lg, kBlock, 0, (const int32_t *)ml.count,
-                   (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg, (const int32_t *)L.noff,
-                   (const int32_t *)L.inc, bits, gc);
+            // the round's test and the marking of the last round's moves: one launch
+            launch(lc, "round", 0.0, k_round_balance_log, gs + lg, kBlock, 0, gs, rb, sg.st, sg.go, ri,
+                   (const int32_t *)ml.count, (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg,
+                   (const int32_t *)L.noff, (const int32_t *)L.inc, bits);
             launch(lc, "gain_update", 0.0, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
                    (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,

@@ -106,16 +106,16 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
 // One wavefront per logged chunk of a moved node's incidences: marks each
 // hyperedge in the bitmap.  The chunk's hyperedges ascend, so lanes sharing a
 // bitmap word are adjacent and the first lane of each run sets the run's bits
-// with one atomic (none when they are all set already).
-__global__ __launch_bounds__(kBlock) void k_log_hedges(const int32_t *count, const int32_t *cnode,
-                                                       const int32_t *cbeg, const int32_t *noff,
-                                                       const int32_t *inc, uint32_t *bits, const int32_t *go)
+// with one atomic (none when they are all set already).  Here: blocks b of nb
+// (kBlock threads each) of the marking.
+__device__ __forceinline__ void log_hedges_blocks(int64_t b, int64_t nb, const int32_t *count, const int32_t *cnode,
+                                                  const int32_t *cbeg, const int32_t *noff, const int32_t *inc,
+                                                  uint32_t *bits)
 {
-    if (go && *go == 0) return;
     int32_t n = count[0];
     int lane = threadIdx.x & 63;
     const int64_t wpb = kBlock / 64;
-    for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * wpb) {
+    for (int64_t i = b * wpb + (threadIdx.x >> 6); i < n; i += nb * wpb) {
         int32_t v = cnode[i];
         int32_t j = cbeg[i] + lane, end = noff[v + 1];
         bool valid = j < end;
@@ -1476,12 +1476,27 @@ __global__ void k_round_refine(int32_t S, int32_t j, const int32_t *coarsest, ui
 }
 
 // Balance test per segment: the side over its bound, the excess, the room.
-__global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned long long *segw,
-                                const int64_t *max0, const int64_t *max1, uint8_t *done,
-                                uint8_t *mode, uint8_t *gmask, int32_t *m, int64_t *need,
-                                int64_t *room, int32_t *ccount, SelState st, int32_t *go, int32_t ri)
+struct RoundBal {
+    int32_t S;
+    const int32_t *nbase;
+    const unsigned long long *segw;
+    const int64_t *max0, *max1;
+    uint8_t *done, *mode, *gmask;
+    int32_t *m;
+    int64_t *need, *room;
+    int32_t *ccount;
+};
+
+__device__ __forceinline__ void round_balance_seg(int32_t s, const RoundBal &rb, SelState st, int32_t *go,
+                                                  int32_t ri)
 {
-    int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
+    int32_t S = rb.S;
+    const int32_t *nbase = rb.nbase;
+    const unsigned long long *segw = rb.segw;
+    const int64_t *max0 = rb.max0, *max1 = rb.max1;
+    uint8_t *done = rb.done, *mode = rb.mode, *gmask = rb.gmask;
+    int32_t *m = rb.m, *ccount = rb.ccount;
+    int64_t *need = rb.need, *room = rb.room;
     if (s == 0) st.ctl[0] = 2 * S;
     round_counters(go, ri, s);
     int32_t *cur = go + 4 + ri % 3;
@@ -1506,6 +1521,30 @@ __global__ void k_round_balance(int32_t S, const int32_t *nbase, const unsigned 
     mode[s] = md;
     gmask[s] = md ? 1 : 0;
     reset_lists(st, s);
+}
+
+__global__ void k_round_balance(RoundBal rb, SelState st, int32_t *go, int32_t ri)
+{
+    round_balance_seg(blockIdx.x * blockDim.x + threadIdx.x, rb, st, go, ri);
+}
+
+// A later balance round's test and the marking of the hyperedges of the nodes
+// the previous round moved, in one launch: they are independent (the test
+// reads the side weights, the marking the move log, both left by the previous
+// round).  Blocks [0, gs) test, the others mark, when the previous round had
+// anything to do.
+__global__ __launch_bounds__(kBlock) void k_round_balance_log(int64_t gs, RoundBal rb, SelState st, int32_t *go,
+                                                              int32_t ri, const int32_t *count,
+                                                              const int32_t *cnode, const int32_t *cbeg,
+                                                              const int32_t *noff, const int32_t *inc,
+                                                              uint32_t *bits)
+{
+    if ((int64_t)blockIdx.x < gs) {
+        round_balance_seg(blockIdx.x * blockDim.x + threadIdx.x, rb, st, go, ri);
+        return;
+    }
+    if (go[4 + (ri + 2) % 3] == 0) return;  // the previous round moved nothing
+    log_hedges_blocks((int64_t)blockIdx.x - gs, (int64_t)gridDim.x - gs, count, cnode, cbeg, noff, inc, bits);
 }
 
 
