@@ -95,16 +95,20 @@ __global__ __launch_bounds__(kBlock) void k_decode(int32_t N, const uint64_t *ke
     atomicAdd(&gw[e], nw[v]);
 }
 
+struct AttachOp {
+    const int32_t *off, *pins, *hseg;
+    const uint8_t *sact;
+    const int32_t *match, *cnt, *gw;
+    int32_t *grp;
+    template <int S> __device__ __forceinline__ void run(int64_t vb, int32_t count, const int32_t *list) const;
+};
+
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_attach(int32_t count, const int32_t *list,
-                                                   const int32_t *off, const int32_t *pins,
-                                                   const int32_t *hseg, const uint8_t *sact,
-                                                   const int32_t *match, const int32_t *cnt,
-                                                   const int32_t *gw, int32_t *grp)
+__device__ __forceinline__ void AttachOp::run(int64_t vb, int32_t count, const int32_t *list) const
 {
     __shared__ unsigned long long lds[16];
     int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
     if (S == SMALL && d > kSmallMax) return;
@@ -167,14 +171,12 @@ __device__ __forceinline__ uint64_t fp_term(int32_t q, uint64_t salt)
 
 // Third loop of Algorithm 2 for hyperedges of degree <= 8: parents sorted in
 // registers by an odd-even transposition network.
-__global__ __launch_bounds__(kBlock) void k_qbuild_small(int32_t E, const int32_t *off,
-                                                         const int32_t *pins,
-                                                         const int32_t *hseg,
-                                                         const uint8_t *sact,
-                                                         const int32_t *parent, int32_t *qpins,
-                                                         int32_t *qlen, uint64_t *fp)
+// block vb of the one-thread-per-hyperedge sweep (degree <= kSmallMax)
+__device__ __forceinline__ void qbuild_small(int64_t vb, int32_t E, const int32_t *off, const int32_t *pins,
+                                             const int32_t *hseg, const uint8_t *sact, const int32_t *parent,
+                                             int32_t *qpins, int32_t *qlen, uint64_t *fp)
 {
-    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t e = vb * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int32_t b = off[e], d = off[e + 1] - b;
     if (d > kSmallMax) return;
@@ -278,16 +280,14 @@ __device__ __forceinline__ int32_t wave_unique_emit(const int32_t (&x)[R], int32
     return len;
 }
 
-// Degree 9..256: one wavefront per hyperedge, parents sorted in registers.
-__global__ __launch_bounds__(kBlock) void k_qbuild_wave(int32_t count, const int32_t *list,
-                                                        const int32_t *off, const int32_t *pins,
-                                                        const int32_t *hseg,
-                                                        const uint8_t *sact,
-                                                        const int32_t *parent, int32_t *qpins,
-                                                        int32_t *qlen, uint64_t *fp)
+// Degree 9..256: one wavefront per hyperedge, parents sorted in registers
+// (block vb of that sweep).
+__device__ __forceinline__ void qbuild_wave(int64_t vb, int32_t count, const int32_t *list, const int32_t *off,
+                                            const int32_t *pins, const int32_t *hseg, const uint8_t *sact,
+                                            const int32_t *parent, int32_t *qpins, int32_t *qlen, uint64_t *fp)
 {
     int lane = threadIdx.x & 63;
-    int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    int64_t w = (vb * blockDim.x + threadIdx.x) >> 6;
     if (w >= count) return;
     int32_t e = list[w];
     int32_t b = off[e], d = off[e + 1] - b;
@@ -316,6 +316,19 @@ __global__ __launch_bounds__(kBlock) void k_qbuild_wave(int32_t count, const int
         qlen[e] = len >= 2 ? len : 0;
         fp[e] = fp_finish(sum, len);
     }
+}
+
+// Both sweeps in one launch: blocks [0, ceil(E / kBlock)) one thread per
+// hyperedge, the rest one wavefront per listed mid hyperedge.
+__global__ __launch_bounds__(kBlock) void k_qbuild_sw(int32_t E, int32_t nmid, const int32_t *lmid,
+                                                      const int32_t *off, const int32_t *pins,
+                                                      const int32_t *hseg, const uint8_t *sact,
+                                                      const int32_t *parent, int32_t *qpins, int32_t *qlen,
+                                                      uint64_t *fp)
+{
+    int64_t b = blockIdx.x, ns = ceil_div(E, kBlock);
+    if (b < ns) qbuild_small(b, E, off, pins, hseg, sact, parent, qpins, qlen, fp);
+    else qbuild_wave(b - ns, nmid, lmid, off, pins, hseg, sact, parent, qpins, qlen, fp);
 }
 
 // Sorted distinct parents of one hyperedge by a whole workgroup: a is a
@@ -528,14 +541,17 @@ __global__ __launch_bounds__(kBlock) void k_dd_resolve(int32_t E, const int32_t 
 }
 
 
+struct CopyPinsOp {
+    const int32_t *off, *rep, *qlen, *qpins, *hdst;
+    int32_t *cpins;
+    template <int S> __device__ __forceinline__ void run(int64_t vb, int32_t count, const int32_t *list) const;
+};
+
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_copy_pins(int32_t count, const int32_t *list,
-                                                      const int32_t *off, const int32_t *rep,
-                                                      const int32_t *qlen, const int32_t *qpins,
-                                                      const int32_t *hdst, int32_t *cpins)
+__device__ __forceinline__ void CopyPinsOp::run(int64_t vb, int32_t count, const int32_t *list) const
 {
     int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e];
     if (S == SMALL && off[e + 1] - b > kSmallMax) return;

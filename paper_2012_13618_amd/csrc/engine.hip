@@ -96,18 +96,10 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
            (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
 
     // Algorithm 2, singletons
-    launch(lc, "attach_small", 4.0 * E, k_attach<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
-           (const int32_t *)nullptr, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
-           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
-    launch(lc, "attach_wave", 0.0, k_attach<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
-           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
-           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
-    launch(lc, "attach_block", 0.0, k_attach<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0, f.nbig,
-           (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)b.match,
-           (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp);
+    AttachOp aop{(const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg, (const uint8_t *)sact,
+                 (const int32_t *)b.match, (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp};
+    launch(lc, "attach", 4.0 * E, k_buckets<AttachOp>, buckets_grid(E, f.nmid, f.nbig), kBlock, 0, aop, E, f.nmid,
+           (const int32_t *)f.lmid, f.nbig, (const int32_t *)f.lbig);
     launch(lc, "lead", 12.0 * N, k_lead, ceil_div(N, kBlock), kBlock, 0, N,
            (const int32_t *)f.nseg, (const uint8_t *)sact, (const int32_t *)b.match,
            (const int32_t *)b.cnt, b.grp, b.lead);
@@ -132,13 +124,9 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
            c.nseg);
 
     // Algorithm 2, coarse hyperedges
-    launch(lc, "qbuild_small", 4.0 * E + 12.0 * P, k_qbuild_small, sched_grid<SMALL>(E), kBlock, 0, E,
-           (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
-           (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
-    launch(lc, "qbuild_wave", 0.0, k_qbuild_wave, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
-           (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
-           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins,
-           b.qlen, b.fp);
+    launch(lc, "qbuild", 4.0 * E + 12.0 * P, k_qbuild_sw, ceil_div(E, kBlock) + ceil_div(f.nmid, kBlock / 64),
+           kBlock, 0, E, f.nmid, (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
+           (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
     launch(lc, "qbuild_block", 0.0, k_qbuild_block, sched_grid<BLOCK>(f.nbig), kBlock,
            (size_t)kBigMax * sizeof(int32_t), f.nbig, (const int32_t *)f.lbig,
            (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
@@ -184,15 +172,9 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
             b.totEP);
         launch(lc, "classify", 4.0 * E, k_classify, ceil_div(E, kClsItems), kBlock, 0, E, (const int32_t *)c.off,
                (const uint64_t *)b.totEP, c.lmid, c.lbig, c.lhuge, b.counters);
-        launch(lc, "copy_pins_small", 8.0 * P, k_copy_pins<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
-               (const int32_t *)nullptr, (const int32_t *)f.off, rep, qlen,
-               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
-        launch(lc, "copy_pins_wave", 0.0, k_copy_pins<WAVE>, sched_grid<WAVE>(f.nmid), kBlock, 0, f.nmid,
-               (const int32_t *)f.lmid, (const int32_t *)f.off, rep, qlen,
-               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
-        launch(lc, "copy_pins_block", 0.0, k_copy_pins<BLOCK>, sched_grid<BLOCK>(f.nbig), kBlock, 0,
-               f.nbig, (const int32_t *)f.lbig, (const int32_t *)f.off, rep, qlen,
-               (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins);
+        CopyPinsOp cop{(const int32_t *)f.off, rep, qlen, (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins};
+        launch(lc, "copy_pins", 8.0 * P, k_buckets<CopyPinsOp>, buckets_grid(E, f.nmid, f.nbig), kBlock, 0, cop, E,
+               f.nmid, (const int32_t *)f.lmid, f.nbig, (const int32_t *)f.lbig);
         launch(lc, "level_fixup", 0.0, k_level_fixup, 1, kFixupThreads, 0, S, N, E, (const int32_t *)f.nbase,
                (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
                (const int32_t *)b.totN, (const uint64_t *)b.totEP, l + 1, cx.prm.max_levels,
@@ -252,12 +234,9 @@ void build_incidence(Ctx &cx, Level &L)
     const int32_t N = L.N, E = L.E, P = L.P;
     uint32_t *k0 = ar.get<uint32_t>(P), *k1 = ar.get<uint32_t>(P);
     int32_t *v0 = ar.get<int32_t>(P), *v1 = ar.get<int32_t>(P);
-    launch(lc, "incidence", 8.0 * P, k_expand_pairs<SMALL>, sched_grid<SMALL>(E), kBlock, 0, E,
-           (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
-    launch(lc, "incidence", 0.0, k_expand_pairs<WAVE>, sched_grid<WAVE>(L.nmid), kBlock, 0, L.nmid,
-           (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
-    launch(lc, "incidence", 0.0, k_expand_pairs<BLOCK>, sched_grid<BLOCK>(L.nbig), kBlock, 0, L.nbig,
-           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins, k0, v0);
+    ExpandPairsOp eop{(const int32_t *)L.off, (const int32_t *)L.pins, k0, v0};
+    launch(lc, "incidence", 8.0 * P, k_buckets<ExpandPairsOp>, buckets_grid(E, L.nmid, L.nbig), kBlock, 0, eop, E,
+           L.nmid, (const int32_t *)L.lmid, L.nbig, (const int32_t *)L.lbig);
     int bits = 0;
     while (bits < 31 && ((int64_t)1 << bits) < (int64_t)N) bits++;
     int64_t ntiles = ceil_div(P > 0 ? P : 1, kRsTile);
@@ -311,11 +290,8 @@ void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key)
            (const int32_t *)L.off, (const int32_t *)L.hw, (const int32_t *)L.hseg,
            (const int32_t *)L.hbase, sact, cx.prm.policy, hkey);
     double bytes = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 8.0 * L.N;
-    launch(lc, "match_small", bytes, k_match_nodes<SMALL>, sched_grid<SMALL>(L.N), kBlock, 0, L.N,
-           (const int32_t *)L.ncount, (const int32_t *)nullptr, (const int32_t *)L.noff,
-           (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
-    launch(lc, "match_wave", 0.0, k_match_nodes<WAVE>, sched_grid<WAVE>(L.nmid_bound), kBlock, 0, L.N,
-           (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
+    launch(lc, "match", bytes, k_match_sw, ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64), kBlock, 0,
+           L.N, (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,
            (const int32_t *)L.inc, (const int32_t *)L.nseg, sact, (const uint64_t *)hkey, key);
     launch(lc, "match_chunks", 0.0, k_match_chunks, L.nchunk_bound, kBlock, 0, (const int32_t *)L.ncount,
            (const int32_t *)L.chunk_node, (const int32_t *)L.chunk_beg, (const int32_t *)L.noff,

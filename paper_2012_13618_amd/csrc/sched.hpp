@@ -13,28 +13,55 @@ namespace bp {
 
 enum Sched { SMALL = 0, WAVE = 1, BLOCK = 2 };
 
-// Hyperedge handled by this thread's group, or -1.  lane/stride give the
-// thread's position within the group.  For SMALL the caller still has to skip
-// hyperedges above kSmallMax.
+// Hyperedge handled by this thread's group in block vb of its schedule, or
+// -1.  lane/stride give the thread's position within the group.  For SMALL
+// the caller still has to skip hyperedges above kSmallMax.
 template <int S>
-__device__ __forceinline__ int32_t sched_hedge(int32_t count, const int32_t *list, int &lane,
-                                               int &stride)
+__device__ __forceinline__ int32_t sched_hedge_at(int64_t vb, int32_t count, const int32_t *list, int &lane,
+                                                  int &stride)
 {
     if (S == SMALL) {
-        int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+        int64_t e = vb * blockDim.x + threadIdx.x;
         lane = 0;
         stride = 1;
         return e < count ? (int32_t)e : -1;
     } else if (S == WAVE) {
-        int64_t w = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+        int64_t w = (vb * blockDim.x + threadIdx.x) >> 6;
         lane = threadIdx.x & 63;
         stride = 64;
         return w < count ? list[w] : -1;
     } else {
         lane = threadIdx.x;
         stride = blockDim.x;
-        return blockIdx.x < (unsigned)count ? list[blockIdx.x] : -1;
+        return vb < count ? list[vb] : -1;
     }
+}
+
+template <int S>
+__device__ __forceinline__ int32_t sched_hedge(int32_t count, const int32_t *list, int &lane,
+                                               int &stride)
+{
+    return sched_hedge_at<S>(blockIdx.x, count, list, lane, stride);
+}
+
+// All three buckets of a hyperedge sweep in one launch: blocks [0, ns) take
+// every hyperedge of degree <= kSmallMax one per thread, the next ones the
+// listed mid hyperedges one per wavefront, the last ones the listed big
+// hyperedges one per workgroup; op.run<S>(vb, count, list) does the work of
+// block vb of schedule S.  The buckets are disjoint, so they run together.
+inline int64_t buckets_grid(int64_t E, int64_t nmid, int64_t nbig)
+{
+    return ceil_div(E, kBlock) + ceil_div(nmid, kBlock / 64) + nbig;
+}
+
+template <typename Op>
+__global__ __launch_bounds__(kBlock) void k_buckets(Op op, int32_t E, int32_t nmid, const int32_t *lmid,
+                                                    int32_t nbig, const int32_t *lbig)
+{
+    int64_t b = blockIdx.x, ns = ceil_div(E, kBlock), nw = ceil_div(nmid, kBlock / 64);
+    if (b < ns) op.template run<SMALL>(b, E, nullptr);
+    else if (b < ns + nw) op.template run<WAVE>(b - ns, nmid, lmid);
+    else op.template run<BLOCK>(b - ns - nw, nbig, lbig);
 }
 
 template <int S> inline int64_t sched_grid(int64_t count)

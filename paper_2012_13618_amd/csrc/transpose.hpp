@@ -98,13 +98,18 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, cons
 }
 
 // pins -> (node, hyperedge) pairs in pin order
+struct ExpandPairsOp {
+    const int32_t *off, *pins;
+    uint32_t *keys;
+    int32_t *vals;
+    template <int S> __device__ __forceinline__ void run(int64_t vb, int32_t count, const int32_t *list) const;
+};
+
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_expand_pairs(int32_t count, const int32_t *list,
-                                                         const int32_t *off, const int32_t *pins,
-                                                         uint32_t *keys, int32_t *vals)
+__device__ __forceinline__ void ExpandPairsOp::run(int64_t vb, int32_t count, const int32_t *list) const
 {
     int lane, stride;
-    int32_t e = sched_hedge<S>(count, list, lane, stride);
+    int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
     if (S == SMALL && d > kSmallMax) return;
@@ -261,22 +266,21 @@ __global__ __launch_bounds__(kBlock) void k_hedge_keys(int32_t E, const int32_t 
 // Node schedule: SMALL = every node of degree <= 32 by one thread, WAVE/BLOCK
 // = listed nodes, their count read on the device (the grid is an upper bound).
 template <int S>
-__device__ __forceinline__ int32_t sched_node(int32_t count, const int32_t *dcount,
+__device__ __forceinline__ int32_t sched_node(int64_t vb, int32_t count, const int32_t *dcount,
                                               const int32_t *list, int &lane, int &stride)
 {
-    return sched_hedge<S>(S == SMALL ? count : *dcount, list, lane, stride);
+    return sched_hedge_at<S>(vb, S == SMALL ? count : *dcount, list, lane, stride);
 }
 
+// Block vb of schedule S of Algorithm 1's per-node minimum.
 template <int S>
-__global__ __launch_bounds__(kBlock) void k_match_nodes(int32_t count, const int32_t *dcount,
-                                                        const int32_t *list,
-                                                        const int32_t *noff, const int32_t *inc,
-                                                        const int32_t *nseg, const uint8_t *sact,
-                                                        const uint64_t *hkey, uint64_t *key)
+__device__ __forceinline__ void match_nodes(int64_t vb, int32_t count, const int32_t *dcount, const int32_t *list,
+                                            const int32_t *noff, const int32_t *inc, const int32_t *nseg,
+                                            const uint8_t *sact, const uint64_t *hkey, uint64_t *key)
 {
     __shared__ unsigned long long lds[16];
     int lane, stride;
-    int32_t v = sched_node<S>(count, dcount, list, lane, stride);
+    int32_t v = sched_node<S>(vb, count, dcount, list, lane, stride);
     if (v < 0) return;
     int32_t b = noff[v], d = noff[v + 1] - b;
     if (S == SMALL && d > kNodeSmallMax) {
@@ -291,6 +295,18 @@ __global__ __launch_bounds__(kBlock) void k_match_nodes(int32_t count, const int
         }
     m = group_min<S>(m, lds);
     if (lane == 0) key[v] = m;
+}
+
+// Nodes of degree <= 32 one per thread (blocks [0, ceil(N / kBlock))) and the
+// listed mid nodes one per wavefront (the other blocks; their count is read
+// on the device, the grid is an upper bound), in one launch.
+__global__ __launch_bounds__(kBlock) void k_match_sw(int32_t N, const int32_t *dcount, const int32_t *lnmid,
+                                                     const int32_t *noff, const int32_t *inc, const int32_t *nseg,
+                                                     const uint8_t *sact, const uint64_t *hkey, uint64_t *key)
+{
+    int64_t b = blockIdx.x, ns = ceil_div(N, kBlock);
+    if (b < ns) match_nodes<SMALL>(b, N, dcount, nullptr, noff, inc, nseg, sact, hkey, key);
+    else match_nodes<WAVE>(b - ns, N, dcount, lnmid, noff, inc, nseg, sact, hkey, key);
 }
 
 }  // namespace bp
