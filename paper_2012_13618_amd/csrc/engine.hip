@@ -264,7 +264,8 @@ void build_incidence(Ctx &cx, Level &L)
     L.lnmid = ar.get<int32_t>(L.nmid_bound);
     L.lnbig = ar.get<int32_t>(L.nbig_bound);
     L.ncount = ar.get<int32_t>(4);
-    fill(lc, L.ncount, 4, 0);
+    L.bigslot = ar.get<int32_t>(N);
+    Fills().add(L.ncount, 4, 0).add(L.bigslot, (int64_t)N, -1).run(lc);
     launch(lc, "incidence", 8.0 * N, k_classify_nodes, ceil_div(N, kClsNodes), kBlock, 0, N,
            (const int32_t *)L.noff, L.lnmid, L.lnbig, L.ncount);
     L.nchunk_bound = (int64_t)P / kNodeChunk + L.nbig_bound + 1;
@@ -273,8 +274,6 @@ void build_incidence(Ctx &cx, Level &L)
     L.chunk_big = ar.get<int32_t>(L.nchunk_bound);
     L.big_chunks = ar.get<int32_t>(L.nbig_bound);
     L.big_done = ar.get<int32_t>(L.nbig_bound);
-    L.bigslot = ar.get<int32_t>(N);
-    fill(lc, L.bigslot, N, -1);
     launch(lc, "incidence", 0.0, k_big_chunks, 1, kBlock, 0, (const int32_t *)L.lnbig,
            (const int32_t *)L.noff, L.ncount, L.chunk_node, L.chunk_beg, L.chunk_big, L.big_chunks,
            L.bigslot);
@@ -529,8 +528,11 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     LaunchCtx &lc = cx.lc;
     int64_t gs = ceil_div(L.S, kBlock);
     for (int it = 0; it < cx.prm.refine_iters; it++) {
-        launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
-               sg.mode, sg.gmask, sg.done, sg.st, sg.go);
+        // a later iteration finds the modes and masks the first one set, unless
+        // the multi-workgroup selection needs its lists reset
+        if (it == 0 || !seg_path(cx, L, 0))
+            launch(lc, "round", 0.0, k_round_refine, gs, kBlock, 0, L.S, j, (const int32_t *)sg.coarsest,
+                   sg.mode, sg.gmask, sg.done, sg.st, sg.go);
         run_gains(cx, L, sg, gain, !seg_path(cx, L, 0), nullptr);
         select_and_flip(cx, L, sg, gain, nullptr);
     }
@@ -539,8 +541,25 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                sg.mode, sg.gmask, sg.done, sg.st, sg.go);
     // balance step: the first round computes every gain; later rounds update
     // the gains from the hyperedges of the nodes the previous round moved
-    fill(lc, sg.go, 8, 0);
-    fill(lc, sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
+    // incremental gains pay off once a full recomputation is long against
+    // the three short launches they take
+    bool incr = L.P >= cx.sched.incremental_min_pins && !fuse_all(cx, L);
+    Arena &ar = *cx.ar;
+    MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
+    uint32_t *bits = nullptr;
+    int64_t nbits = ceil_div(L.E, 32);
+    Fills zf;
+    zf.add(sg.go, 8, 0).add(sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
+    if (incr) {
+        int64_t chunks = (int64_t)L.P / kLogChunk + L.N + 1;
+        ml.moved = ar.get<uint8_t>(L.N);
+        ml.cnode = ar.get<int32_t>(chunks);
+        ml.cbeg = ar.get<int32_t>(chunks);
+        ml.count = ar.get<int32_t>(4);
+        bits = ar.get<uint32_t>(nbits);
+        zf.add(ml.moved, (int64_t)L.N, (uint8_t)0).add(bits, nbits, 0u).add(ml.count, 4, 0);
+    }
+    zf.run(lc);
     // small segments: the whole balance step in one workgroup each; when every
     // segment is small that is all, else the rounds below run the others
     if (cx.sched.fuse_max_pins > 0) {
@@ -553,24 +572,6 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // LDS keys of the balance finish (32 KiB at most): room for a sorted
     // copy behind the candidates when the lists are short
     int32_t cap = sg.cand_stride <= 2048 ? 2 * sg.cand_stride : (sg.cand_stride <= 4096 ? sg.cand_stride : 0);
-    Arena &ar = *cx.ar;
-    // incremental gains pay off once a full recomputation is long against
-    // the three short launches they take
-    bool incr = L.P >= cx.sched.incremental_min_pins;
-    MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
-    uint32_t *bits = nullptr;
-    int64_t nbits = ceil_div(L.E, 32);
-    if (incr) {
-        int64_t chunks = (int64_t)L.P / kLogChunk + L.N + 1;
-        ml.moved = ar.get<uint8_t>(L.N);
-        ml.cnode = ar.get<int32_t>(chunks);
-        ml.cbeg = ar.get<int32_t>(chunks);
-        ml.count = ar.get<int32_t>(4);
-        bits = ar.get<uint32_t>(nbits);
-        fill(lc, ml.moved, L.N, (uint8_t)0);
-        fill(lc, bits, nbits, 0u);
-        fill(lc, ml.count, 4, 0);
-    }
     BalFinish bf{sg.mode, L.nw, sg.need, sg.room, L.side, (unsigned long long *)sg.w, sg.done, sg.stuck, ml,
                  sg.go, sg.bal_moved, sg.st.rsel};
     // chunked selections: the level's chunk table (buffers of the whole
@@ -724,19 +725,22 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
         if (chunk_path(cx, x)) tab_n = std::max<int64_t>(tab_n, ceil_div(x.N, kChunkNodes) + x.S);
     alloc_chunk_bufs(ar, sg, tab_n);
     int32_t *gain = ar.get<int32_t>(lv[0].N);
-    fill(lc, sg.st.hist, (int64_t)2 * sg.S * kBins, 0u);
-    fill(lc, sg.st.ctl, 4, 0);
-    fill(lc, sg.st.tick, (int64_t)sg.S, 0);
-    fill(lc, sg.st.rsel, (int64_t)2 * sg.S, 0);
+    Fills()
+        .add(sg.st.hist, (int64_t)2 * sg.S * kBins, 0u)
+        .add(sg.st.ctl, 4, 0)
+        .add(sg.st.tick, (int64_t)sg.S, 0)
+        .add(sg.st.rsel, (int64_t)2 * sg.S, 0)
+        .run(lc);
 
     for (int32_t j = Lmax; j >= 0; j--) {
         Level &L = lv[j];
         L.side = ar.get<uint8_t>(L.N);
-        launch(lc, "project", 6.0 * L.N, k_project, ceil_div(L.N, kBlock), kBlock, 0, L.N, j,
+        // (and the segments' side weights zeroed)
+        launch(lc, "project", 6.0 * L.N, k_project, std::max<int64_t>(1, ceil_div(L.N, kBlock)), kBlock, 0, L.N, j,
                (const int32_t *)L.nseg, (const int32_t *)sg.coarsest,
                (const int32_t *)(j < Lmax ? L.parent : nullptr),
-               (const uint8_t *)(j < Lmax ? lv[j + 1].side : nullptr), L.side);
-        fill(lc, sg.w, (int64_t)2 * sg.S, (int64_t)0);
+               (const uint8_t *)(j < Lmax ? lv[j + 1].side : nullptr), L.side, (unsigned long long *)sg.w,
+               2 * sg.S);
         launch(lc, "side_weights", 5.0 * L.N, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
                (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,
                (unsigned long long *)sg.w);
@@ -1934,7 +1938,7 @@ bp_status bp_step_initial(const bp_hypergraph *hg, int32_t k0, int32_t k1, uint8
     int32_t *gain = cx.ar->get<int32_t>(L.N);
     launch(cx.lc, "project", 0.0, k_project, ceil_div(L.N, kBlock), kBlock, 0, L.N, 0,
            (const int32_t *)L.nseg, (const int32_t *)sg.coarsest, (const int32_t *)nullptr,
-           (const uint8_t *)nullptr, L.side);
+           (const uint8_t *)nullptr, L.side, (unsigned long long *)nullptr, 0);
     fill(cx.lc, sg.w, 2, (int64_t)0);
     launch(cx.lc, "side_weights", 0.0, k_side_weights, reduce_grid(L.N), kBlock, 0, L.N,
            (const int32_t *)L.nseg, (const uint8_t *)L.side, (const int32_t *)L.nw,

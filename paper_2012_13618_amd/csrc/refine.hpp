@@ -15,11 +15,15 @@ constexpr uint8_t kList0 = 1, kList1 = 2, kGainNonNeg = 4, kMinPair = 8;
 
 // side of level j: projected from level j+1 for segments coarsened past j,
 // all-ones start of Algorithm 3 for segments whose coarsest level is j.
+// Also zeroes zero[0, nzero) (block 0), for the side weights that follow.
 __global__ __launch_bounds__(kBlock) void k_project(int32_t N, int32_t j, const int32_t *nseg,
                                                     const int32_t *coarsest,
                                                     const int32_t *parent,
-                                                    const uint8_t *side_coarse, uint8_t *side)
+                                                    const uint8_t *side_coarse, uint8_t *side,
+                                                    unsigned long long *zero, int32_t nzero)
 {
+    if (blockIdx.x == 0)
+        for (int32_t i = threadIdx.x; i < nzero; i += blockDim.x) zero[i] = 0ull;
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;
     int32_t c = coarsest[nseg[v]];

@@ -167,4 +167,60 @@ template <typename T> inline void fill(LaunchCtx &lc, T *p, int64_t n, T v)
     launch(lc, "fill", (double)n * sizeof(T), k_fill<T>, g, kBlock, 0, p, n, v);
 }
 
+// Several arrays filled in one launch (grid y = array): up to kFillMax of
+// them, elements of 1, 4 or 8 bytes.
+constexpr int kFillMax = 6;
+struct FillSet {
+    void *p[kFillMax];
+    int64_t n[kFillMax];
+    uint64_t v[kFillMax];
+    int32_t size[kFillMax];
+};
+
+__global__ __launch_bounds__(kBlock) void k_fill_set(FillSet fs)
+{
+    int k = blockIdx.y;
+    int64_t n = fs.n[k];
+    uint64_t v = fs.v[k];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        if (fs.size[k] == 1) ((uint8_t *)fs.p[k])[i] = (uint8_t)v;
+        else if (fs.size[k] == 4) ((uint32_t *)fs.p[k])[i] = (uint32_t)v;
+        else ((uint64_t *)fs.p[k])[i] = v;
+    }
+}
+
+class Fills {
+  public:
+    template <typename T> Fills &add(T *p, int64_t n, T v)
+    {
+        static_assert(sizeof(T) == 1 || sizeof(T) == 4 || sizeof(T) == 8, "element size");
+        if (n <= 0) return *this;
+        if (k_ == kFillMax) throw Error(BP_ERR_DEVICE, "too many arrays in one fill");
+        uint64_t bits = 0;
+        __builtin_memcpy(&bits, &v, sizeof(T));
+        fs_.p[k_] = (void *)p;
+        fs_.n[k_] = n;
+        fs_.v[k_] = bits;
+        fs_.size[k_] = (int32_t)sizeof(T);
+        g_ = std::max<int64_t>(g_, std::min<int64_t>(ceil_div(n, kBlock), 4096));
+        bytes_ += (double)n * sizeof(T);
+        k_++;
+        return *this;
+    }
+    void run(LaunchCtx &lc)
+    {
+        if (k_ == 0) return;
+        launch3(lc, "fill", bytes_, k_fill_set, dim3((unsigned)g_, (unsigned)k_, 1), kBlock, 0, fs_);
+        k_ = 0;
+        g_ = 0;
+        bytes_ = 0.0;
+    }
+
+  private:
+    FillSet fs_{};
+    int k_ = 0;
+    int64_t g_ = 0;
+    double bytes_ = 0.0;
+};
+
 }  // namespace bp
