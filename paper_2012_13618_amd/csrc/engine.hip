@@ -697,10 +697,23 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
     {
         unsigned long long *bd = ar.get<unsigned long long>(2 * (Lmax + 1));
         fill(lc, bd, 2 * (int64_t)(Lmax + 1), 0ull);
-        for (int32_t j = 0; j <= Lmax; j++)
-            launch(lc, "level_bound", 4.0 * (lv[j].N + lv[j].E), k_level_bound,
-                   std::min<int64_t>(reduce_grid(std::max(lv[j].N, lv[j].E)), 128), kBlock, 0, lv[j].N, lv[j].E,
-                   (const int32_t *)lv[j].noff, (const int32_t *)lv[j].hw, bd + 2 * j);
+        for (int32_t j0 = 0; j0 <= Lmax; j0 += kBoundLevels) {
+            LevelBoundArgs la{};
+            int32_t nl = std::min<int32_t>(kBoundLevels, Lmax + 1 - j0);
+            int64_t g = 1;
+            double bytes = 0.0;
+            for (int32_t q = 0; q < nl; q++) {
+                const Level &x = lv[j0 + q];
+                la.noff[q] = x.noff;
+                la.hw[q] = x.hw;
+                la.N[q] = x.N;
+                la.E[q] = x.E;
+                g = std::max<int64_t>(g, std::min<int64_t>(reduce_grid(std::max(x.N, x.E)), 128));
+                bytes += 4.0 * (x.N + x.E);
+            }
+            launch3(lc, "level_bound", bytes, k_level_bound, dim3((unsigned)g, (unsigned)nl, 1), kBlock, 0, la,
+                    bd + 2 * j0);
+        }
         std::vector<unsigned long long> hb(2 * (Lmax + 1));
         BP_HIP(hipMemcpyAsync(hb.data(), bd, sizeof(unsigned long long) * hb.size(), hipMemcpyDeviceToHost,
                               lc.stream));

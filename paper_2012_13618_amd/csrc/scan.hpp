@@ -2,9 +2,11 @@
 //
 // in(i) yields element i (computed on the fly, so flags need not be
 // materialised); out(i, exclusive_prefix, value) consumes the result (it can
-// write the prefix, or scatter/compact).  Three passes: tile sums, one
-// workgroup scanning the tile sums, then the tiles re-scanned with their
-// offsets.  Integer sums only, so the result is independent of scheduling.
+// write the prefix, or scatter/compact).  Tile sums, then the tiles
+// re-scanned with their offsets; the offsets come from one workgroup scanning
+// the tile sums, or, up to kScanInlineTiles tiles, each re-scanning tile adds
+// up the sums before it itself (they stay in L2), which saves that launch.
+// Integer sums only, so the result is independent of scheduling.
 #pragma once
 #include "common.hpp"
 
@@ -12,6 +14,7 @@ namespace bp {
 
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
+constexpr int64_t kScanInlineTiles = 4096;
 
 template <typename T, typename In>
 __global__ __launch_bounds__(kBlock) void k_scan_tiles(In in, int64_t n, T *tile_sum)
@@ -44,11 +47,21 @@ template <typename T> __global__ __launch_bounds__(1024) void k_scan_spine(T *ti
     if (threadIdx.x == 0) *total = carry;
 }
 
-template <typename T, typename In, typename Out>
-__global__ __launch_bounds__(kBlock) void k_scan_apply(In in, int64_t n, const T *tile_off, Out out)
+// INLINE: tiles holds the tile sums (not yet their offsets); this tile adds
+// up those before it, and the last tile writes the total.
+template <typename T, typename In, typename Out, bool INLINE>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(In in, int64_t n, const T *tiles, Out out, T *total)
 {
-    __shared__ T lds[16];
+    __shared__ T lds[16], lds2[16];
     __shared__ T stage[kScanTile];
+    T off;
+    if (INLINE) {
+        T s = 0;
+        for (int64_t t = threadIdx.x; t < (int64_t)blockIdx.x; t += kBlock) s += tiles[t];
+        off = block_sum(s, lds2);
+    } else {
+        off = tiles[blockIdx.x];
+    }
     int64_t base = (int64_t)blockIdx.x * kScanTile;
     // coalesced load into LDS, then each thread scans a contiguous run
 #pragma unroll
@@ -65,7 +78,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(In in, int64_t n, const T
         local += v[j];
     }
     T tot;
-    T ex = block_excl_scan(local, lds, &tot) + tile_off[blockIdx.x];
+    T ex = block_excl_scan(local, lds, &tot) + off;
+    if (INLINE && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *total = off + tot;
 #pragma unroll
     for (int j = 0; j < kScanItems; j++) {
         int64_t i = base + threadIdx.x * kScanItems + j;
@@ -73,6 +87,8 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(In in, int64_t n, const T
         ex += v[j];
     }
 }
+
+template <typename T> __global__ void k_scan_zero(T *p) { *p = T(0); }
 
 // Scratch needed by scan(): tile sums + total.
 struct ScanScratch {
@@ -87,10 +103,18 @@ inline void scan(LaunchCtx &lc, Arena &ar, const char *name, int64_t n, In in, O
     int64_t nt = ceil_div(n > 0 ? n : 1, kScanTile);
     T *tiles = ar.get<T>(nt);
     double bytes = (double)n * 2 * sizeof(T);
-    if (n > 0) launch(lc, name, bytes, k_scan_tiles<T, In>, nt, kBlock, 0, in, n, tiles);
-    else BP_HIP(hipMemsetAsync(tiles, 0, sizeof(T), lc.stream));
-    launch(lc, name, 0.0, k_scan_spine<T>, 1, 1024, 0, tiles, n > 0 ? nt : int64_t(1), d_total);
-    if (n > 0) launch(lc, name, bytes, k_scan_apply<T, In, Out>, nt, kBlock, 0, in, n, (const T *)tiles, out);
+    if (n <= 0) {
+        launch(lc, name, 0.0, k_scan_zero<T>, 1, 1, 0, d_total);
+        return;
+    }
+    launch(lc, name, bytes, k_scan_tiles<T, In>, nt, kBlock, 0, in, n, tiles);
+    if (nt <= kScanInlineTiles) {
+        launch(lc, name, bytes, k_scan_apply<T, In, Out, true>, nt, kBlock, 0, in, n, (const T *)tiles, out,
+               d_total);
+        return;
+    }
+    launch(lc, name, 0.0, k_scan_spine<T>, 1, 1024, 0, tiles, nt, d_total);
+    launch(lc, name, bytes, k_scan_apply<T, In, Out, false>, nt, kBlock, 0, in, n, (const T *)tiles, out, d_total);
 }
 
 }  // namespace bp

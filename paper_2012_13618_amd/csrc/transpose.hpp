@@ -192,10 +192,21 @@ __global__ __launch_bounds__(kBlock) void k_big_chunks(const int32_t *lnbig, con
 }
 
 // Largest node degree and largest hyperedge weight of a level (the gain span
-// bound of the selection).
-__global__ __launch_bounds__(kBlock) void k_level_bound(int32_t N, int32_t E, const int32_t *noff,
-                                                        const int32_t *hw, unsigned long long *out)
+// bound of the selection), for up to kBoundLevels levels in one launch (grid y
+// = level): out[2 j], out[2 j + 1] for level y of the launch.
+constexpr int kBoundLevels = 32;
+struct LevelBoundArgs {
+    const int32_t *noff[kBoundLevels];
+    const int32_t *hw[kBoundLevels];
+    int32_t N[kBoundLevels], E[kBoundLevels];
+};
+
+__global__ __launch_bounds__(kBlock) void k_level_bound(LevelBoundArgs a, unsigned long long *outs)
 {
+    int j = blockIdx.y;
+    int32_t N = a.N[j], E = a.E[j];
+    const int32_t *noff = a.noff[j], *hw = a.hw[j];
+    unsigned long long *out = outs + 2 * j;
     int64_t n = N > E ? N : E, lo, hi;
     reduce_chunk(n, gridDim.x, blockIdx.x, lo, hi);
     unsigned long long d = 0, w = 0;
