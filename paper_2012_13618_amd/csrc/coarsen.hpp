@@ -49,9 +49,18 @@ struct CoarsenBufs {
     int32_t *huge_scratch;
 };
 
+// Also Algorithm 1's hyperedge keys (what k_hedge_keys computes): hkey[e].
+struct HedgeKeyArgs {
+    const int32_t *off, *hw, *hseg, *hbase;
+    const uint8_t *sact;
+    int policy;
+    uint64_t *hkey;
+};
+
 __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, int32_t *grp,
                                int32_t *cnw, int32_t *cnt, int32_t *gw, int32_t *lead,
-                               int32_t *wsum, uint64_t *tkeys, int32_t *tmin, int32_t *counters)
+                               int32_t *wsum, uint64_t *tkeys, int32_t *tmin, int32_t *counters,
+                               HedgeKeyArgs hk)
 {
     int64_t n = N > E ? N : E;
     if (T > n) n = T;
@@ -67,6 +76,10 @@ __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, i
             gw[i] = 0;
             lead[i] = INT32_MAX;
             wsum[i] = 0;
+            int32_t s = hk.hseg[i];
+            hk.hkey[i] = hk.sact[s] ? hedge_key(hk.policy, (uint32_t)(i - hk.hbase[s]), hk.off[i + 1] - hk.off[i],
+                                                hk.hw[i])
+                                    : kNoKey;
         }
         if (i < T) {
             tkeys[i] = kEmptySlot;

@@ -39,6 +39,27 @@ static void set_schedule(const Schedule &s)
 
 // ---- one coarsening step ------------------------------------------------------
 
+// The coarse level's hyperedge lists by degree (blocks [0, ncls)) and the copy
+// of its pins (the other blocks, by degree bucket of the fine hyperedges), in
+// one launch: their outputs are disjoint.
+__global__ __launch_bounds__(kBlock) void k_classify_copy(int64_t ncls, int32_t E, const int32_t *coff,
+                                                          const uint64_t *tot, int32_t *lmid, int32_t *lbig,
+                                                          int32_t *lhuge, int32_t *counters, CopyPinsOp op,
+                                                          int32_t nmid, const int32_t *flmid, int32_t nbig,
+                                                          const int32_t *flbig)
+{
+    int64_t b = blockIdx.x;
+    if (b < ncls) {
+        classify_block(b, E, coff, tot, lmid, lbig, lhuge, counters);
+        return;
+    }
+    b -= ncls;
+    int64_t ns = ceil_div(E, kBlock), nw = ceil_div(nmid, kBlock / 64);
+    if (b < ns) op.template run<SMALL>(b, E, nullptr);
+    else if (b < ns + nw) op.template run<WAVE>(b - ns, nmid, flmid);
+    else op.template run<BLOCK>(b - ns - nw, nbig, flbig);
+}
+
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
                    Level &c)
 {
@@ -85,12 +106,15 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     alloc_lists(ar, c, E);
 
     int64_t initn = std::max<int64_t>(std::max<int64_t>(N, E), T);
-    launch(lc, "coarsen_init", 8.0 * N + 16.0 * E + 12.0 * T, k_coarsen_init,
+    uint64_t *hkey = ar.get<uint64_t>(E);
+    HedgeKeyArgs hk{(const int32_t *)f.off, (const int32_t *)f.hw, (const int32_t *)f.hseg,
+                    (const int32_t *)f.hbase, sact, cx.prm.policy, hkey};
+    launch(lc, "coarsen_init", 8.0 * N + 16.0 * E + 12.0 * T + 20.0 * E, k_coarsen_init,
            std::min<int64_t>(ceil_div(initn, kBlock), 8192), kBlock, 0, N, E, T, b.key, b.grp,
-           c.nw, b.cnt, b.gw, b.lead, b.wsum, b.tkeys, b.tmin, b.counters);
+           c.nw, b.cnt, b.gw, b.lead, b.wsum, b.tkeys, b.tmin, b.counters, hk);
 
     // Algorithm 1: per-node minimum over its own hyperedges' keys
-    run_match_keys(cx, f, sact, b.key);
+    run_match_keys(cx, f, sact, b.key, hkey);
     launch(lc, "decode", 16.0 * N, k_decode, ceil_div(N, kBlock), kBlock, 0, N,
            (const uint64_t *)b.key, (const int32_t *)f.nseg, (const int32_t *)f.hbase,
            (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
@@ -170,10 +194,10 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
                 }
             },
             b.totEP);
-        launch(lc, "classify", 4.0 * E, k_classify, ceil_div(E, kClsItems), kBlock, 0, E, (const int32_t *)c.off,
-               (const uint64_t *)b.totEP, c.lmid, c.lbig, c.lhuge, b.counters);
         CopyPinsOp cop{(const int32_t *)f.off, rep, qlen, (const int32_t *)b.qpins, (const int32_t *)b.hdst, c.pins};
-        launch(lc, "copy_pins", 8.0 * P, k_buckets<CopyPinsOp>, buckets_grid(E, f.nmid, f.nbig), kBlock, 0, cop, E,
+        int64_t ncls = ceil_div(E, kClsItems);
+        launch(lc, "copy_pins", 4.0 * E + 8.0 * P, k_classify_copy, ncls + buckets_grid(E, f.nmid, f.nbig), kBlock, 0,
+               ncls, E, (const int32_t *)c.off, (const uint64_t *)b.totEP, c.lmid, c.lbig, c.lhuge, b.counters, cop,
                f.nmid, (const int32_t *)f.lmid, f.nbig, (const int32_t *)f.lbig);
         launch(lc, "level_fixup", 0.0, k_level_fixup, 1, kFixupThreads, 0, S, N, E, (const int32_t *)f.nbase,
                (const int32_t *)f.hbase, (const int32_t *)b.cid, (const int32_t *)b.hb_tmp,
@@ -280,14 +304,18 @@ void build_incidence(Ctx &cx, Level &L)
     L.cc = ar.get<int2>(E);
 }
 
-void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key)
+void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key, const uint64_t *hkey_ready)
 {
     Arena &ar = *cx.ar;
     LaunchCtx &lc = cx.lc;
-    uint64_t *hkey = ar.get<uint64_t>(L.E);
-    launch(lc, "hedge_keys", 20.0 * L.E, k_hedge_keys, ceil_div(L.E, kBlock), kBlock, 0, L.E,
-           (const int32_t *)L.off, (const int32_t *)L.hw, (const int32_t *)L.hseg,
-           (const int32_t *)L.hbase, sact, cx.prm.policy, hkey);
+    const uint64_t *hkey = hkey_ready;
+    if (!hkey) {
+        uint64_t *h = ar.get<uint64_t>(L.E);
+        launch(lc, "hedge_keys", 20.0 * L.E, k_hedge_keys, ceil_div(L.E, kBlock), kBlock, 0, L.E,
+               (const int32_t *)L.off, (const int32_t *)L.hw, (const int32_t *)L.hseg,
+               (const int32_t *)L.hbase, sact, cx.prm.policy, h);
+        hkey = h;
+    }
     double bytes = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 8.0 * L.N;
     launch(lc, "match", bytes, k_match_sw, ceil_div(L.N, kBlock) + ceil_div(L.nmid_bound, kBlock / 64), kBlock, 0,
            L.N, (const int32_t *)L.ncount, (const int32_t *)L.lnmid, (const int32_t *)L.noff,

@@ -282,7 +282,8 @@ uint64_t eps_factor(int32_t k, double eps);
 void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_next, int32_t l,
                    Level &c);
 void build_incidence(Ctx &cx, Level &L);
-void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key);
+// hkey: the level's hyperedge keys when already computed, else null
+void run_match_keys(Ctx &cx, Level &L, const uint8_t *sact, uint64_t *key, const uint64_t *hkey = nullptr);
 void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0);
 void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int32_t *go);
 void run_select(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, const int32_t *go, int32_t clip = 0);

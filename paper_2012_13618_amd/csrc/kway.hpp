@@ -94,9 +94,9 @@ __global__ void k_copy_weights(int64_t n, const int32_t *src, int32_t *dst)
 // treats its items independently.
 constexpr int kClsItems = 2048;
 
-__global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *off, const uint64_t *tot,
-                                                     int32_t *lmid, int32_t *lbig, int32_t *lhuge,
-                                                     int32_t *counters)
+// Block vb of the classification.
+__device__ __forceinline__ void classify_block(int64_t vb, int32_t E, const int32_t *off, const uint64_t *tot,
+                                               int32_t *lmid, int32_t *lbig, int32_t *lhuge, int32_t *counters)
 {
     __shared__ int32_t items[3][kClsItems];
     __shared__ int32_t cnt[3], base[3];
@@ -105,7 +105,7 @@ __global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *o
         E = (int32_t)(*tot >> 32);
         P = (int32_t)(*tot & 0xffffffffu);
     }
-    int64_t first = (int64_t)blockIdx.x * kClsItems;
+    int64_t first = vb * kClsItems;
     if (first >= E) return;
     if (!tot) P = off[E];
     if (threadIdx.x < 3) cnt[threadIdx.x] = 0;
@@ -124,6 +124,13 @@ __global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *o
     for (int i = threadIdx.x; i < cnt[0]; i += blockDim.x) lmid[base[0] + i] = items[0][i];
     for (int i = threadIdx.x; i < cnt[1]; i += blockDim.x) lbig[base[1] + i] = items[1][i];
     for (int i = threadIdx.x; i < cnt[2]; i += blockDim.x) lhuge[base[2] + i] = items[2][i];
+}
+
+__global__ __launch_bounds__(kBlock) void k_classify(int32_t E, const int32_t *off, const uint64_t *tot,
+                                                     int32_t *lmid, int32_t *lbig, int32_t *lhuge,
+                                                     int32_t *counters)
+{
+    classify_block(blockIdx.x, E, off, tot, lmid, lbig, lhuge, counters);
 }
 
 template <int S>
