@@ -58,18 +58,53 @@ __global__ __launch_bounds__(kBlock) void k_validate(int32_t N, int32_t E, const
 // ---- level 0: drop hyperedges that cannot be cut --------------------------------
 
 // copy the kept hyperedges' pins (degree >= 2) to their compacted place
+constexpr int kNormShort = 16;
+
 __global__ __launch_bounds__(kBlock) void k_norm_copy(int32_t E, const int32_t *off,
                                                       const int32_t *pins, const int32_t *dst,
                                                       int32_t *cpins)
 {
-    // one wavefront per hyperedge would waste lanes on degree-2 edges; instead
-    // each thread copies one hyperedge, long ones are split across the wave
+    // a thread per hyperedge of at most kNormShort pins (its loads all in
+    // flight before the stores); longer ones are copied by the whole
+    // wavefront, one after another, 8 loads a lane in flight.  Every lane
+    // reaches the ballot: lanes past E carry an empty hyperedge.
+    const int lane = threadIdx.x & 63;
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= E) return;
-    int32_t b = off[e], d = off[e + 1] - b;
-    if (d < 2) return;
-    int32_t o = dst[e];
-    for (int i = 0; i < d; i++) cpins[o + i] = pins[b + i];
+    int32_t b = 0, d = 0, o = 0;
+    if (e < E) {
+        b = off[e];
+        d = off[e + 1] - b;
+        if (d >= 2) o = dst[e];
+        else d = 0;
+    }
+    if (d <= kNormShort) {
+        int32_t v[kNormShort];
+#pragma unroll
+        for (int i = 0; i < kNormShort; i++)
+            if (i < d) v[i] = pins[b + i];
+#pragma unroll
+        for (int i = 0; i < kNormShort; i++)
+            if (i < d) cpins[o + i] = v[i];
+    }
+    unsigned long long lm = __ballot(d > kNormShort);
+    while (lm) {
+        int l = __ffsll((long long)lm) - 1;
+        lm &= lm - 1;
+        int32_t lb = __shfl(b, l, 64), ld = __shfl(d, l, 64), lo = __shfl(o, l, 64);
+        for (int32_t i0 = 0; i0 < ld; i0 += 8 * 64) {
+            int32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                int32_t i = i0 + u * 64 + lane;
+                v[u] = i < ld ? pins[lb + i] : 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; u++) {
+                int32_t i = i0 + u * 64 + lane;
+                if (i < ld) cpins[lo + i] = v[u];
+            }
+        }
+    }
 }
 
 __global__ void k_iota(int64_t n, int32_t *p)
