@@ -30,7 +30,7 @@ struct CoarsenBufs {
     int32_t *match;    // [N]
     int32_t *grp;      // [N]
     int32_t *cid;      // [N]
-    int32_t *cnt, *gw; // [E]
+    uint64_t *cg;      // [E] nodes matched to the hyperedge << 32 | their weight
     int32_t *lead;     // [E]
     int32_t *qpins;    // [P]
     int32_t *qlen;     // [E]
@@ -58,7 +58,7 @@ struct HedgeKeyArgs {
 };
 
 __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, int32_t *grp,
-                               int32_t *cnw, int32_t *cnt, int32_t *gw, int32_t *lead,
+                               int32_t *cnw, uint64_t *cg, int32_t *lead,
                                int32_t *wsum, uint64_t *tkeys, int32_t *tmin, int32_t *counters,
                                HedgeKeyArgs hk)
 {
@@ -72,8 +72,7 @@ __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, i
             cnw[i] = 0;
         }
         if (i < E) {
-            cnt[i] = 0;
-            gw[i] = 0;
+            cg[i] = 0;
             lead[i] = INT32_MAX;
             wsum[i] = 0;
             int32_t s = hk.hseg[i];
@@ -92,7 +91,7 @@ __global__ void k_coarsen_init(int32_t N, int32_t E, int64_t T, uint64_t *key, i
 __global__ __launch_bounds__(kBlock) void k_decode(int32_t N, const uint64_t *key,
                                                    const int32_t *nseg, const int32_t *hbase,
                                                    const uint8_t *sact, const int32_t *nw,
-                                                   int32_t *match, int32_t *cnt, int32_t *gw)
+                                                   int32_t *match, uint64_t *cg)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N) return;
@@ -104,14 +103,16 @@ __global__ __launch_bounds__(kBlock) void k_decode(int32_t N, const uint64_t *ke
     }
     int32_t e = hbase[s] + (int32_t)(fmix32_inv((uint32_t)k) - 1u);
     match[v] = e;
-    atomicAdd(&cnt[e], 1);
-    atomicAdd(&gw[e], nw[v]);
+    // count and weight in one atomic: a weight sum stays below 2^31, so the
+    // low half never carries into the count
+    atomicAdd((unsigned long long *)&cg[e], (1ull << 32) | (uint32_t)nw[v]);
 }
 
 struct AttachOp {
     const int32_t *off, *pins, *hseg;
     const uint8_t *sact;
-    const int32_t *match, *cnt, *gw;
+    const int32_t *match;
+    const uint64_t *cg;
     int32_t *grp;
     template <int S> __device__ __forceinline__ void run(int64_t vb, int32_t count, const int32_t *list) const;
 };
@@ -125,16 +126,19 @@ __device__ __forceinline__ void AttachOp::run(int64_t vb, int32_t count, const i
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
     if (S == SMALL && d > kSmallMax) return;
-    if (cnt[e] != 1 || !sact[hseg[e]]) return;
+    if ((cg[e] >> 32) != 1 || !sact[hseg[e]]) return;
     unsigned long long best = kNoKey, uu = kNoKey;
     for (int i = lane; i < d; i += stride) {
         int32_t v = pins[b + i];
         int32_t m = match[v];
         if (m == e) {
             uu = (unsigned long long)v;
-        } else if (cnt[m] >= 2) {
-            unsigned long long c = ((unsigned long long)(uint32_t)gw[m] << 32) | (uint32_t)v;
-            best = c < best ? c : best;
+        } else {
+            uint64_t x = cg[m];
+            if ((x >> 32) >= 2) {
+                unsigned long long c = (x << 32) | (uint32_t)v;
+                best = c < best ? c : best;
+            }
         }
     }
     best = group_min<S>(best, lds);
@@ -144,12 +148,12 @@ __device__ __forceinline__ void AttachOp::run(int64_t vb, int32_t count, const i
 
 __global__ __launch_bounds__(kBlock) void k_lead(int32_t N, const int32_t *nseg,
                                                  const uint8_t *sact, const int32_t *match,
-                                                 const int32_t *cnt, int32_t *grp, int32_t *lead)
+                                                 const uint64_t *cg, int32_t *grp, int32_t *lead)
 {
     int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= N || !sact[nseg[v]]) return;
     int32_t m = match[v];
-    int32_t g = (m >= 0 && cnt[m] >= 2) ? m : grp[v];
+    int32_t g = (m >= 0 && (cg[m] >> 32) >= 2) ? m : grp[v];
     grp[v] = g;
     if (g >= 0) atomicMin(&lead[g], (int32_t)v);
 }

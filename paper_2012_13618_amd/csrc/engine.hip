@@ -73,8 +73,7 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     b.match = ar.get<int32_t>(N);
     b.grp = ar.get<int32_t>(N);
     b.cid = ar.get<int32_t>(N);
-    b.cnt = ar.get<int32_t>(E);
-    b.gw = ar.get<int32_t>(E);
+    b.cg = ar.get<uint64_t>(E);
     b.lead = ar.get<int32_t>(E);
     b.qpins = ar.get<int32_t>(P);
     b.qlen = ar.get<int32_t>(E);
@@ -111,22 +110,22 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
                     (const int32_t *)f.hbase, sact, cx.prm.policy, hkey};
     launch(lc, "coarsen_init", 8.0 * N + 16.0 * E + 12.0 * T + 20.0 * E, k_coarsen_init,
            std::min<int64_t>(ceil_div(initn, kBlock), 8192), kBlock, 0, N, E, T, b.key, b.grp,
-           c.nw, b.cnt, b.gw, b.lead, b.wsum, b.tkeys, b.tmin, b.counters, hk);
+           c.nw, b.cg, b.lead, b.wsum, b.tkeys, b.tmin, b.counters, hk);
 
     // Algorithm 1: per-node minimum over its own hyperedges' keys
     run_match_keys(cx, f, sact, b.key, hkey);
     launch(lc, "decode", 16.0 * N, k_decode, ceil_div(N, kBlock), kBlock, 0, N,
            (const uint64_t *)b.key, (const int32_t *)f.nseg, (const int32_t *)f.hbase,
-           (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cnt, b.gw);
+           (const uint8_t *)sact, (const int32_t *)f.nw, b.match, b.cg);
 
     // Algorithm 2, singletons
     AttachOp aop{(const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg, (const uint8_t *)sact,
-                 (const int32_t *)b.match, (const int32_t *)b.cnt, (const int32_t *)b.gw, b.grp};
+                 (const int32_t *)b.match, (const uint64_t *)b.cg, b.grp};
     launch(lc, "attach", 4.0 * E, k_buckets<AttachOp>, buckets_grid(E, f.nmid, f.nbig), kBlock, 0, aop, E, f.nmid,
            (const int32_t *)f.lmid, f.nbig, (const int32_t *)f.lbig);
     launch(lc, "lead", 12.0 * N, k_lead, ceil_div(N, kBlock), kBlock, 0, N,
            (const int32_t *)f.nseg, (const uint8_t *)sact, (const int32_t *)b.match,
-           (const int32_t *)b.cnt, b.grp, b.lead);
+           (const uint64_t *)b.cg, b.grp, b.lead);
 
     // coarse node ids: exclusive scan of leader flags
     {
@@ -1877,13 +1876,12 @@ bp_status bp_step_match(const bp_hypergraph *hg, int32_t policy, int32_t *d_matc
     uint8_t *sact = cx.ar->get<uint8_t>(1);
     fill(cx.lc, sact, 1, (uint8_t)1);
     uint64_t *key = cx.ar->get<uint64_t>(L.N);
-    int32_t *cnt = cx.ar->get<int32_t>(L.E), *gw = cx.ar->get<int32_t>(L.E);
+    uint64_t *cg = cx.ar->get<uint64_t>(L.E);
     run_match_keys(cx, L, sact, key);
-    fill(cx.lc, cnt, L.E, 0);
-    fill(cx.lc, gw, L.E, 0);
+    fill(cx.lc, cg, L.E, (uint64_t)0);
     launch(cx.lc, "decode", 0.0, k_decode, ceil_div(L.N, kBlock), kBlock, 0, L.N,
            (const uint64_t *)key, (const int32_t *)L.nseg, (const int32_t *)L.hbase,
-           (const uint8_t *)sact, (const int32_t *)L.nw, d_match, cnt, gw);
+           (const uint8_t *)sact, (const int32_t *)L.nw, d_match, cg);
     return BP_OK;
     BP_GUARD_END
 }
