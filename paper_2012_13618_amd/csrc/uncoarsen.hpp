@@ -993,21 +993,29 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     __shared__ uint64_t keys[kKeys], sorted[KIND == 1 ? kKeys : 1];
     __shared__ uint8_t sdl[kCap];  // the segment's sides
     __shared__ int32_t nkeys;
-    if (go && *go == 0) return;
+    // the round's flag is loaded together with what the block reads next (all
+    // in bounds: the grid never exceeds the segments or the chunk table, and a
+    // chunk entry past the count is not used)
+    const int32_t gv = go ? *go : 1;
     int32_t s, a0, n;
+    uint8_t md;
     if (CH) {
         int32_t ci = blockIdx.x;
-        if (ci >= ca.count[0]) return;
+        int32_t cc = ca.count[0];
         s = ca.seg[ci];
         a0 = ca.beg[ci];
+        if (gv == 0 || ci >= cc) return;
         n = min(sv.nbase[s + 1] - a0, kChunkNodes);
+        md = sv.mode[s];
     } else {
         s = blockIdx.x;
         a0 = sv.nbase[s];
-        n = sv.nbase[s + 1] - a0;
+        int32_t a1 = sv.nbase[s + 1];
+        md = sv.mode[s];
+        if (gv == 0) return;
+        n = a1 - a0;
     }
     const int idbits = CH ? bitlen_u32((uint32_t)max(n - 1, 0)) : idbits_lv;
-    uint8_t md = sv.mode[s];
     int32_t g[kSegItems];
     uint64_t sbits = 0, ebits = 0;  // bit j: item j's side, item j eligible for its side's list
     // per list: size and gain extremes, from the gains just loaded
@@ -1252,10 +1260,12 @@ __global__ __launch_bounds__(1024) void k_bal_merge(int32_t S, const int32_t *nb
     __shared__ int64_t lds64[16];
     __shared__ int32_t cnt[kChunkMax], p1s, fits;
     __shared__ int64_t movedw;
-    if (go && *go == 0) return;
+    // the round's flag, the mode and the bounds loaded together (s < S)
+    const int32_t gv = go ? *go : 1;
     int32_t s = blockIdx.x;
-    if (!bf.mode[s]) return;
+    uint8_t md = bf.mode[s];
     int32_t n = nbase[s + 1] - nbase[s];
+    if (gv == 0 || !md) return;
     int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
     const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
     // every slot of the segment's lists (past a list's count: unused), with the counts
