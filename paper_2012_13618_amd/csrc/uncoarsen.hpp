@@ -225,10 +225,11 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
     __shared__ int32_t queue[kUpdQueue], bigq[kUpdQueue];  // bigq: wavefront ones from the front, workgroup ones from the back
     __shared__ int32_t nq, nbq, nhq, npins;
     __shared__ int32_t lds[16];
-    if (go && *go == 0) return;
+    const int32_t gv = go ? *go : 1, nbig = ncount[1];  // loaded together
+    if (gv == 0) return;
     // the move log was read by the previous launch: empty it for this round's moves
     if (logcount && blockIdx.x == 0 && threadIdx.x == 0) *logcount = 0;
-    int32_t nb = min(ncount[1], kUpdSlots);
+    int32_t nb = min(nbig, kUpdSlots);
     for (int i = threadIdx.x; i < nb; i += blockDim.x) slot[i] = 0;
     int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int64_t G = gridDim.x;
@@ -813,8 +814,9 @@ __global__ __launch_bounds__(kBlock) void k_select_pass(int32_t N, int p, int32_
     __shared__ uint32_t h[2 * kBins];
     __shared__ int64_t lds[16];
     __shared__ int last;
-    if (go && *go == 0) return;
-    if (p > 0 && st.ctl[0] <= 0) return;
+    const int32_t gv = go ? *go : 1, ctl = st.ctl[0];  // loaded together
+    if (gv == 0) return;
+    if (p > 0 && ctl <= 0) return;
     int64_t v0 = (int64_t)blockIdx.x * kSelNodes;
     if (v0 < N) {
         int64_t v1 = v0 + kSelNodes < N ? v0 + kSelNodes : N;
@@ -905,8 +907,9 @@ __global__ __launch_bounds__(kBlock) void k_select_pick(int32_t nlists, int p, i
                                                         SelState st, const int32_t *go, int32_t clip)
 {
     __shared__ int64_t lds[16];
-    if (go && *go == 0) return;
-    if (p > 0 && st.ctl[0] <= 0) return;
+    const int32_t gv = go ? *go : 1, ctl = st.ctl[0];  // loaded together
+    if (gv == 0) return;
+    if (p > 0 && ctl <= 0) return;
     int32_t c = blockIdx.x;
     if (c >= nlists) return;
     sel_pick_list(st, c, p, idbits, sv.mode, sv.m, lds, clip);
