@@ -107,12 +107,11 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
 // hyperedge in the bitmap.  The chunk's hyperedges ascend, so lanes sharing a
 // bitmap word are adjacent and the first lane of each run sets the run's bits
 // with one atomic (none when they are all set already).  Here: blocks b of nb
-// (kBlock threads each) of the marking.
-__device__ __forceinline__ void log_hedges_blocks(int64_t b, int64_t nb, const int32_t *count, const int32_t *cnode,
+// (kBlock threads each) of the marking of the n logged chunks.
+__device__ __forceinline__ void log_hedges_blocks(int64_t b, int64_t nb, int32_t n, const int32_t *cnode,
                                                   const int32_t *cbeg, const int32_t *noff, const int32_t *inc,
                                                   uint32_t *bits)
 {
-    int32_t n = count[0];
     int lane = threadIdx.x & 63;
     const int64_t wpb = kBlock / 64;
     for (int64_t i = b * wpb + (threadIdx.x >> 6); i < n; i += nb * wpb) {
@@ -1556,8 +1555,10 @@ __global__ __launch_bounds__(kBlock) void k_round_balance_log(int64_t gs, RoundB
         round_balance_seg(blockIdx.x * blockDim.x + threadIdx.x, rb, st, go, ri);
         return;
     }
-    if (go[4 + (ri + 2) % 3] == 0) return;  // the previous round moved nothing
-    log_hedges_blocks((int64_t)blockIdx.x - gs, (int64_t)gridDim.x - gs, count, cnode, cbeg, noff, inc, bits);
+    // the previous round's counter and its log size, loaded together
+    const int32_t prev = go[4 + (ri + 2) % 3], n = count[0];
+    if (prev == 0) return;  // the previous round moved nothing
+    log_hedges_blocks((int64_t)blockIdx.x - gs, (int64_t)gridDim.x - gs, n, cnode, cbeg, noff, inc, bits);
 }
 
 
