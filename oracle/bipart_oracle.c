@@ -66,12 +66,11 @@ uint32_t oracle_hash32(uint32_t x)
     return x;
 }
 
-/* Smallest m with m*m >= n ("sqrt(n) nodes", Algorithm 3). */
+/* Smallest m with m*m >= n ("sqrt(n) nodes", Algorithm 3), by counting up. */
 static int64_t ceil_sqrt(int64_t n)
 {
-    int64_t m = (int64_t)sqrt((double)n);
+    int64_t m = 0;
     while (m * m < n) m++;
-    while (m > 0 && (m - 1) * (m - 1) >= n) m--;
     return m;
 }
 
@@ -349,6 +348,10 @@ uint64_t oracle_eps_factor(int32_t k, double eps)
     while (((int64_t)1 << levels) < (int64_t)k) levels++;
     if (levels < 1) levels = 1;
     double f = pow(1.0 + eps, 1.0 / (double)levels);
+    /* Any factor of 2^30 or more already lets one side hold the whole weight
+     * (weights sum below 2^31), so larger ones are capped at 2^62: the bounds
+     * they give behave identically, and the conversion stays in range. */
+    if (!(f < 1073741824.0)) return (uint64_t)1 << 62;
     return (uint64_t)floor(ldexp(f, 32));
 }
 

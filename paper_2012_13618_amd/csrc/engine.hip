@@ -948,6 +948,11 @@ uint64_t eps_factor(int32_t k, double eps)
     while (((int64_t)1 << levels) < (int64_t)k) levels++;
     if (levels < 1) levels = 1;
     double f = std::pow(1.0 + eps, 1.0 / (double)levels);
+    // A factor of 2^30 or more lets either side of any split hold all of the
+    // weight (sums stay below 2^31 and a side's share is at least a third), so
+    // every such factor gives the same bounds: cap it where the conversion and
+    // the bound products stay in range.
+    if (!(f < 1073741824.0)) return uint64_t(1) << 62;
     return (uint64_t)std::floor(std::ldexp(f, 32));
 }
 
@@ -1010,7 +1015,9 @@ static int64_t validate_device(Ctx &cx, const Input &in)
 // with (1+eps) in 32.32 fixed point.
 int64_t part_limit(int64_t W, int32_t k, double eps)
 {
-    uint64_t F0 = (uint64_t)std::floor(std::ldexp(1.0 + eps, 32));
+    // 1 + eps at or above 2^31 exceeds every k, so the limit is at least W either way.
+    double f = 1.0 + eps;
+    uint64_t F0 = f < 2147483648.0 ? (uint64_t)std::floor(std::ldexp(f, 32)) : uint64_t(1) << 63;
     unsigned __int128 a = (unsigned __int128)(uint64_t)W * F0;
     int64_t lim_f = (int64_t)(a / ((unsigned __int128)(uint64_t)k << 32));
     int64_t lim_c = (W + k - 1) / k;

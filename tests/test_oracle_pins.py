@@ -102,7 +102,7 @@ def test_gains_golden():
 
 # ---- matching (Algorithm 1) ------------------------------------------------------
 
-@pytest.mark.parametrize("name", ["fig2_coarsen.json", "singleton_dedup.json"])
+@pytest.mark.parametrize("name", ["fig2_coarsen.json", "singleton_dedup.json", "singleton_candidates.json"])
 def test_match_golden(name):
     gd = golden(name)
     m = oracle.match(gd["n"], gd["offsets"], gd["pins"], hw=gd["hedge_w"])
@@ -141,7 +141,7 @@ def test_match_is_lexicographic_argmin(policy, seed):
 
 # ---- coarsening (Algorithm 2) ----------------------------------------------------
 
-@pytest.mark.parametrize("name", ["fig2_coarsen.json", "singleton_dedup.json"])
+@pytest.mark.parametrize("name", ["fig2_coarsen.json", "singleton_dedup.json", "singleton_candidates.json"])
 def test_coarsen_golden(name):
     gd = golden(name)
     parent, coff, cpins, cnw, chw = oracle.coarsen(gd["n"], gd["offsets"], gd["pins"],
@@ -285,6 +285,114 @@ def test_balance_postcondition(seed):
         assert not stuck
 
 
+# ---- the multilevel bisection (Section 2.3, Algorithm 5, Section 3.4) ---------------
+
+def _arr(x):
+    return np.asarray(x, np.int32)
+
+
+def test_multilevel_golden_trace():
+    gd = golden("multilevel.json")
+    lv = gd["levels"]
+    mx = gd["max_side_weight"]
+    assert oracle.bounds(9, 1, 1, F105) == (mx, mx)
+    # coarsening: every level's parents and the next level's graph
+    for j in range(len(lv) - 1):
+        f, c = lv[j], lv[j + 1]
+        parent, coff, cpins, cnw, chw = oracle.coarsen(f["n"], f["offsets"], f["pins"], nw=f["node_w"])
+        assert list(parent) == f["parent"], f"level {j} parents"
+        assert list(coff) == c["offsets"] and list(cpins) == c["pins"], f"level {j + 1} hyperedges"
+        assert list(cnw) == c["node_w"] and len(cnw) == c["n"], f"level {j + 1} weights"
+        assert np.all(chw == 1)
+    # the coarsest level: initial bisection, then its own refinement
+    top = lv[-1]
+    side = oracle.initial(top["n"], top["offsets"], top["pins"], 1, 1, nw=top["node_w"])
+    assert list(side) == gd["coarsest_initial"]
+    side, _ = oracle.refine(top["n"], top["offsets"], top["pins"], side, mx, mx, nw=top["node_w"])
+    assert list(side) == gd["coarsest_refined"]
+    # uncoarsening: projection through the parents, refinement of every level
+    for step in gd["uncoarsen"]:
+        L = lv[step["level"]]
+        side = side[_arr(L["parent"])]
+        assert list(side) == step["projected"], f"level {step['level']} projection"
+        side, _ = oracle.refine(L["n"], L["offsets"], L["pins"], side, mx, mx, nw=L["node_w"])
+        assert list(side) == step["refined"], f"level {step['level']} refinement"
+    # the whole bisection in one call follows the same trace
+    got, levels = oracle.bisect(gd["n"], gd["offsets"], gd["pins"], 1, 1, F105,
+                                prm=oracle.params(min_coarse_nodes=0))
+    assert levels == len(lv) - 1
+    assert list(got) == gd["final_side"]
+    assert oracle.cut(gd["n"], gd["offsets"], gd["pins"], got.astype(np.int32), 2)[0] == gd["final_cut"]
+
+
+def test_multilevel_golden_coarsest_at_threshold():
+    gd = golden("multilevel.json")
+    c = gd["coarsest_level1"]
+    L1 = gd["levels"][1]
+    mx = gd["max_side_weight"]
+    side = oracle.initial(L1["n"], L1["offsets"], L1["pins"], 1, 1, nw=L1["node_w"])
+    assert list(side) == c["initial"]
+    side, _ = oracle.refine(L1["n"], L1["offsets"], L1["pins"], side, mx, mx, nw=L1["node_w"])
+    assert list(side) == c["refined"]
+    got, levels = oracle.bisect(gd["n"], gd["offsets"], gd["pins"], 1, 1, F105,
+                                prm=oracle.params(min_coarse_nodes=4))
+    assert levels == 1 and list(got) == c["final_side"]
+
+
+def test_stop_rule_closed_forms():
+    gd = golden("multilevel.json")
+    for c in gd["stop_rule"]["cases"]:
+        prm = oracle.params(max_levels=c["max_levels"], min_coarse_nodes=c["min_coarse_nodes"])
+        _, levels = oracle.bisect(gd["n"], gd["offsets"], gd["pins"], 1, 1, F105, prm=prm)
+        assert levels == c["levels"], c
+    # disjoint pairs: one step merges every pair and leaves no hyperedge, so
+    # coarsening stops there whatever the node threshold and level limit
+    off, pins = [0, 2, 4, 6, 8], list(range(8))
+    for t in (0, 1, 3):
+        _, levels = oracle.bisect(8, off, pins, 1, 1, F105, prm=oracle.params(min_coarse_nodes=t))
+        assert levels == 1
+    # one hyperedge over every node: one step to a single node
+    _, levels = oracle.bisect(6, [0, 6], list(range(6)), 1, 1, F105, prm=oracle.params(min_coarse_nodes=0))
+    assert levels == 1
+
+
+def _vcycle(h, k0, k1, F, prm):
+    """The multilevel scheme re-driven from Python over the single steps:
+    coarsen while the stop rule allows, partition the coarsest graph, then
+    project and refine every level up to the input."""
+    W = int(h.node_w.sum())
+    m0, m1 = oracle.bounds(W, k0, k1, F)
+    lv = [(h.num_nodes, h.offsets, h.pins, h.node_w, h.hedge_w)]
+    parents = []
+    while (len(parents) < prm.max_levels and len(lv[-1][1]) > 1
+           and lv[-1][0] > prm.min_coarse_nodes):
+        n, off, pins, nw, hw = lv[-1]
+        parent, coff, cpins, cnw, chw = oracle.coarsen(n, off, pins, nw, hw, policy=prm.policy)
+        parents.append(parent)
+        lv.append((len(cnw), coff, cpins, cnw, chw))
+    n, off, pins, nw, hw = lv[-1]
+    side = oracle.initial(n, off, pins, k0, k1, nw=nw, hw=hw)
+    side, _ = oracle.refine(n, off, pins, side, m0, m1, prm.refine_iters, nw=nw, hw=hw)
+    for j in range(len(parents) - 1, -1, -1):
+        side = side[parents[j]]
+        n, off, pins, nw, hw = lv[j]
+        side, _ = oracle.refine(n, off, pins, side, m0, m1, prm.refine_iters, nw=nw, hw=hw)
+    return side, len(parents)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_bisect_is_the_multilevel_scheme(seed):
+    h = I.random_small(300, 330, 2, 6, seed, weighted_nodes=(seed % 2 == 1),
+                       weighted_hedges=(seed >= 2))
+    for t, maxl, k0, k1 in [(0, 25, 1, 1), (20, 25, 2, 1), (40, 2, 1, 1), (0, 1, 3, 2), (5, 4, 1, 1)]:
+        prm = oracle.params(max_levels=maxl, min_coarse_nodes=t, policy=seed % 5)
+        want, wl = _vcycle(h, k0, k1, F105, prm)
+        got, gl = oracle.bisect(h.num_nodes, h.offsets, h.pins, k0, k1, F105, nw=h.node_w, hw=h.hedge_w,
+                                prm=prm)
+        assert gl == wl and np.array_equal(got, want), (t, maxl, k0, k1)
+    assert wl >= 1
+
+
 # ---- bounds and eps ---------------------------------------------------------------
 
 def test_bounds_closed_forms():
@@ -305,6 +413,20 @@ def test_eps_factor():
     assert abs(f ** 3 - 1.03) < 1e-8
     f = oracle.eps_factor(5, 0.1) / 2 ** 32   # ceil(log2 5) = 3 tree levels
     assert abs(f ** 3 - 1.1) < 1e-8
+
+
+def test_huge_eps_is_unconstrained():
+    # A per-bisection factor of 2^30 or more lets either side hold the whole
+    # weight, so all such factors give the same result; they are capped at 2^62.
+    assert oracle.eps_factor(2, 1e12) == 1 << 62
+    assert oracle.eps_factor(8, 1e300) == 1 << 62
+    assert oracle.eps_factor(2, 2.0 ** 30 - 2) == (2 ** 30 - 1) << 32
+    h = I.random_small(200, 240, 2, 6, 3, weighted_nodes=True)
+    W = int(h.node_w.sum())
+    assert min(oracle.bounds(W, 2, 1, 1 << 62)) >= W
+    a = oracle.partition_hg(h, k=3, eps=1e12)
+    b = oracle.partition_hg(h, k=3, eps=1e6)     # bound already above W, uncapped
+    assert np.array_equal(a[0], b[0]) and a[1] == b[1]
 
 
 # ---- k-way (Algorithm 6) and the whole method --------------------------------------
