@@ -134,7 +134,7 @@ def test_batch_invalid_member_is_named(bp):
 def test_full_batch_256(bp):
     """The 256-graph batch (k = 2 for even members, 4 for odd): the batched run
     equals the single-graph GPU path on every member and the oracle on the
-    eight smallest members."""
+    eight smallest and the eight largest members."""
     import torch
     say("full batch 256: generating")
     hs = [I.batch_member(i) for i in range(256)]
@@ -145,8 +145,9 @@ def test_full_batch_256(bp):
     parts, cuts, st, reps = bp.partition_batch_device(dev, ks, es)
     torch.cuda.synchronize()
     say("  launches", reps[0].kernel_launches, "syncs", reps[0].host_syncs)
-    small = sorted(range(256), key=lambda i: hs[i].num_pins)[:8]
-    for i in small:
+    by_size = sorted(range(256), key=lambda i: hs[i].num_pins)
+    for i in by_size[:8] + by_size[-8:]:
+        say("  oracle on member", i, hs[i].num_pins, "pins")
         ref_part, ref_cut = oracle.partition_hg(hs[i])
         assert np.array_equal(parts[i].cpu().numpy(), ref_part), i
         assert cuts[i] == ref_cut, i

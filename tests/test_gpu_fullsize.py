@@ -1,0 +1,92 @@
+"""Oracle parity at the full workload sizes, in the launch configuration the
+benchmark times (one bp_partition_device call on inputs already in HBM).
+
+- column-net, 4M rows x 4M columns, nonzeros per column power-law 2.1 on
+  [1, 5000] (16.2M pins), k = 8, eps = 0.03: compared element by element with
+  the oracle, which runs on a host thread while the GPU works;
+- the same shape on [2, 5000] (38.0M pins): the oracle needs minutes there, so
+  its result was stored by tests/golden/make_fullsize_oracle.py (which calls
+  only the oracle); the GPU part vector must hash to the same SHA-256, with the
+  same cut, part sizes, part weights and sampled part ids.
+"""
+import hashlib
+import sys
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2012_13618_amd import inputs as I
+from tests.conftest import golden
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bp():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_13618_amd as mod
+    mod.lib()
+    return mod
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _gpu_partition(bp, h):
+    import torch
+    dh = bp.DeviceHypergraph.from_host(h)
+    part = torch.empty(h.num_nodes, dtype=torch.int32, device="cuda")
+    _, cut, status, rep = bp.partition_device(dh, h.meta["k"], h.meta["eps"], part_out=part)
+    torch.cuda.synchronize()
+    got = part.cpu().numpy()
+    del dh, part
+    return got, cut, status, rep
+
+
+def test_colnet_4m_k8_equals_oracle(bp):
+    say("column-net 4M (d in [1,5000]) k=8: generating")
+    h = I.column_net()
+    box = {}
+
+    def run_oracle():
+        t0 = time.time()
+        box["ref"] = oracle.partition_hg(h)
+        box["s"] = time.time() - t0
+
+    th = threading.Thread(target=run_oracle)
+    th.start()
+    say("  oracle started on a host thread; GPU partition", h.num_pins, "pins")
+    got, cut, status, rep = _gpu_partition(bp, h)
+    say("  GPU done: cut", cut, "tree levels", rep.tree_levels, "bisections", rep.bisections)
+    while th.is_alive():
+        th.join(20)
+        say("  waiting for the oracle ...")
+    ref_part, ref_cut = box["ref"]
+    say(f"  oracle done in {box['s']:.1f} s: cut {ref_cut}")
+    assert rep.tree_levels == 3 and rep.bisections == 7
+    diff = np.flatnonzero(got != ref_part)
+    assert diff.size == 0, f"{diff.size} nodes differ, first {diff[:10].tolist()}"
+    assert cut == ref_cut
+
+
+def test_colnet_4m_pl2_k8_equals_stored_oracle(bp):
+    ref = golden("fullsize_oracle.json")["colnet4m_d2_k8"]
+    say("column-net 4M (d in [2,5000]) k=8: generating")
+    h = I.column_net(dmin=2)
+    assert (h.num_nodes, h.num_hedges, h.num_pins) == (ref["nodes"], ref["hedges"], ref["pins"])
+    say("  GPU partition", h.num_pins, "pins")
+    got, cut, status, rep = _gpu_partition(bp, h)
+    say("  GPU done: cut", cut, "stored oracle cut", ref["cut"])
+    k = ref["k"]
+    assert np.array_equal(got[::ref["sample_stride"]], np.asarray(ref["sample"], np.int32))
+    assert np.bincount(got, minlength=k).tolist() == ref["part_sizes"]
+    assert np.bincount(got, weights=h.node_w, minlength=k).astype(np.int64).tolist() == ref["part_weights"]
+    assert cut == ref["cut"]
+    assert hashlib.sha256(np.ascontiguousarray(got, dtype="<i4").tobytes()).hexdigest() == ref["sha256"]
