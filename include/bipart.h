@@ -150,6 +150,21 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
                               bp_report *report, void *stream);
 
 /*
+ * Device memory: each call works in an arena of device memory that is kept,
+ * per device, for the next call (steady calls allocate nothing).  A call that
+ * used less than a quarter of its arena (and the arena holds over 1 GiB)
+ * frees the excess when it ends.  bp_release_memory frees every arena of the
+ * current device that no call is using; later calls allocate again.
+ */
+bp_status bp_release_memory(void);
+
+/* Caps the device memory one call's arena may hold at `bytes` (0 = no cap,
+ * the default; process-wide).  A call that would need more fails with
+ * BP_ERR_OUT_OF_MEMORY and leaves the library usable.  BP_ERR_INVALID_ARG for
+ * a negative value. */
+bp_status bp_set_memory_limit(int64_t bytes);
+
+/*
  * Batched form: n independent hypergraphs partitioned in ONE device run.  All
  * graphs are segments of the same levels (the nested scheme of Algorithm 6
  * with every graph as a root bisection), so the launch sequence and the

@@ -32,7 +32,7 @@ EXPORTS = [
     "bp_partition_batch_device", "bp_server_default_config", "bp_request_footprint",
     "bp_server_create", "bp_server_submit", "bp_server_wait", "bp_server_destroy",
     "bp_profile_floor", "bp_schedule_default", "bp_schedule_set", "bp_schedule_get",
-    "bp_autotune_batch_device",
+    "bp_autotune_batch_device", "bp_release_memory", "bp_set_memory_limit",
 ]
 
 
@@ -144,6 +144,8 @@ def lib():
         L.bp_schedule_set.argtypes = [P]
         L.bp_schedule_get.argtypes = [P]
         L.bp_autotune_batch_device.argtypes = [i32, P, P, P, P, P, i32, P, P, P]
+        L.bp_release_memory.argtypes = []
+        L.bp_set_memory_limit.argtypes = [i64]
         for name in EXPORTS:
             f = getattr(L, name)
             if f.restype is ctypes.c_int:
@@ -346,6 +348,16 @@ def partition_device(dh: DeviceHypergraph, k, eps, prm: Params | None = None, pa
                                           part_out.data_ptr(), ctypes.byref(cut),
                                           ctypes.byref(rep), _stream()))
     return part_out[:dh.num_nodes], int(cut.value), st, rep
+
+
+def release_memory():
+    """Frees the cached device memory of every idle call context of the current device."""
+    _check(lib().bp_release_memory())
+
+
+def set_memory_limit(nbytes):
+    """Caps the device memory one call may hold (0 = no cap)."""
+    _check(lib().bp_set_memory_limit(int(nbytes)))
 
 
 def partition_batch_device(dhs, ks, epss, prm: Params | None = None, parts_out=None):

@@ -1,6 +1,7 @@
 // Shared helpers of the gfx950 partitioner: error handling, launch wrapper,
 // device memory arena, hashing and wave64/workgroup reductions and scans.
 #pragma once
+#include <atomic>
 
 #include <hip/hip_runtime.h>
 
@@ -218,11 +219,23 @@ inline void launch(LaunchCtx &lc, const char *name, double bytes, K kernel, int6
 
 // ---- device memory arena ----------------------------------------------------
 // Bump allocator over large hipMalloc blocks; reset() keeps the blocks for
-// reuse by the next call, so steady-state calls allocate nothing.
+// reuse by the next call, so steady-state calls allocate nothing.  An arena
+// made with adopt() works inside one caller-provided block instead and never
+// allocates: running out of it is BP_ERR_OUT_OF_MEMORY.
+
+// Process-wide ceiling on the device memory one arena may hold (0 = none).
+inline std::atomic<int64_t> g_arena_limit{0};
 
 class Arena {
   public:
     ~Arena() { release(); }
+    // Use [base, base + size) as the only block; nothing is ever allocated or freed.
+    void adopt(void *base, size_t size)
+    {
+        release();
+        fixed_ = true;
+        blocks_.push_back({(char *)base, size, 0});
+    }
     void *alloc(size_t bytes)
     {
         bytes = (bytes + 255) & ~size_t(255);
@@ -234,9 +247,18 @@ class Arena {
                 b.used += bytes;
                 return p;
             }
+            if (fixed_) break;
             cur_++;
         }
+        if (fixed_)
+            throw Error(BP_ERR_OUT_OF_MEMORY, "the fixed device workspace of " +
+                                                  std::to_string(blocks_.empty() ? 0 : blocks_[0].size) +
+                                                  " bytes is too small for this input");
         size_t sz = bytes > kChunk ? bytes : kChunk;
+        int64_t lim = g_arena_limit.load();
+        if (lim > 0 && (int64_t)(reserved() + sz) > lim)
+            throw Error(BP_ERR_OUT_OF_MEMORY, "device memory limit of " + std::to_string(lim) +
+                                                  " bytes per call reached");
         char *p = nullptr;
         hipError_t e = hipMalloc(&p, sz);
         if (e != hipSuccess) {
@@ -253,9 +275,23 @@ class Arena {
         for (auto &b : blocks_) b.used = 0;
         cur_ = 0;
     }
+    // Frees every block beyond the first `keep` bytes' worth (blocks are
+    // freed whole, last first); call only between calls (after reset()).
+    void trim(size_t keep)
+    {
+        if (fixed_) return;
+        size_t total = reserved();
+        while (!blocks_.empty() && total > keep) {
+            total -= blocks_.back().size;
+            (void)hipFree(blocks_.back().ptr);
+            blocks_.pop_back();
+        }
+        cur_ = 0;
+    }
     void release()
     {
-        for (auto &b : blocks_) (void)hipFree(b.ptr);
+        if (!fixed_)
+            for (auto &b : blocks_) (void)hipFree(b.ptr);
         blocks_.clear();
         cur_ = 0;
     }
@@ -281,6 +317,7 @@ class Arena {
     };
     std::vector<Block> blocks_;
     size_t cur_ = 0;
+    bool fixed_ = false;
 };
 
 // ---- hashing -----------------------------------------------------------------

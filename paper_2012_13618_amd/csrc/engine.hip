@@ -1314,10 +1314,17 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
 }
 
 // ---- context pool -------------------------------------------------------------------
+// Arenas of finished calls are kept per device for the next call, so steady
+// calls allocate nothing.  A call that used much less than its arena holds
+// trims it (a large input followed by small ones does not pin gigabytes), and
+// bp_release_memory frees every idle arena of the current device.
+
+constexpr int kMaxDevices = 64;
+constexpr size_t kTrimFloor = size_t(1) << 30;
 
 struct Pool {
     std::mutex mu;
-    std::vector<Arena *> arenas;
+    std::vector<Arena *> arenas[kMaxDevices];
     std::vector<void *> pinned;
     static Pool &get()
     {
@@ -1326,16 +1333,27 @@ struct Pool {
     }
 };
 
+static int current_device()
+{
+    int dev = 0;
+    BP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Error(BP_ERR_DEVICE, "device id beyond the supported range");
+    return dev;
+}
+
 struct CtxGuard {
     Ctx cx;
+    int dev = 0;
+    bool pooled = true;
     CtxGuard(hipStream_t stream, const bp_params *p)
     {
+        dev = current_device();
         Pool &pl = Pool::get();
         {
             std::lock_guard<std::mutex> g(pl.mu);
-            if (!pl.arenas.empty()) {
-                cx.ar = pl.arenas.back();
-                pl.arenas.pop_back();
+            if (!pl.arenas[dev].empty()) {
+                cx.ar = pl.arenas[dev].back();
+                pl.arenas[dev].pop_back();
             }
             if (!pl.pinned.empty()) {
                 cx.info_h = (LevelInfo *)pl.pinned.back();
@@ -1344,8 +1362,20 @@ struct CtxGuard {
         }
         if (!cx.ar) cx.ar = new Arena();
         if (!cx.info_h) BP_HIP(hipHostMalloc((void **)&cx.info_h, 4096, hipHostMallocDefault));
+        init(stream, p, Profiler::get().on);
+    }
+    // A context over a caller-owned arena and host readback buffer, outside
+    // the pool (no allocation at all, no profiling events).
+    CtxGuard(hipStream_t stream, const bp_params *p, Arena *fixed, LevelInfo *info) : pooled(false)
+    {
+        cx.ar = fixed;
+        cx.info_h = info;
+        init(stream, p, false);
+    }
+    void init(hipStream_t stream, const bp_params *p, bool prof)
+    {
         cx.lc.stream = stream;
-        cx.lc.prof = Profiler::get().on;
+        cx.lc.prof = prof;
         cx.info_d = cx.ar->get<LevelInfo>(1);
         bp_default_params(&cx.prm);
         if (p) cx.prm = *p;
@@ -1358,13 +1388,29 @@ struct CtxGuard {
         }
         // everything queued must finish before the arena is reused
         (void)hipStreamSynchronize(cx.lc.stream);
+        size_t used = cx.ar->used();
         cx.ar->reset();
+        if (!pooled) return;
+        if (cx.ar->reserved() > std::max(4 * used, kTrimFloor)) cx.ar->trim(std::max(2 * used, kTrimFloor));
         Pool &pl = Pool::get();
         std::lock_guard<std::mutex> g(pl.mu);
-        pl.arenas.push_back(cx.ar);
+        pl.arenas[dev].push_back(cx.ar);
         pl.pinned.push_back(cx.info_h);
     }
 };
+
+// Frees the device memory of every idle arena of the current device.
+static void release_idle_arenas()
+{
+    int dev = current_device();
+    Pool &pl = Pool::get();
+    std::vector<Arena *> idle;
+    {
+        std::lock_guard<std::mutex> g(pl.mu);
+        idle.swap(pl.arenas[dev]);
+    }
+    for (Arena *a : idle) delete a;
+}
 
 }  // namespace bp
 
@@ -1554,6 +1600,21 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
     BP_GUARD_BEGIN
     CtxGuard g((hipStream_t)stream, params);
     return partition_device(g.cx, device_input(hg), k, eps, d_part_out, cut_out, report);
+    BP_GUARD_END
+}
+
+bp_status bp_set_memory_limit(int64_t bytes)
+{
+    if (bytes < 0) return fail(BP_ERR_INVALID_ARG, "negative memory limit");
+    g_arena_limit.store(bytes);
+    return BP_OK;
+}
+
+bp_status bp_release_memory(void)
+{
+    BP_GUARD_BEGIN
+    release_idle_arenas();
+    return BP_OK;
     BP_GUARD_END
 }
 

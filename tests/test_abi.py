@@ -112,3 +112,8 @@ def test_schedule_defaults_and_validation():
             _expect(-1, lambda: bp.schedule_set(s))
     finally:
         bp.schedule_set(old)
+
+
+def test_memory_limit_argument_check():
+    _expect(-1, lambda: bp.set_memory_limit(-1))
+    bp.set_memory_limit(0)
