@@ -5,9 +5,12 @@ initial bisection, projection + refinement at every level, every tree level
 of the recursive bisection, and the final cut) on inputs already in HBM.
 Prints ONE JSON line on stdout; details go to stderr.
 
-Default workload: the netlist-shaped hypergraph (1,000,000 unit nodes,
-1,200,000 hyperedges, degrees power-law 2.5 on [2,1000], 80% of pins within
-+-2000 of an anchor), k = 2, eps = 0.05.
+Default workload: the sparse-matrix column-net hypergraph (4,000,000 rows as
+nodes, 4,000,000 columns as hyperedges, nonzeros per column power-law 2.1 on
+[1,5000], 16.2M pins, node weight = row nonzeros), k = 8 by recursive
+bisection (three tree levels), eps = 0.03.  Other workloads: --workload
+colnet2 (the same on [2,5000], 38.0M pins), vlsi (netlist-shaped, 1M nodes,
+k = 2), tiny, batch, serve.
 """
 import argparse
 import json
@@ -20,7 +23,34 @@ sys.path.insert(0, ROOT)
 
 METRIC = "pins/sec full k-way partition (coarsen+refine) vs HBM roofline; p99 latency served"
 HBM_PEAK_GBS = 8000.0
-WORKLOAD_TAG = {"vlsi": "vlsi1m_k2", "colnet": "colnet4m_k8", "tiny": "tiny1k_k2"}
+WORKLOAD_TAG = {"vlsi": "vlsi1m_k2", "colnet": "colnet4m_k8", "colnet2": "colnet4m_pl2_k8",
+                "tiny": "tiny1k_k2"}
+
+# Kernel families by phase of the multilevel scheme: coarsening (Algorithms 1
+# and 2 with the incidence each level needs) and uncoarsening (Algorithms 3-5:
+# projection, gains, swaps, balance rounds).  The rest (validation, level-0
+# copy, k-way extraction, cut) is "other".
+PHASE_OF = {
+    "coarsen": ["match", "match_chunks", "hedge_keys", "coarsen_init", "decode", "attach", "lead",
+                "parent", "qbuild", "qbuild_block", "qbuild_huge", "dedup", "copy_pins", "classify",
+                "node_ids", "hedge_ids", "incidence", "radix_hist", "radix_scatter", "level_fixup"],
+    "refine": ["project", "side_weights", "gain_nodes", "gain_hedges", "gain_stats", "gain_update",
+               "select", "select_pick", "seg_select", "seg_balance", "seg_initial", "balance", "flip",
+               "round", "level_bound"],
+}
+
+
+def host_cpu():
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "model": model}
 
 
 def log(*a):
@@ -36,11 +66,11 @@ def make_workload(name):
     elif name == "colnet":
         h = I.column_net()
         desc = ("column-net sparse matrix: N=E=4,000,000, nnz per column power-law alpha=2.1 on "
-                "[1,5000], node weight = row nnz")
+                "[1,5000] (16.2M pins), node weight = row nnz, k=8 (3 tree levels), eps=0.03")
     elif name == "colnet2":
         h = I.column_net(dmin=2)
         desc = ("column-net sparse matrix: N=E=4,000,000, nnz per column power-law alpha=2.1 on "
-                "[2,5000], node weight = row nnz")
+                "[2,5000] (38.0M pins), node weight = row nnz, k=8 (3 tree levels), eps=0.03")
     elif name == "tiny":
         h = I.tiny()
         desc = "random: N=1,000 unit nodes, E=2,000 hyperedges of degree U{2..8}"
@@ -65,23 +95,40 @@ def cpu_baseline_batch(hs, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
+    cpu = host_cpu()
     return {"value": pins / el, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": f"the first {runs} of the 256 members ({pins} pins), {el:.1f} s single-threaded"}
+            "sample": f"the first {runs} of the 256 members ({pins} pins), {el:.1f} s single-threaded",
+            "host_nproc": cpu["nproc"], "host_cpu": cpu["model"]}
 
 
-def cpu_baseline(h, k, eps, budget_s):
-    """The sequential oracle, single-threaded, on the same workload."""
+def cpu_sample(name, h):
+    """A bounded sample of the workload for the oracle (10-30 s on one core):
+    the workload itself, except the 38M-pin column-net, whose sample is the
+    same generator at half the rows and columns (same degree law, weights, k
+    and eps)."""
+    from paper_2012_13618_amd import inputs as I
+    if name == "colnet2":
+        s = I.column_net(n=2_000_000, dmin=2)
+        return s, (f"one full k={s.meta['k']} partition of the same column-net generator at half size "
+                   f"(N=E=2,000,000, {s.num_pins} pins)")
+    return h, f"full k={h.meta['k']} partition(s) of the workload itself ({h.num_pins} pins each)"
+
+
+def cpu_baseline(name, h, k, eps, budget_s):
+    """The sequential oracle as it stands, single-threaded, on a bounded sample."""
     import oracle
+    s, what = cpu_sample(name, h)
     runs, t0 = 0, time.perf_counter()
     while True:
-        oracle.partition_hg(h, k=k, eps=eps)
+        oracle.partition_hg(s, k=k, eps=eps)
         runs += 1
         el = time.perf_counter() - t0
         if el >= budget_s or runs >= 5:
             break
-    return {"value": h.num_pins * runs / el, "unit": "pins/s", "cores": 1, "kind": "oracle",
-            "sample": f"{runs} full run(s) of the same workload ({h.num_pins} pins each), "
-                      f"{el:.1f} s single-threaded"}
+    cpu = host_cpu()
+    return {"value": s.num_pins * runs / el, "unit": "pins/s", "cores": 1, "kind": "oracle",
+            "sample": f"{runs} x {what}, {el:.1f} s on one thread",
+            "host_nproc": cpu["nproc"], "host_cpu": cpu["model"]}
 
 
 # Kernel families and the device functions that implement them (for matching
@@ -144,6 +191,17 @@ def profiled_step(step, workload=None):
         gbs = s["bytes"] / (s["total_ms"] * 1e6) if s["total_ms"] > 0 else 0
         log(f"  {s['name']:<16} {s['launches']:6d} launches {s['total_ms']:8.3f} ms "
             f"(net {corr(s):8.3f}) avg {1000 * s['total_ms'] / s['launches']:8.2f} us  {gbs:8.1f} GB/s")
+    phases = {}
+    for ph, fams in PHASE_OF.items():
+        sel = [s for s in stats if s["name"] in fams]
+        b = sum(s["bytes"] for s in sel)
+        t = sum(s["total_ms"] for s in sel)
+        n = sum(s["launches"] for s in sel)
+        gbs = b / (t * 1e6) if t > 0 else 0.0
+        phases[ph] = {"algorithmic_bytes": round(b), "kernel_ms": round(t, 3), "launches": n,
+                      "achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"phase {ph}: {b / 1e9:.3f} GB algorithmic over {t:.3f} ms of kernel time in {n} launches "
+            f"= {gbs:.1f} GB/s ({100 * gbs / HBM_PEAK_GBS:.2f}% of peak)")
     dom = next((s for s in stats if s["bytes"] > 0), None)
     if not dom:
         return None
@@ -159,7 +217,9 @@ def profiled_step(step, workload=None):
             "algorithmic_bytes_per_launch": round(per_launch),
             "avg_launch_us": round(1e6 * avg_s, 3), "event_floor_us": round(1000 * floor_ms, 3),
             "launches_per_step": dom["launches"],
-            "share_of_kernel_time": round(dom["total_ms"] / tot, 4)}
+            "share_of_kernel_time": round(dom["total_ms"] / tot, 4),
+            # per phase: algorithmic bytes counted per launch over event-timed kernel time
+            "phases": phases}
 
 
 def bench_batch(args):
@@ -278,7 +338,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="vlsi")
+    ap.add_argument("--workload", default="colnet")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -344,14 +404,14 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(h, k, eps, args.cpu_budget)
+        cpu = cpu_baseline(args.workload, h, k, eps, args.cpu_budget)
         log(f"cpu oracle: {cpu['value'] / 1e6:.3f} Mpins/s ({cpu['sample']})")
 
     line = {"metric": METRIC, "value": value, "unit": "pins/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
             "data": "synthetic",
-            "config": {"workload": desc, "nodes": h.num_nodes, "hedges": h.num_hedges,
+            "config": {"workload": desc, "name": args.workload, "nodes": h.num_nodes, "hedges": h.num_hedges,
                        "pins": h.num_pins, "k": k, "eps": eps, "parallelism": "1 GPU",
                        "cut": cut},
             "roofline": roofline, "cpu_baseline": cpu}

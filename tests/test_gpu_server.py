@@ -99,7 +99,8 @@ def test_queued_requests_share_a_run(bp):
 
 
 def test_footprint_estimate_bounds_device_memory(bp):
-    cases = [(I.vlsi(), 2, 0.05), (I.column_net(), 8, 0.03), (I.serve_request(7), 16, 0.05),
+    cases = [(I.vlsi(), 2, 0.05), (I.vlsi(), 16, 0.05), (I.column_net(), 8, 0.03),
+             (I.column_net(dmin=2), 8, 0.03), (I.serve_request(7), 16, 0.05), (I.tiny(), 2, 0.05),
              (I.batch_member(255), 4, 0.05),
              (I.random_small(20000, 15000, 1, 400, 5, weighted_hedges=True), 64, 0.03)]
     for h, k, e in cases:
