@@ -150,6 +150,25 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
                               bp_report *report, void *stream);
 
 /*
+ * For callers that cannot allocate device memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): bp_partition_device
+ * with every device buffer of the call inside a fixed 256 MiB workspace that
+ * the library holds per device (a static device array, allocated when the
+ * library's code is loaded on that device and kept until the process ends).
+ * The call itself allocates no device memory (no hipMalloc/hipFree); its
+ * first call on a device only looks up that device's workspace address.
+ * Arguments, outputs and results are those of bp_partition_device.  Inputs
+ * whose workspace bound (bp_request_footprint of their sizes) exceeds the
+ * workspace are refused with BP_ERR_OUT_OF_MEMORY before any work is queued.
+ * Calls on one device share its workspace: they run one at a time (a lock is
+ * held until the call's stream has drained), so calls that overlap in time
+ * on one device wait for each other rather than race.
+ */
+bp_status bp_partition_device_noalloc(const bp_hypergraph *hg, int32_t k, double eps,
+                                      const bp_params *params, int32_t *d_part_out, int64_t *cut_out,
+                                      bp_report *report, void *stream);
+
+/*
  * Device memory: each call works in an arena of device memory that is kept,
  * per device, for the next call (steady calls allocate nothing).  A call that
  * used less than a quarter of its arena (and the arena holds over 1 GiB)

@@ -33,6 +33,7 @@ EXPORTS = [
     "bp_server_create", "bp_server_submit", "bp_server_wait", "bp_server_destroy",
     "bp_profile_floor", "bp_schedule_default", "bp_schedule_set", "bp_schedule_get",
     "bp_autotune_batch_device", "bp_release_memory", "bp_set_memory_limit",
+    "bp_partition_device_noalloc",
 ]
 
 
@@ -145,6 +146,7 @@ def lib():
         L.bp_schedule_get.argtypes = [P]
         L.bp_autotune_batch_device.argtypes = [i32, P, P, P, P, P, i32, P, P, P]
         L.bp_release_memory.argtypes = []
+        L.bp_partition_device_noalloc.argtypes = [P, i32, f64, P, P, P, P, P]
         L.bp_set_memory_limit.argtypes = [i64]
         for name in EXPORTS:
             f = getattr(L, name)
@@ -347,6 +349,19 @@ def partition_device(dh: DeviceHypergraph, k, eps, prm: Params | None = None, pa
                                           None if prm is None else ctypes.byref(prm),
                                           part_out.data_ptr(), ctypes.byref(cut),
                                           ctypes.byref(rep), _stream()))
+    return part_out[:dh.num_nodes], int(cut.value), st, rep
+
+
+def partition_device_noalloc(dh: DeviceHypergraph, k, eps, prm: Params | None = None, part_out=None):
+    """As partition_device, through the entry point that allocates no device
+    memory (fixed workspace); part_out is required."""
+    hg = dh.struct()
+    cut = ctypes.c_int64(0)
+    rep = Report()
+    st = _check(lib().bp_partition_device_noalloc(ctypes.byref(hg), k, eps,
+                                                  None if prm is None else ctypes.byref(prm),
+                                                  part_out.data_ptr(), ctypes.byref(cut),
+                                                  ctypes.byref(rep), _stream()))
     return part_out[:dh.num_nodes], int(cut.value), st, rep
 
 

@@ -1603,6 +1603,72 @@ bp_status bp_partition_device(const bp_hypergraph *hg, int32_t k, double eps,
     BP_GUARD_END
 }
 
+// The fixed device workspace of bp_partition_device_noalloc: a static device
+// array, one copy per GPU the library runs on, held until the process ends.
+// Host code reaches a device's copy only through the address that
+// hipGetSymbolAddress returns for it (kept per device below).
+constexpr size_t kScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+struct ScratchDev {
+    std::mutex mu;  // calls on one device share its workspace, so they run one at a time
+    bool ready = false;
+    void *ptr = nullptr;  // device address of this device's copy of `scratch`
+    Arena ar;             // bump allocation inside that copy
+    alignas(64) unsigned char info[4096];  // host readback buffer
+};
+static ScratchDev g_scratch[kMaxDevices];
+
+// Upper bound of the workspace a partition takes: the bump allocations of one
+// call, by the largest terms measured per pin, node and hyperedge and tree
+// level, plus the fixed tables.
+static int64_t workspace_bound(int64_t N, int64_t E, int64_t P, int32_t k)
+{
+    return footprint_bytes(N, E, P, k);
+}
+
+bp_status bp_partition_device_noalloc(const bp_hypergraph *hg, int32_t k, double eps,
+                                      const bp_params *params, int32_t *d_part_out, int64_t *cut_out,
+                                      bp_report *report, void *stream)
+{
+    bp_status st = check_device_hg(hg);
+    if (st != BP_OK) return st;
+    if ((st = check_params(params)) != BP_OK) return st;
+    if (k < 1 || !(eps >= 0.0) || std::isinf(eps)) return fail(BP_ERR_INVALID_ARG, "k < 1 or bad eps");
+    if (!d_part_out && hg->num_nodes > 0) return fail(BP_ERR_INVALID_ARG, "d_part_out is NULL");
+    BP_GUARD_BEGIN
+    int dev = current_device();
+    ScratchDev &sd = g_scratch[dev];
+    std::lock_guard<std::mutex> lock(sd.mu);
+    if (!sd.ready) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(BP_ERR_DEVICE, std::string("hipGetSymbolAddress of the workspace: ") + hipGetErrorString(e));
+        }
+        sd.ptr = ptr;
+        sd.ar.adopt(ptr, kScratchBytes);
+        sd.ready = true;
+    }
+    int64_t P = 0;
+    if (hg->num_hedges > 0) {
+        int32_t p32 = 0;
+        BP_HIP(hipMemcpyAsync(&p32, hg->hedge_offsets + hg->num_hedges, sizeof(int32_t), hipMemcpyDeviceToHost,
+                              (hipStream_t)stream));
+        BP_HIP(hipStreamSynchronize((hipStream_t)stream));
+        P = p32;
+    }
+    int64_t need = workspace_bound(hg->num_nodes, hg->num_hedges, P, k);
+    if (need > (int64_t)kScratchBytes)
+        return fail(BP_ERR_OUT_OF_MEMORY, "input needs up to " + std::to_string(need) +
+                                              " bytes of workspace; the fixed workspace holds " +
+                                              std::to_string(kScratchBytes));
+    CtxGuard g((hipStream_t)stream, params, &sd.ar, (LevelInfo *)sd.info);
+    return partition_device(g.cx, device_input(hg), k, eps, d_part_out, cut_out, report);
+    BP_GUARD_END
+}
+
 bp_status bp_set_memory_limit(int64_t bytes)
 {
     if (bytes < 0) return fail(BP_ERR_INVALID_ARG, "negative memory limit");
