@@ -114,9 +114,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_scatter(const GraphDesc *d, in
 
 // ---- per-graph cut and part weights ------------------------------------------------
 
-// Per-graph connectivity-1 cut.  SMALL: hyperedges of degree <= 8 over
-// contiguous chunks, per-graph sums in LDS (one atomic per graph and chunk);
-// WAVE / BLOCK: the listed hyperedges, one atomic per cut hyperedge.
+// Per-graph connectivity-1 cut.  Every schedule takes contiguous chunks (of
+// hyperedges for SMALL, of the degree lists for WAVE / BLOCK, whose entries
+// ascend roughly with the hyperedge id and so with the graph) and sums per
+// graph in LDS, one global atomic per graph and chunk; a graph more than
+// kAggLists past the chunk's first one adds globally.
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t *list,
                                                     const int32_t *off, const int32_t *pins,
@@ -128,41 +130,46 @@ __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t
     __shared__ int32_t lds[16];
     __shared__ unsigned long long acc[kAggLists];
     bool mask64 = kmax <= 64;
+    int64_t lo, hi;
     if (S == SMALL) {
-        int64_t lo, hi;
         reduce_chunk(count, gridDim.x, blockIdx.x, lo, hi);
-        if (lo >= hi) return;
-        int32_t s0 = hseg[lo], ns = hseg[hi - 1] + 1 - s0;
-        bool local = ns <= kAggLists;
-        for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) acc[i] = 0;
-        __syncthreads();
+    } else {  // list chunks as even as the grid allows (a wavefront or workgroup per entry)
+        int64_t per = ceil_div((int64_t)count, (int64_t)gridDim.x);
+        lo = min((int64_t)blockIdx.x * per, (int64_t)count);
+        hi = min(lo + per, (int64_t)count);
+    }
+    if (lo >= hi) return;
+    int32_t s0 = hseg[S == SMALL ? (int32_t)lo : list[lo]];
+    for (int i = threadIdx.x; i < kAggLists; i += blockDim.x) acc[i] = 0;
+    __syncthreads();
+    auto add = [&](int32_t e, int32_t lam) {
+        unsigned long long c = (unsigned long long)hw[e] * (lam - 1);
+        int32_t q = hseg[e] - s0;
+        if (q >= 0 && q < kAggLists) atomicAdd(&acc[q], c);
+        else atomicAdd(&cut[hseg[e]], c);
+    };
+    if (S == SMALL) {
         for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
             if (off[e + 1] - off[e] > kSmallMax) continue;
             int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
-            if (lam <= 1) continue;
-            unsigned long long c = (unsigned long long)hw[e] * (lam - 1);
-            if (local) atomicAdd(&acc[hseg[e] - s0], c);
-            else atomicAdd(&cut[hseg[e]], c);
+            if (lam > 1) add((int32_t)e, lam);
         }
-        __syncthreads();
-        if (local)
-            for (int i = threadIdx.x; i < ns; i += blockDim.x)
-                if (acc[i]) atomicAdd(&cut[s0 + i], acc[i]);
     } else if (S == WAVE) {
-        int64_t wpb = blockDim.x >> 6;
-        for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += (int64_t)gridDim.x * wpb) {
+        for (int64_t i = lo + (threadIdx.x >> 6); i < hi; i += blockDim.x >> 6) {
             int32_t e = list[i];
             int32_t lam = hedge_lambda<WAVE>(e, threadIdx.x & 63, 64, off, pins, part, mask64, orl, lds);
-            if ((threadIdx.x & 63) == 0 && lam > 1)
-                atomicAdd(&cut[hseg[e]], (unsigned long long)hw[e] * (lam - 1));
+            if ((threadIdx.x & 63) == 0 && lam > 1) add(e, lam);
         }
     } else {
-        for (int64_t i = blockIdx.x; i < count; i += gridDim.x) {
+        for (int64_t i = lo; i < hi; i++) {
             int32_t e = list[i];
             int32_t lam = hedge_lambda<BLOCK>(e, threadIdx.x, blockDim.x, off, pins, part, mask64, orl, lds);
-            if (threadIdx.x == 0 && lam > 1) atomicAdd(&cut[hseg[e]], (unsigned long long)hw[e] * (lam - 1));
+            if (threadIdx.x == 0 && lam > 1) add(e, lam);
         }
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAggLists; i += blockDim.x)
+        if (acc[i]) atomicAdd(&cut[s0 + i], acc[i]);
 }
 
 // part weights of every graph: pw[kbase[g] + part] (LDS histogram when a

@@ -967,17 +967,19 @@ static CutResult compute_cut(Ctx &cx, Level &L, int32_t N_nodes, const int32_t *
     LaunchCtx &lc = cx.lc;
     check_lists(L);
     unsigned long long *acc = ar.get<unsigned long long>(4);
-    fill(lc, acc, 4, 0ull);
     int mask64 = k <= 64 ? 1 : 0;
-    launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut<SMALL>, reduce_grid(L.E), kBlock, 0, L.E,
+    const int64_t gs = cut_grid<SMALL>(L.E), gw = cut_grid<WAVE>(L.nmid), gb = cut_grid<BLOCK>(L.nbig);
+    unsigned long long *partial = ar.get<unsigned long long>(gs + gw + gb);
+    launch(lc, "cut_small", 8.0 * L.E + 8.0 * L.P, k_cut<SMALL>, gs, kBlock, 0, L.E,
            (const int32_t *)nullptr, (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
-           d_part, mask64, acc);
-    launch(lc, "cut_wave", 0.0, k_cut<WAVE>, std::min<int64_t>(sched_grid<WAVE>(L.nmid), kReduceBlocks), kBlock,
-           0, L.nmid, (const int32_t *)L.lmid, (const int32_t *)L.off, (const int32_t *)L.pins,
-           (const int32_t *)L.hw, d_part, mask64, acc);
-    launch(lc, "cut_block", 0.0, k_cut<BLOCK>, std::min<int64_t>(L.nbig, kReduceBlocks), kBlock, 0, L.nbig,
-           (const int32_t *)L.lbig, (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
-           d_part, mask64, acc);
+           d_part, mask64, partial);
+    launch(lc, "cut_wave", 0.0, k_cut<WAVE>, gw, kBlock, 0, L.nmid, (const int32_t *)L.lmid,
+           (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw, d_part, mask64, partial + gs);
+    launch(lc, "cut_block", 0.0, k_cut<BLOCK>, gb, kBlock, 0, L.nbig, (const int32_t *)L.lbig,
+           (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw, d_part, mask64,
+           partial + gs + gw);
+    launch(lc, "cut", 0.0, k_sum_u64, 1, 1024, 0, (int32_t)(gs + gw + gb), (const unsigned long long *)partial,
+           acc);
     unsigned long long *pw = ar.get<unsigned long long>(k);
     fill(lc, pw, k, 0ull);
     launch(lc, "part_weights", 8.0 * N_nodes, k_part_weights,
@@ -1273,11 +1275,10 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
         launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, reduce_grid(root.E), kBlock,
                0, root.E, (const int32_t *)nullptr, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
-        launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, std::min<int64_t>(sched_grid<WAVE>(root.nmid), kReduceBlocks),
-               kBlock, 0, root.nmid,
+        launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, cut_grid<WAVE>(root.nmid), kBlock, 0, root.nmid,
                (const int32_t *)root.lmid, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
-        launch(lc, "cut_block", 0.0, k_cut_seg<BLOCK>, std::min<int64_t>(root.nbig, kReduceBlocks), kBlock, 0,
+        launch(lc, "cut_block", 0.0, k_cut_seg<BLOCK>, std::min<int64_t>(root.nbig, kCutBlocks), kBlock, 0,
                root.nbig,
                (const int32_t *)root.lbig, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);

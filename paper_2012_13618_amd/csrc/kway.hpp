@@ -372,11 +372,24 @@ __device__ __forceinline__ int32_t hedge_lambda(int32_t e, int lane, int stride,
 
 // Connectivity-1 cut, summed over the hyperedges of one schedule (SMALL: all
 // hyperedges of degree <= 8, one per thread; WAVE / BLOCK: the listed ones).
-// Strided over at most kReduceBlocks workgroups, one atomic each.
+// Each workgroup writes its sum to partial[blockIdx.x] (no same-address
+// atomics); k_sum_u64 adds the partial sums up.  SMALL: contiguous chunks of
+// hyperedges over at most kReduceBlocks workgroups; WAVE / BLOCK: the listed
+// hyperedges, as many workgroups as keep every wavefront on about one
+// hyperedge (at most kCutBlocks).
+constexpr int64_t kCutBlocks = 16384;
+
+template <int S> inline int64_t cut_grid(int64_t count)
+{
+    if (S == SMALL) return reduce_grid(count);
+    int64_t g = S == WAVE ? sched_grid<WAVE>(count) : count;
+    return g < kCutBlocks ? g : kCutBlocks;
+}
+
 template <int S>
 __global__ __launch_bounds__(kBlock) void k_cut(int32_t count, const int32_t *list, const int32_t *off,
                                                 const int32_t *pins, const int32_t *hw, const int32_t *part,
-                                                int mask64, unsigned long long *cut)
+                                                int mask64, unsigned long long *partial)
 {
     __shared__ unsigned long long orl[16];
     __shared__ int32_t lds[16];
@@ -404,7 +417,23 @@ __global__ __launch_bounds__(kBlock) void k_cut(int32_t count, const int32_t *li
         }
     }
     contrib = block_sum(contrib, lds64);
-    if (threadIdx.x == 0 && contrib) atomicAdd(cut, (unsigned long long)contrib);
+    if (threadIdx.x == 0) partial[blockIdx.x] = (unsigned long long)contrib;
+}
+
+// out[0] = the sum of a[0, n): one workgroup.
+__global__ void k_sum_u64(int32_t n, const unsigned long long *a, unsigned long long *out)
+{
+    __shared__ unsigned long long lds[16];
+    unsigned long long t = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) t += a[i];
+    t = wave_sum(t);
+    if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long r = 0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); i++) r += lds[i];
+        *out = r;
+    }
 }
 
 // Part weights: registers for k <= 8, an LDS histogram for k <= 4096, else
