@@ -283,22 +283,37 @@ SERVE_DESC = ("served stream: open-loop Poisson arrivals; request pins log-unifo
               "netlist-shaped, N = pins / (1.2 x 4.54), E = 1.2 N, k uniform in {2, 4, 16}, eps = 0.05")
 
 
-def bench_serve(args):
-    """Open-loop Poisson stream into the server; value = pins/s delivered over
-    the makespan; latency percentiles are submission to results on the host."""
-    import threading
+def _pct(x, q):
     import numpy as np
+    return round(float(np.percentile(np.asarray(x), q)), 3)
+
+
+def serve_fifo_plain(reqs, arrivals):
+    """The same stream solved one request at a time, in arrival order, on the
+    plain path (host arrays in, host arrays out, as a request is): latency =
+    completion - scheduled arrival."""
     import paper_2012_13618_amd as bp
-    from paper_2012_13618_amd import inputs as I
-    R = args.requests
-    reqs = [I.serve_request(r) for r in range(R)]
-    arrivals = I.poisson_arrivals(R, args.rate)
-    pins = sum(h.num_pins for h in reqs)
-    log(f"workload serve: {R} requests, {pins} pins, rate {args.rate}/s")
-    with bp.Server(hbm_budget_bytes=args.budget_gib << 30, max_slots=args.slots) as srv:
-        for h in reqs[:args.warmup]:  # warm the worker's device memory
-            srv.wait(srv.submit(h))
-        tickets = [None] * R
+    lat = []
+    t0 = time.perf_counter()
+    for h, a in zip(reqs, arrivals):
+        d = t0 + a - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        bp.partition(h.num_nodes, h.offsets, h.pins, h.meta["k"], h.meta["eps"])
+        lat.append(1000.0 * (time.perf_counter() - t0 - a))
+    return lat, time.perf_counter() - t0
+
+
+def serve_served(reqs, arrivals, args):
+    """The stream into the server: a feeder submits at the arrival times,
+    the requests are collected as they complete; latency = completion -
+    scheduled arrival."""
+    import threading
+    import paper_2012_13618_amd as bp
+    R = len(reqs)
+    with bp.Server(hbm_budget_bytes=args.budget_gib << 30, max_slots=args.slots, workers=args.workers,
+                   max_run_pins=args.run_pins) as srv:
+        tickets, subs = [None] * R, [0.0] * R
         t0 = time.perf_counter()
 
         def feeder():
@@ -306,6 +321,7 @@ def bench_serve(args):
                 d = t0 + arrivals[i] - time.perf_counter()
                 if d > 0:
                     time.sleep(d)
+                subs[i] = time.perf_counter()
                 tickets[i] = srv.submit(h)
 
         th = threading.Thread(target=feeder)
@@ -313,23 +329,75 @@ def bench_serve(args):
         stats = []
         for i in range(R):
             while tickets[i] is None:
-                time.sleep(0.0005)
+                time.sleep(0.0002)
             stats.append(srv.wait(tickets[i])[3])
         th.join()
         el = time.perf_counter() - t0
-    lat = np.array([s.latency_ms for s in stats])
-    bsz = np.array([s.batch_size for s in stats])
-    value = pins / el
-    p50, p99 = float(np.percentile(lat, 50)), float(np.percentile(lat, 99))
-    log(f"makespan {el:.3f} s  {value / 1e6:.1f} Mpins/s  latency p50 {p50:.2f} ms p99 {p99:.2f} ms "
-        f"mean batch {bsz.mean():.2f} max {bsz.max()}")
-    line = {"metric": METRIC, "value": value, "unit": "pins/s", "n_gpus": 1, "steps": R,
-            "warmup": args.warmup, "ms_per_step": el * 1000.0 / R, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
-            "config": {"workload": SERVE_DESC, "requests": R, "pins": pins, "rate_per_s": args.rate,
-                       "parallelism": "1 GPU", "budget_gib": args.budget_gib, "max_slots": args.slots},
-            "latency_ms": {"p50": round(p50, 3), "p99": round(p99, 3), "max": round(float(lat.max()), 3)},
-            "mean_batch": round(float(bsz.mean()), 3), "roofline": None, "cpu_baseline": None}
+    lat = [1000.0 * (subs[i] - t0 - arrivals[i]) + stats[i].latency_ms for i in range(R)]
+    return lat, el, [s.batch_size for s in stats]
+
+
+def bench_serve(args):
+    """Open-loop Poisson streams at fractions of the plain path's capacity
+    (1 / mean plain solve time), into the server and, for comparison, solved
+    FIFO one at a time on the plain path; pins/s over the makespan and
+    latency percentiles for both."""
+    import numpy as np
+    import paper_2012_13618_amd as bp
+    from paper_2012_13618_amd import inputs as I
+    R = args.requests
+    reqs = [I.serve_request(r) for r in range(R)]
+    pins = sum(h.num_pins for h in reqs)
+    log(f"workload serve: {R} requests, {pins} pins")
+    for h in reqs[:args.warmup]:
+        bp.partition(h.num_nodes, h.offsets, h.pins, h.meta["k"], h.meta["eps"])
+    t = []
+    for h in reqs:
+        t0 = time.perf_counter()
+        bp.partition(h.num_nodes, h.offsets, h.pins, h.meta["k"], h.meta["eps"])
+        t.append(time.perf_counter() - t0)
+    capacity = 1.0 / float(np.mean(t))
+    log(f"plain solve: mean {1000 * np.mean(t):.2f} ms -> capacity {capacity:.1f} requests/s, "
+        f"{pins / sum(t) / 1e6:.1f} Mpins/s back to back")
+    loads = []
+    for frac in [float(x) for x in args.loads.split(",")]:
+        rate = frac * capacity
+        arrivals = I.poisson_arrivals(R, rate)
+        lat_s, el_s, bsz = serve_served(reqs, arrivals, args)
+        lat_f, el_f = serve_fifo_plain(reqs, arrivals)
+        row = {"load": frac, "rate_per_s": round(rate, 3),
+               "served": {"pins_per_s": pins / el_s, "p50_ms": _pct(lat_s, 50), "p99_ms": _pct(lat_s, 99),
+                          "mean_batch": round(float(np.mean(bsz)), 3)},
+               "fifo_plain": {"pins_per_s": pins / el_f, "p50_ms": _pct(lat_f, 50), "p99_ms": _pct(lat_f, 99)}}
+        log(f"load {frac}: served {pins / el_s / 1e6:.1f} Mpins/s p50 {row['served']['p50_ms']} ms "
+            f"p99 {row['served']['p99_ms']} ms | FIFO plain {pins / el_f / 1e6:.1f} Mpins/s "
+            f"p50 {row['fifo_plain']['p50_ms']} ms p99 {row['fifo_plain']['p99_ms']} ms")
+        loads.append(row)
+    top = loads[-1]
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        n_or, p_or, t0 = 0, 0, time.perf_counter()
+        for h in reqs:
+            oracle.partition_hg(h)
+            n_or += 1
+            p_or += h.num_pins
+            if time.perf_counter() - t0 >= args.cpu_budget:
+                break
+        el = time.perf_counter() - t0
+        hc = host_cpu()
+        cpu = {"value": p_or / el, "unit": "pins/s", "cores": 1, "kind": "oracle",
+               "sample": f"the first {n_or} requests of the stream solved one after another, {el:.1f} s",
+               "host_nproc": hc["nproc"], "host_cpu": hc["model"]}
+    line = {"metric": METRIC, "value": top["served"]["pins_per_s"], "unit": "pins/s", "n_gpus": 1,
+            "steps": R, "warmup": args.warmup, "ms_per_step": 1000.0 / top["rate_per_s"],
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic",
+            "config": {"workload": SERVE_DESC, "requests": R, "pins": pins, "parallelism": "1 GPU",
+                       "plain_capacity_per_s": round(capacity, 3), "budget_gib": args.budget_gib,
+                       "max_slots": args.slots, "workers": args.workers, "max_run_pins": args.run_pins},
+            "latency_ms": {"p50": top["served"]["p50_ms"], "p99": top["served"]["p99_ms"]},
+            "loads": loads, "roofline": None, "cpu_baseline": cpu}
     print(json.dumps(line), flush=True)
 
 
@@ -349,10 +417,13 @@ def main():
                     help="batch: pick the launch schedule with the autotuner first")
     ap.add_argument("--no-compare", action="store_true",
                     help="batch: skip timing the graphs one call at a time")
-    ap.add_argument("--requests", type=int, default=256, help="serve: requests in the stream")
-    ap.add_argument("--rate", type=float, default=100.0, help="serve: mean arrivals per second")
+    ap.add_argument("--requests", type=int, default=200, help="serve: requests in the stream")
+    ap.add_argument("--loads", default="0.5,0.7,0.9,1.5",
+                    help="serve: arrival rates as fractions of the plain path's capacity")
     ap.add_argument("--budget-gib", type=int, default=128, help="serve: admission budget")
     ap.add_argument("--slots", type=int, default=256, help="serve: most requests per run")
+    ap.add_argument("--workers", type=int, default=4, help="serve: runs in flight at once")
+    ap.add_argument("--run-pins", type=int, default=4 << 20, help="serve: input pins per run")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "

@@ -110,6 +110,12 @@ typedef struct {
     int32_t host_syncs;        /* device-to-host waits the call needed        */
     int32_t kernel_launches;   /* kernels launched by the call                */
     int64_t device_bytes;      /* device memory the call held at its end      */
+    int32_t levels[64];        /* per bisection-tree level t < 64: the most
+                                  coarsening steps of its bisections (the whole
+                                  run's for the batched form)                 */
+    double imbalance;          /* max_part_weight * k / W - 1 (0 when W = 0)   */
+    int32_t graph_replays;     /* rounds replayed from captured graphs          */
+    int32_t reserved;
 } bp_report;
 
 /* Fills *p with the defaults listed above. */
@@ -241,6 +247,9 @@ typedef struct {
                                       262144) select each balance round's nodes in chunks of
                                       16384 nodes, one workgroup each, merged per segment;
                                       0: never (default 262144) */
+    int32_t graph_rounds;          /* 1: a level's later rounds (from the seventh) are replayed
+                                      from three captured hipGraphs instead of launched one
+                                      kernel at a time; 0: launched (default 0) */
 } bp_schedule;
 
 /* Fills *s with the defaults above. */
@@ -266,26 +275,33 @@ bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const
 
 /* ---- served form ----------------------------------------------------------
  *
- * A server owns a worker thread on one device.  Requests are submitted one
- * at a time from any thread; the worker drains the queue in runs, each run
- * partitioning every request it admitted as one batch (see
- * bp_partition_batch).  Admission: a run takes queued requests in arrival
- * order while the sum of their footprint estimates (bp_request_footprint)
- * stays within hbm_budget_bytes and at most max_slots requests; requests
- * that arrive during a run join the next one.  A request whose own estimate
- * exceeds the budget is refused at submission with BP_ERR_REJECTED.  Every
- * result equals bp_partition of that request alone.
+ * A server owns `workers` worker threads on one device, each with its own
+ * stream and device memory, so that runs overlap on the device.  Requests
+ * are submitted one at a time from any thread.  A free worker starts a run
+ * at once with the oldest queued requests: the first one, then the next ones
+ * while the run stays under max_run_pins input pins and max_slots requests,
+ * and while the footprint estimates (bp_request_footprint) of all runs in
+ * flight stay within hbm_budget_bytes; when the oldest request does not fit
+ * beside the runs in flight, the worker waits for one to end.  A request
+ * that arrives while others run therefore starts as soon as a worker and
+ * memory are free, and a small request does not wait behind a large one
+ * already running.  Each run partitions its requests as one batch (see
+ * bp_partition_batch).  A request whose own estimate exceeds the budget is
+ * refused at submission with BP_ERR_REJECTED.  Every result equals
+ * bp_partition of that request alone.
  */
 typedef struct bp_server bp_server;
 
 typedef struct {
-    int64_t hbm_budget_bytes;   /* > 0: device bytes the requests of one run may need together */
+    int64_t hbm_budget_bytes;   /* > 0: device bytes the runs in flight may need together        */
     int32_t max_slots;          /* >= 1: most requests per run                                  */
     int32_t max_batch_delay_us; /* >= 0: after the oldest queued request arrived, wait up to this
                                    long for more before starting a run (0: start at once)      */
-    int32_t device;             /* HIP device id the worker uses                                */
-    int32_t reserved;           /* set to 0                                                     */
+    int32_t device;             /* HIP device id the workers use                               */
+    int32_t workers;            /* 1..16: runs in flight at once (default 4)                   */
     bp_params params;           /* partitioner parameters for every request                    */
+    int64_t max_run_pins;       /* >= 1: a run takes further requests only while its input pins
+                                   stay at or below this (default 4194304)                     */
 } bp_server_config;
 
 typedef struct {
@@ -298,7 +314,8 @@ typedef struct {
     double latency_ms;          /* submission to results on the host                 */
 } bp_req_stats;
 
-/* Defaults: 64 GiB budget, 256 slots, no batching delay, device 0, default params. */
+/* Defaults: 64 GiB budget, 256 slots, no batching delay, device 0, 4 workers,
+ * 4194304 pins per run, default params. */
 void bp_server_default_config(bp_server_config *cfg);
 
 /* Footprint estimate (device bytes) of one partition of a hypergraph with

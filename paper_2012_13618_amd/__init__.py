@@ -60,16 +60,20 @@ class Report(ctypes.Structure):
                 ("tree_levels", ctypes.c_int32), ("bisections", ctypes.c_int32),
                 ("coarsen_levels", ctypes.c_int32), ("pins_coarsened", ctypes.c_int64),
                 ("pins_refined", ctypes.c_int64), ("host_syncs", ctypes.c_int32),
-                ("kernel_launches", ctypes.c_int32), ("device_bytes", ctypes.c_int64)]
+                ("kernel_launches", ctypes.c_int32), ("device_bytes", ctypes.c_int64),
+                ("levels", ctypes.c_int32 * 64), ("imbalance", ctypes.c_double),
+                ("graph_replays", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("levels", "reserved")}
+        d["levels"] = list(self.levels)[:max(self.tree_levels, 0)]
+        return d
 
 
 class ServerConfig(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("max_slots", ctypes.c_int32),
                 ("max_batch_delay_us", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("params", Params)]
+                ("workers", ctypes.c_int32), ("params", Params), ("max_run_pins", ctypes.c_int64)]
 
 
 class ReqStats(ctypes.Structure):
@@ -86,7 +90,8 @@ class ReqStats(ctypes.Structure):
 class Schedule(ctypes.Structure):
     _fields_ = [("incremental_min_pins", ctypes.c_int32), ("seg_select_max_nodes", ctypes.c_int32),
                 ("round_chunk_max", ctypes.c_int32), ("fused_pick_lists", ctypes.c_int32),
-                ("fuse_max_pins", ctypes.c_int32), ("chunk_select_max_nodes", ctypes.c_int32)]
+                ("fuse_max_pins", ctypes.c_int32), ("chunk_select_max_nodes", ctypes.c_int32),
+                ("graph_rounds", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -241,9 +246,13 @@ class Server:
     """The served form: submit host hypergraphs, wait for their partitions."""
 
     def __init__(self, hbm_budget_bytes=None, max_slots=None, max_batch_delay_us=None, device=0,
-                 prm: Params | None = None):
+                 prm: Params | None = None, workers=None, max_run_pins=None):
         cfg = ServerConfig()
         lib().bp_server_default_config(ctypes.byref(cfg))
+        if workers is not None:
+            cfg.workers = int(workers)
+        if max_run_pins is not None:
+            cfg.max_run_pins = int(max_run_pins)
         if hbm_budget_bytes is not None:
             cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         if max_slots is not None:

@@ -472,6 +472,75 @@ static bool trace_on()
     return on == 1;
 }
 
+// Graph replay of a level's rounds: every round after the first issues the
+// same launches, which depend on the round index only through ri % 3 (its
+// counter slot) and ri > 0, so three graphs, captured once from rounds
+// 3, 4 and 5 on a private stream, replay every later round of the level on
+// the call's stream.
+struct RoundGraphs {
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};
+    int32_t launches[3] = {0, 0, 0};
+    bool failed = false;
+    ~RoundGraphs()
+    {
+        for (int k = 0; k < 3; k++) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+        }
+    }
+};
+
+// A non-blocking stream of the current device for capturing (one per thread
+// and device, kept for the process).
+static hipStream_t capture_stream()
+{
+    thread_local hipStream_t st[kCaptureDevices] = {};
+    int dev = 0;
+    BP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kCaptureDevices) return nullptr;
+    if (!st[dev]) BP_HIP(hipStreamCreateWithFlags(&st[dev], hipStreamNonBlocking));
+    return st[dev];
+}
+
+// Issues round ri through the level's graphs (capturing the slot's graph on
+// first use); false when capture is not possible, the round then to be
+// launched directly.
+template <typename Round>
+static bool replay_round(LaunchCtx &lc, Segs &sg, RoundGraphs &rg, int64_t ri, Round &round)
+{
+    int k = (int)(ri % 3);
+    if (rg.failed) return false;
+    if (!rg.exec[k]) {
+        hipStream_t cs = capture_stream();
+        if (!cs || hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            (void)hipGetLastError();
+            rg.failed = true;
+            return false;
+        }
+        hipStream_t own = lc.stream;
+        int32_t before = lc.launches;
+        lc.stream = cs;
+        try {
+            round((int32_t)(3 + k), sg.go + 4 + k);  // the same slot and ri > 0
+        } catch (...) {
+            lc.stream = own;
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(cs, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        lc.stream = own;
+        rg.launches[k] = lc.launches - before;
+        lc.launches = before;
+        BP_HIP(hipStreamEndCapture(cs, &rg.graph[k]));
+        BP_HIP(hipGraphInstantiate(&rg.exec[k], rg.graph[k], nullptr, nullptr, 0));
+    }
+    BP_HIP(hipGraphLaunch(rg.exec[k], lc.stream));
+    lc.launches += rg.launches[k];
+    return true;
+}
+
 // With estimate (balance rounds), go[3] holds the rounds the segments still
 // need as estimated by the last round: the next chunk is that long, and an
 // estimate of zero ends the loop.  round(ri, gc) issues round ri; gc is its
@@ -483,11 +552,15 @@ static int64_t chunked_rounds(Ctx &cx, Segs &sg, int64_t limit, bool estimate, R
     int64_t issued = 0;
     int chunk = estimate ? 1 : 2;
     std::vector<int64_t> first;  // serial of each round's first launch (profiling)
+    // graphs from round 6 on: a level that ends sooner never captures
+    const bool graphs = cx.sched.graph_rounds && !lc.prof && !cx.no_graphs;
+    RoundGraphs rg;
     lc.hold++;
     for (;;) {
         for (int i = 0; i < chunk; i++) {
             first.push_back(lc.serial);
-            round((int32_t)issued, sg.go + 4 + issued % 3);
+            if (graphs && issued >= 6 && replay_round(lc, sg, rg, issued, round)) cx.graph_replays++;
+            else round((int32_t)issued, sg.go + 4 + issued % 3);
             issued++;
         }
         BP_HIP(hipMemcpyAsync(cx.info_h, sg.go, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, lc.stream));
@@ -718,6 +791,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
         l++;
     }
     if (cx.first_levels < 0) cx.first_levels = l;
+    cx.tree_depth.push_back(l);
     int32_t Lmax = l;
 
     // per level: a bound on the gain span, for the number of selection passes
@@ -1026,6 +1100,16 @@ int64_t part_limit(int64_t W, int32_t k, double eps)
     return std::max(lim_f, lim_c);
 }
 
+// Report fields shared by every form: coarsening depth per tree level,
+// imbalance, graph replays.
+static void report_extras(const Ctx &cx, int64_t maxw, int64_t W, int32_t k, bp_report &r)
+{
+    for (int t = 0; t < 64; t++) r.levels[t] = t < (int)cx.tree_depth.size() ? cx.tree_depth[t] : 0;
+    r.imbalance = W > 0 ? (double)maxw * k / (double)W - 1.0 : 0.0;
+    r.graph_replays = cx.graph_replays;
+    r.reserved = 0;
+}
+
 bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int32_t *d_part,
                            int64_t *cut_out, bp_report *rep)
 {
@@ -1082,6 +1166,7 @@ bp_status partition_device(Ctx &cx, const Input &in, int32_t k, double eps, int3
         rep->host_syncs = lc.syncs;
         rep->kernel_launches = lc.launches;
         rep->device_bytes = (int64_t)cx.ar->used();
+        report_extras(cx, cr.maxw, W, k, *rep);
     }
     return balanced ? BP_OK : BP_WARN_IMBALANCED;
 }
@@ -1173,6 +1258,8 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
         r.cut = 0;
         r.maxw = W[i];
         r.limit = part_limit(W[i], x.k, x.eps);
+        r.W = W[i];
+        r.k = x.k;
         r.balanced = r.maxw <= r.limit;
     }
 
@@ -1297,6 +1384,8 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
             r.cut = (int64_t)accv[i];
             r.maxw = (int64_t)accv[S + i];
             r.limit = part_limit(W[i], x.k, x.eps);
+            r.W = W[i];
+            r.k = x.k;
             r.balanced = r.maxw <= r.limit;
         }
     }
@@ -1666,6 +1755,7 @@ bp_status bp_partition_device_noalloc(const bp_hypergraph *hg, int32_t k, double
                                               " bytes of workspace; the fixed workspace holds " +
                                               std::to_string(kScratchBytes));
     CtxGuard g((hipStream_t)stream, params, &sd.ar, (LevelInfo *)sd.info);
+    g.cx.no_graphs = true;  // instantiating a graph allocates
     return partition_device(g.cx, device_input(hg), k, eps, d_part_out, cut_out, report);
     BP_GUARD_END
 }
@@ -1704,6 +1794,7 @@ static void fill_batch_reports(const Ctx &cx, const std::vector<BatchOut> &res, 
         r.host_syncs = cx.lc.syncs;
         r.kernel_launches = cx.lc.launches;
         r.device_bytes = (int64_t)cx.ar->used();
+        report_extras(cx, res[g].maxw, res[g].W, res[g].k, r);
     }
 }
 
@@ -1809,6 +1900,7 @@ static Schedule to_schedule(const bp_schedule *s)
     r.fused_pick_lists = s->fused_pick_lists;
     r.fuse_max_pins = s->fuse_max_pins;
     r.chunk_select_max_nodes = s->chunk_select_max_nodes;
+    r.graph_rounds = s->graph_rounds;
     return r;
 }
 
@@ -1820,13 +1912,14 @@ static void from_schedule(const Schedule &r, bp_schedule *s)
     s->fused_pick_lists = r.fused_pick_lists;
     s->fuse_max_pins = r.fuse_max_pins;
     s->chunk_select_max_nodes = r.chunk_select_max_nodes;
+    s->graph_rounds = r.graph_rounds;
 }
 
 static bool schedule_ok(const bp_schedule *s)
 {
     return s && s->incremental_min_pins >= 0 && s->seg_select_max_nodes >= 0 && s->round_chunk_max >= 1 &&
            s->round_chunk_max <= 64 && s->fused_pick_lists >= 0 && s->fused_pick_lists <= 4096 &&
-           s->fuse_max_pins >= 0 && s->chunk_select_max_nodes >= 0;
+           s->fuse_max_pins >= 0 && s->chunk_select_max_nodes >= 0 && (s->graph_rounds == 0 || s->graph_rounds == 1);
 }
 
 void bp_schedule_default(bp_schedule *s)
@@ -1900,7 +1993,8 @@ bp_status bp_autotune_batch_device(int32_t n, const bp_hypergraph *graphs, const
         for (int32_t seg : {0, 4096, 16384, 32768})
             for (int32_t chunk : {16, 32})
                 cand.push_back(
-                    Schedule{inc, seg, chunk, base.fused_pick_lists, base.fuse_max_pins, base.chunk_select_max_nodes});
+                    Schedule{inc, seg, chunk, base.fused_pick_lists, base.fuse_max_pins, base.chunk_select_max_nodes,
+                             base.graph_rounds});
     double best_t = 1e300;
     Schedule best_s = base;
     for (const Schedule &sc : cand) {

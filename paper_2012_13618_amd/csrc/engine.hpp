@@ -23,7 +23,10 @@ struct Schedule {
     int32_t fused_pick_lists = 8;
     int32_t fuse_max_pins = 1 << 17;
     int32_t chunk_select_max_nodes = 1 << 18;
+    int32_t graph_rounds = 0;
 };
+
+constexpr int kCaptureDevices = 64;
 
 Schedule current_schedule();  // the process-wide schedule (a copy, taken under a lock)
 
@@ -37,6 +40,9 @@ struct Ctx {
     int64_t pins_coarsened = 0, pins_refined = 0;
     int32_t first_levels = -1;
     int32_t bisections = 0;
+    bool no_graphs = false;  // the call may not capture (the allocation-free entry point)
+    int32_t graph_replays = 0;
+    std::vector<int32_t> tree_depth;  // most coarsening steps of a bisection, per tree level
 
     LevelInfo &readback()
     {
@@ -270,8 +276,8 @@ struct BatchItem {
 };
 
 struct BatchOut {
-    int64_t cut = 0, maxw = 0, limit = 0;
-    int32_t balanced = 1;
+    int64_t cut = 0, maxw = 0, limit = 0, W = 0;
+    int32_t balanced = 1, k = 1;
 };
 
 std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,

@@ -1,12 +1,17 @@
-// Served form: requests arrive one by one, a single worker thread drains the
-// queue in runs, and every run partitions all the requests it admitted as
-// one batch (the batched form: one segment per request).  Admission is by
-// device-memory footprint: a run takes queued requests in arrival order
-// while their summed footprint estimate stays within the budget and the slot
-// count allows; a request whose own estimate is above the budget is refused
-// at submission.  Requests that arrive while a run is executing join the next
-// run, so the engine is never idle while work is queued.  Each result is the
-// partition the request gets alone.
+// Served form with continuous admission: requests arrive one by one and
+// several workers, each with its own stream and device memory, serve them in
+// runs that overlap on the device.  A free worker starts a run at once with
+// the oldest queued requests: the first one, then the following ones while
+// the run holds fewer than max_run_pins input pins (a large request runs
+// nearly alone, small ones go together), at most max_slots requests, and
+// while the footprint estimates of every run in flight stay within the
+// budget; otherwise it waits until a run in flight ends.  So a request that
+// arrives while others are on the device starts as soon as a worker and
+// memory are free, and a small request never waits behind a large one that
+// is already running.  A request whose own estimate is above the budget is
+// refused at submission.  Each result is the partition the request gets
+// alone (every run is the batched form, whose results equal the per-graph
+// ones).
 //
 // Included once, from the library's C ABI translation unit.
 #pragma once
@@ -60,14 +65,22 @@ struct Server {
     std::deque<std::shared_ptr<Request>> queue;
     std::unordered_map<uint64_t, std::shared_ptr<Request>> tickets;
     uint64_t next_ticket = 1;
-    int64_t queued_bytes = 0;
+    int64_t queued_bytes = 0, queued_pins = 0;
+    int64_t inflight_bytes = 0;  // footprint estimates of the runs on the device
     bool stop = false;
     int32_t waiters = 0;
-    std::thread worker;
+    std::vector<std::thread> workers;
 
+    // enough queued to start a run without waiting out the batching delay
     bool run_full() const
     {
-        return (int32_t)queue.size() >= cfg.max_slots || queued_bytes >= cfg.hbm_budget_bytes;
+        return (int32_t)queue.size() >= cfg.max_slots || queued_bytes >= cfg.hbm_budget_bytes ||
+               queued_pins >= cfg.max_run_pins;
+    }
+    // the oldest queued request fits beside the runs in flight
+    bool head_fits() const
+    {
+        return !queue.empty() && inflight_bytes + queue.front()->footprint <= cfg.hbm_budget_bytes;
     }
 };
 
@@ -120,30 +133,39 @@ inline void serve_loop(Server *s)
     hipStream_t stream = nullptr;
     LevelInfo *info_h = nullptr;
     Arena arena;
-    if (hipSetDevice(s->cfg.device) != hipSuccess || hipStreamCreate(&stream) != hipSuccess ||
+    if (hipSetDevice(s->cfg.device) != hipSuccess || hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess ||
         hipHostMalloc((void **)&info_h, 4096, hipHostMallocDefault) != hipSuccess) {
         init_error = std::string("server device setup failed: ") + hipGetErrorString(hipGetLastError());
     }
     for (;;) {
         std::vector<std::shared_ptr<Request>> run;
+        int64_t run_bytes = 0;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            s->cv_work.wait(lk, [&] { return s->stop || !s->queue.empty(); });
+            s->cv_work.wait(lk, [&] { return s->stop || s->head_fits(); });
             if (s->stop) break;
             if (s->cfg.max_batch_delay_us > 0 && !s->run_full()) {
                 auto until = s->queue.front()->t_submit + std::chrono::microseconds(s->cfg.max_batch_delay_us);
                 s->cv_work.wait_until(lk, until, [&] { return s->stop || s->run_full(); });
                 if (s->stop) break;
+                if (!s->head_fits()) continue;  // another worker took the requests meanwhile
             }
-            int64_t used = 0;
+            int64_t pins = 0;
             while (!s->queue.empty() && (int32_t)run.size() < s->cfg.max_slots &&
-                   used + s->queue.front()->footprint <= s->cfg.hbm_budget_bytes) {
-                used += s->queue.front()->footprint;
-                s->queued_bytes -= s->queue.front()->footprint;
-                run.push_back(s->queue.front());
+                   (run.empty() || pins + (int64_t)s->queue.front()->pins.size() <= s->cfg.max_run_pins) &&
+                   s->inflight_bytes + run_bytes + s->queue.front()->footprint <= s->cfg.hbm_budget_bytes) {
+                auto &r = s->queue.front();
+                run_bytes += r->footprint;
+                pins += (int64_t)r->pins.size();
+                s->queued_bytes -= r->footprint;
+                s->queued_pins -= (int64_t)r->pins.size();
+                run.push_back(r);
                 s->queue.pop_front();
             }
+            s->inflight_bytes += run_bytes;
         }
+        // more queued requests may fit beside this run on another worker
+        s->cv_work.notify_one();
         auto t0 = std::chrono::steady_clock::now();
         for (auto &r : run) r->t_start = t0;
         bp_status err = BP_OK;
@@ -168,6 +190,7 @@ inline void serve_loop(Server *s)
         auto t1 = std::chrono::steady_clock::now();
         {
             std::lock_guard<std::mutex> lk(s->mu);
+            s->inflight_bytes -= run_bytes;
             for (auto &r : run) {
                 if (err != BP_OK) {
                     r->status = err;
@@ -178,6 +201,7 @@ inline void serve_loop(Server *s)
             }
         }
         s->cv_done.notify_all();
+        s->cv_work.notify_all();  // memory freed: a waiting worker may start
     }
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -189,6 +213,7 @@ inline void serve_loop(Server *s)
         }
         s->queue.clear();
         s->queued_bytes = 0;
+        s->queued_pins = 0;
     }
     s->cv_done.notify_all();
     if (stream) (void)hipStreamSynchronize(stream);
@@ -212,8 +237,9 @@ void bp_server_default_config(bp_server_config *c)
     c->max_slots = 256;
     c->max_batch_delay_us = 0;
     c->device = 0;
-    c->reserved = 0;
+    c->workers = 4;
     bp_default_params(&c->params);
+    c->max_run_pins = int64_t(4) << 20;
 }
 
 bp_status bp_request_footprint(int32_t num_nodes, int32_t num_hedges, int64_t num_pins, int32_t k,
@@ -228,14 +254,15 @@ bp_status bp_request_footprint(int32_t num_nodes, int32_t num_hedges, int64_t nu
 bp_status bp_server_create(const bp_server_config *cfg, bp_server **out)
 {
     if (!cfg || !out) return fail(BP_ERR_INVALID_ARG, "NULL config or output");
-    if (cfg->hbm_budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_batch_delay_us < 0 || cfg->device < 0)
+    if (cfg->hbm_budget_bytes <= 0 || cfg->max_slots < 1 || cfg->max_batch_delay_us < 0 || cfg->device < 0 ||
+        cfg->workers < 1 || cfg->workers > 16 || cfg->max_run_pins < 1)
         return fail(BP_ERR_INVALID_ARG, "invalid server config");
     bp_status st = check_params(&cfg->params);
     if (st != BP_OK) return st;
     BP_GUARD_BEGIN
     bp_server *srv = new bp_server();
     srv->s.cfg = *cfg;
-    srv->s.worker = std::thread(bp::serve_loop, &srv->s);
+    for (int32_t w = 0; w < cfg->workers; w++) srv->s.workers.emplace_back(bp::serve_loop, &srv->s);
     *out = srv;
     return BP_OK;
     BP_GUARD_END
@@ -272,6 +299,7 @@ bp_status bp_server_submit(bp_server *srv, const bp_hypergraph *hg, int32_t k, d
         s.tickets[r->ticket] = r;
         s.queue.push_back(r);
         s.queued_bytes += fp;
+        s.queued_pins += P;
         *ticket = r->ticket;
     }
     s.cv_work.notify_one();
@@ -323,7 +351,8 @@ bp_status bp_server_destroy(bp_server *srv)
         s.stop = true;
     }
     s.cv_work.notify_all();
-    if (s.worker.joinable()) s.worker.join();
+    for (auto &w : s.workers)
+        if (w.joinable()) w.join();
     {
         std::unique_lock<std::mutex> lk(s.mu);
         s.cv_done.wait(lk, [&] { return s.waiters == 0; });

@@ -97,7 +97,7 @@ def test_schedule_defaults_and_validation():
     d = bp.schedule_default()
     assert d.as_dict() == {"incremental_min_pins": 1 << 18, "seg_select_max_nodes": 1 << 15,
                            "round_chunk_max": 32, "fused_pick_lists": 8, "fuse_max_pins": 1 << 17,
-                           "chunk_select_max_nodes": 1 << 18}
+                           "chunk_select_max_nodes": 1 << 18, "graph_rounds": 0}
     old = bp.schedule_get()
     try:
         s = bp.schedule_default()
@@ -106,7 +106,7 @@ def test_schedule_defaults_and_validation():
         assert bp.schedule_get().round_chunk_max == 8
         for field, bad in [("round_chunk_max", 0), ("round_chunk_max", 65), ("fused_pick_lists", -1),
                            ("incremental_min_pins", -5), ("seg_select_max_nodes", -1), ("fuse_max_pins", -1),
-                           ("chunk_select_max_nodes", -1)]:
+                           ("chunk_select_max_nodes", -1), ("graph_rounds", 2)]:
             s = bp.schedule_default()
             setattr(s, field, bad)
             _expect(-1, lambda: bp.schedule_set(s))

@@ -80,11 +80,12 @@ def test_server_from_threads_with_tight_budget(bp):
 
 
 def test_queued_requests_share_a_run(bp):
-    """A large request followed at once by small ones: requests queued
-    together are served by shared runs, each with its own plain result."""
+    """One worker: a large request followed at once by small ones; the small
+    ones queued behind it are served together by one run, each with its own
+    plain result."""
     big = I.serve_request(3)
     small = [I.random_small(500, 600, 2, 10, 200 + i) for i in range(6)]
-    with bp.Server(hbm_budget_bytes=64 << 30) as s:
+    with bp.Server(hbm_budget_bytes=64 << 30, workers=1, max_run_pins=big.num_pins) as s:
         tb = s.submit(big, 16, 0.05)
         ts = [s.submit(h, 2, 0.05) for h in small]
         pb, cb, _, sb = s.wait(tb)
@@ -94,8 +95,61 @@ def test_queued_requests_share_a_run(bp):
     alone = bp.partition(big.num_nodes, big.offsets, big.pins, 16, 0.05)
     assert np.array_equal(pb, alone[0]) and cb == alone[1]
     for h, g in zip(small, got):
-        ref = oracle.partition(h.num_nodes, h.offsets, h.pins, 2, 0.05)
+        ref = bp.partition(h.num_nodes, h.offsets, h.pins, 2, 0.05)
         assert np.array_equal(g[0], ref[0]) and g[1] == ref[1]
+
+
+def test_small_request_does_not_wait_for_a_running_large_one(bp):
+    """Continuous admission: a small request submitted while a large k=16
+    request is on the device starts on another worker and completes first,
+    with its plain result; the large one keeps its plain result too."""
+    import time
+    big = I.vlsi(seed=31, n=400_000)      # 2.2M pins, k = 16: tens of milliseconds
+    small = I.random_small(2000, 2400, 2, 8, 301)
+    done = {}
+    with bp.Server(hbm_budget_bytes=64 << 30, workers=4) as s:
+        tb = s.submit(big, 16, 0.05)
+        time.sleep(0.005)                 # the large run is under way
+        ts = s.submit(small, 2, 0.05)
+
+        def waiter(name, t):
+            r = s.wait(t)
+            done[name] = (time.perf_counter(), r)
+
+        th = [threading.Thread(target=waiter, args=a) for a in (("big", tb), ("small", ts))]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=300)
+    say("small latency", done["small"][1][3].latency_ms, "ms; big latency", done["big"][1][3].latency_ms, "ms")
+    assert done["small"][0] < done["big"][0]
+    assert done["small"][1][3].batch_size == 1 and done["big"][1][3].batch_size == 1
+    ref = bp.partition(small.num_nodes, small.offsets, small.pins, 2, 0.05)
+    assert np.array_equal(done["small"][1][0], ref[0]) and done["small"][1][1] == ref[1]
+    alone = bp.partition(big.num_nodes, big.offsets, big.pins, 16, 0.05)
+    assert np.array_equal(done["big"][1][0], alone[0]) and done["big"][1][1] == alone[1]
+
+
+def test_overlapping_runs_keep_every_result(bp):
+    """Many requests of mixed sizes from several threads, four workers whose
+    runs overlap on the device: every result equals the plain path."""
+    reqs = [I.serve_request(r) for r in range(16)]
+    results = {}
+    with bp.Server(hbm_budget_bytes=64 << 30, workers=4, max_run_pins=1 << 20) as s:
+        def client(idx):
+            for i in idx:
+                h = reqs[i]
+                results[i] = s.wait(s.submit(h, h.meta["k"], h.meta["eps"]))
+        th = [threading.Thread(target=client, args=(list(range(j, 16, 4)),)) for j in range(4)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join(timeout=300)
+    assert len(results) == 16
+    for i, h in enumerate(reqs):
+        part, cut, st, stats = results[i]
+        alone = bp.partition(h.num_nodes, h.offsets, h.pins, h.meta["k"], h.meta["eps"])
+        assert np.array_equal(part, alone[0]) and cut == alone[1] and st == alone[2], i
 
 
 def test_footprint_estimate_bounds_device_memory(bp):

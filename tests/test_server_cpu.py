@@ -22,6 +22,9 @@ def test_bad_config_is_rejected():
     assert _status(lambda: bp.Server(max_slots=0)) == -1
     assert _status(lambda: bp.Server(max_batch_delay_us=-1)) == -1
     assert _status(lambda: bp.Server(prm=bp.params(policy=7))) == -1
+    assert _status(lambda: bp.Server(workers=0)) == -1
+    assert _status(lambda: bp.Server(workers=17)) == -1
+    assert _status(lambda: bp.Server(max_run_pins=0)) == -1
 
 
 def test_footprint_estimate_grows_with_size_and_k():
