@@ -24,7 +24,7 @@ sys.path.insert(0, ROOT)
 METRIC = "pins/sec full k-way partition (coarsen+refine) vs HBM roofline; p99 latency served"
 HBM_PEAK_GBS = 8000.0
 WORKLOAD_TAG = {"vlsi": "vlsi1m_k2", "colnet": "colnet4m_k8", "colnet2": "colnet4m_pl2_k8",
-                "tiny": "tiny1k_k2"}
+                "tiny": "tiny1k_k2", "random10m": "random10m_k2", "random15m": "random15m_k2"}
 
 # Kernel families by phase of the multilevel scheme: coarsening (Algorithms 1
 # and 2 with the incidence each level needs) and uncoarsening (Algorithms 3-5:
@@ -71,6 +71,14 @@ def make_workload(name):
         h = I.column_net(dmin=2)
         desc = ("column-net sparse matrix: N=E=4,000,000, nnz per column power-law alpha=2.1 on "
                 "[2,5000] (38.0M pins), node weight = row nnz, k=8 (3 tree levels), eps=0.03")
+    elif name == "random10m":
+        h = I.random_10m()
+        desc = ("random hypergraph shaped like the paper's Random-10M: N=E=10,000,000, degree uniform "
+                "in [2,21] (115M pins), unit weights, k=2, eps=0.1")
+    elif name == "random15m":
+        h = I.random_15m()
+        desc = ("random hypergraph shaped like the paper's Random-15M: N=15,000,000, E=17,000,000, "
+                "degree uniform in [2,31] (281M pins), unit weights, k=2, eps=0.1")
     elif name == "tiny":
         h = I.tiny()
         desc = "random: N=1,000 unit nodes, E=2,000 hyperedges of degree U{2..8}"
@@ -107,6 +115,13 @@ def cpu_sample(name, h):
     same generator at half the rows and columns (same degree law, weights, k
     and eps)."""
     from paper_2012_13618_amd import inputs as I
+    if name in ("random10m", "random15m"):
+        big = name == "random15m"
+        n, e = (1_000_000, 1_133_333) if big else (1_000_000, 1_000_000)
+        s = I.uniform_hypergraph(n, e, 2, 31 if big else 21, 6 + big, name="sample")
+        s.meta.update(k=2, eps=0.1)
+        return s, (f"one full k=2 partition of the same generator at a fifteenth / tenth of the size "
+                   f"(N={n}, E={e}, {s.num_pins} pins)")
     if name == "colnet2":
         s = I.column_net(n=2_000_000, dmin=2)
         return s, (f"one full k={s.meta['k']} partition of the same column-net generator at half size "
@@ -401,12 +416,107 @@ def bench_serve(args):
     print(json.dumps(line), flush=True)
 
 
+def bench_ksweep(args):
+    """Time against k (Section 4.4 and its figure of time over k): the same
+    graph partitioned into k = 2, 4, 8, 16, 32 parts.  Every tree level of the
+    recursive bisection is one pass over all of its subgraphs, so the time
+    should grow with the tree depth ceil(log2 k) rather than with k."""
+    import numpy as np
+    import torch
+    import paper_2012_13618_amd as bp
+    h, desc = make_workload(args.workload_of)
+    dh = bp.DeviceHypergraph.from_host(h)
+    part = torch.empty(h.num_nodes, dtype=torch.int32, device="cuda")
+    eps = h.meta["eps"]
+    rows = []
+    for k in (2, 4, 8, 16, 32):
+        for _ in range(args.warmup):
+            bp.partition_device(dh, k, eps, part_out=part)
+        ts = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, cut, st, rep = bp.partition_device(dh, k, eps, part_out=part)
+            torch.cuda.synchronize()
+            ts.append(1000.0 * (time.perf_counter() - t0))
+        ms = float(np.median(ts))
+        rows.append({"k": k, "tree_levels": rep.tree_levels, "ms": round(ms, 3), "cut": cut,
+                     "pins_per_s": h.num_pins / ms * 1000.0, "balanced": rep.balanced,
+                     "launches": rep.kernel_launches})
+        log(f"k={k:3d} depth {rep.tree_levels}: {ms:8.3f} ms  cut {cut}  balanced {rep.balanced}")
+    d = np.array([r["tree_levels"] for r in rows], float)
+    t = np.array([r["ms"] for r in rows])
+    A = np.vstack([np.ones_like(d), d]).T
+    coef, *_ = np.linalg.lstsq(A, t, rcond=None)
+    pred = A @ coef
+    r2 = 1.0 - float(np.sum((t - pred) ** 2) / np.sum((t - t.mean()) ** 2))
+    log(f"time ~ {coef[0]:.3f} + {coef[1]:.3f} * ceil(log2 k) ms, R^2 {r2:.4f}")
+    own = next(r for r in rows if r["k"] == h.meta["k"]) if h.meta["k"] in (2, 4, 8, 16, 32) else rows[0]
+    line = {"metric": METRIC, "value": own["pins_per_s"], "unit": "pins/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": own["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": desc, "study": "time against k", "pins": h.num_pins},
+            "sweep": rows, "fit_ms": {"intercept": round(float(coef[0]), 3), "per_tree_level": round(float(coef[1]), 3),
+                                      "r2": round(r2, 4)},
+            "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
+def bench_design(args):
+    """The design space of Section 4.3 (its table of best settings and the
+    cut-time trade-off figure): matching policy x coarsening level limit x
+    refinement iterations on one graph; every setting's time and cut, and the
+    Pareto frontier (no other setting both faster and of smaller cut)."""
+    import numpy as np
+    import torch
+    import paper_2012_13618_amd as bp
+    h, desc = make_workload(args.workload_of)
+    dh = bp.DeviceHypergraph.from_host(h)
+    part = torch.empty(h.num_nodes, dtype=torch.int32, device="cuda")
+    k, eps = h.meta["k"], h.meta["eps"]
+    names = {bp.LDH: "LDH", bp.HDH: "HDH", bp.RAND: "RAND", bp.LWD: "LWD", bp.HWD: "HWD"}
+    rows = []
+    for pol in (bp.LDH, bp.HDH, bp.RAND):
+        for lv in (5, 10, 15, 25):
+            for it in (0, 1, 2, 4):
+                prm = bp.params(policy=pol, max_levels=lv, refine_iters=it)
+                bp.partition_device(dh, k, eps, prm=prm, part_out=part)
+                ts = []
+                for _ in range(args.steps):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    _, cut, st, rep = bp.partition_device(dh, k, eps, prm=prm, part_out=part)
+                    torch.cuda.synchronize()
+                    ts.append(1000.0 * (time.perf_counter() - t0))
+                rows.append({"policy": names[pol], "max_levels": lv, "refine_iters": it,
+                             "ms": round(float(np.median(ts)), 3), "cut": cut, "balanced": rep.balanced})
+                log(f"{names[pol]:4s} levels {lv:2d} iters {it}: {rows[-1]['ms']:8.3f} ms cut {cut}")
+    front = []
+    for r in sorted(rows, key=lambda r: (r["ms"], r["cut"])):
+        if r["balanced"] and (not front or r["cut"] < front[-1]["cut"]):
+            front.append(r)
+    log("Pareto frontier: " + "; ".join(f"{r['policy']}/{r['max_levels']}/{r['refine_iters']} "
+                                        f"{r['ms']} ms cut {r['cut']}" for r in front))
+    default = next(r for r in rows if r["policy"] == "LDH" and r["max_levels"] == 25 and r["refine_iters"] == 2)
+    line = {"metric": METRIC, "value": h.num_pins / default["ms"] * 1000.0, "unit": "pins/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": 1, "ms_per_step": default["ms"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32", "data": "synthetic",
+            "config": {"workload": desc, "study": "policy x level limit x refinement iterations",
+                       "pins": h.num_pins, "k": k, "eps": eps},
+            "sweep": rows, "pareto": front, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="colnet")
+    ap.add_argument("--workload", default="colnet",
+                    help="colnet (default), colnet2, vlsi, tiny, random10m, random15m, batch, serve, "
+                         "ksweep, design")
+    ap.add_argument("--of", dest="workload_of", default="vlsi",
+                    help="ksweep / design: the graph they run on (vlsi, colnet, ...)")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -448,6 +558,10 @@ def main():
         return bench_batch(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "ksweep":
+        return bench_ksweep(args)
+    if args.workload == "design":
+        return bench_design(args)
     h, desc = make_workload(args.workload)
     k, eps = h.meta["k"], h.meta["eps"]
     log(f"workload {args.workload}: N={h.num_nodes} E={h.num_hedges} P={h.num_pins} k={k} eps={eps}")

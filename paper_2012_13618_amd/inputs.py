@@ -198,6 +198,25 @@ def column_net(seed: int = 3, n: int = 4_000_000, dmin: int = 1) -> Hypergraph:
     return h
 
 
+def random_10m(seed: int = 6) -> Hypergraph:
+    """The shape of the paper's Random-10M input (Table 2): N = E = 10M,
+    about 115M pins; degrees uniform in [2, 21] (mean 11.5), pins uniform
+    without replacement, unit weights; k=2, eps=0.1 (the 55:45 balance of the
+    paper's runs).  The paper does not give its generator."""
+    h = uniform_hypergraph(10_000_000, 10_000_000, 2, 21, seed, name="random-10m")
+    h.meta.update(k=2, eps=0.1)
+    return h
+
+
+def random_15m(seed: int = 7) -> Hypergraph:
+    """The shape of the paper's Random-15M input (Table 2): N = 15M, E = 17M,
+    about 281M pins; degrees uniform in [2, 31] (mean 16.5), pins uniform
+    without replacement, unit weights; k=2, eps=0.1."""
+    h = uniform_hypergraph(15_000_000, 17_000_000, 2, 31, seed, name="random-15m")
+    h.meta.update(k=2, eps=0.1)
+    return h
+
+
 def batch_member(i: int, seed: int = 4) -> Hypergraph:
     """Member i of the 256-graph batch: N log-uniform in [1e3, 2e5], E=1.2N,
     netlist structure; k=2 for even i, 4 for odd i; eps=0.05."""
