@@ -507,6 +507,94 @@ def bench_design(args):
     print(json.dumps(line), flush=True)
 
 
+# ---- rocprofv3 summaries (the files under profiles/) ------------------------
+
+KERNEL_SOURCES = ["paper_2012_13618_amd/csrc/" + f for f in (
+    "balance.hpp", "batch.hpp", "coarsen.hpp", "common.hpp", "engine.hip", "engine.hpp", "kway.hpp",
+    "level.hpp", "refine.hpp", "scan.hpp", "sched.hpp", "server.hpp", "transpose.hpp", "uncoarsen.hpp")]
+
+
+def _read_csv(path):
+    import csv
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def _short(name):
+    """A kernel's name without its parameter list and namespace."""
+    n = name[5:] if name.startswith("void ") else name
+    depth, out = 0, ""
+    for ch in n:
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out += ch
+    return out.replace("bp::", "")
+
+
+def summarize_stats(args):
+    """Markdown summary of a rocprofv3 --stats kernel table."""
+    rows = _read_csv(args.summarize_stats)
+    tot = sum(float(r["TotalDurationNs"]) for r in rows)
+    per = args.summary_steps
+    lines = [f"# Kernel time, {args.summary_title}", "",
+             "Command (from the repository root; rocprofv3 run after `cd /tmp && export TMPDIR=/tmp`, "
+             "paths given absolute):", "", "    " + args.summary_command, "",
+             f"rocprofv3 --stats summary; the program ran {per} partition steps (warmup, timed and one "
+             f"hipEvent-profiled step), so per-step figures are totals / {per}.", "",
+             f"Total kernel time: {tot / 1e6:.3f} ms  ({tot / 1e6 / per:.3f} ms per step)", "",
+             "| kernel | calls | calls/step | total ms | ms/step | avg us | min us | max us | % |",
+             "|---|---|---|---|---|---|---|---|---|"]
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    for r in rows[:args.summary_top]:
+        t = float(r["TotalDurationNs"])
+        c = int(r["Calls"])
+        lines.append(f"| {_short(r['Name'])} | {c} | {c / per:.1f} | {t / 1e6:.3f} | {t / 1e6 / per:.3f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {100 * t / tot:.2f} |")
+    with open(args.summary_out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    log("wrote", args.summary_out)
+
+
+def summarize_traffic(args):
+    """HBM bytes per dispatch of one kernel family from two rocprofv3 --pmc
+    runs (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what
+    the counter reads for the 1 GiB device copy that --calibrate-copy runs."""
+    fetch_csv, write_csv = args.summarize_traffic
+    out = {"kernel": args.summary_kernel}
+
+    def one(path, counter):
+        rows = [r for r in _read_csv(path) if r["Counter_Name"] == counter]
+        ks = [float(r["Counter_Value"]) for r in rows if args.summary_kernel in r["Kernel_Name"]]
+        cp = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        return ks, cp
+
+    fk, fc = one(fetch_csv, "FETCH_SIZE")
+    wk, wc = one(write_csv, "WRITE_SIZE")
+    gib = 1 << 30
+    ff = gib / (max(fc) * 1024.0)
+    wf = gib / (max(wc) * 1024.0)
+    fpd, wpd = sum(fk) / len(fk), sum(wk) / len(wk)
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    out.update({"dispatches": len(fk), "fetch_kib_per_dispatch_raw": fpd, "write_kib_per_dispatch_raw": wpd,
+                "copy_calibration": {"bytes": gib, "fetch_kib_raw": max(fc), "write_kib_raw": max(wc),
+                                     "fetch_factor": ff, "write_factor": wf},
+                "hbm_bytes_per_launch": fpd * 1024.0 * ff + wpd * 1024.0 * wf,
+                "fetch_bytes_per_launch": fpd * 1024.0 * ff, "write_bytes_per_launch": wpd * 1024.0 * wf,
+                "kernel_sources": KERNEL_SOURCES, "sources_sha256": h.hexdigest(),
+                "commands": args.summary_command.split(" ;; ")})
+    with open(args.summary_out, "w") as fh:
+        json.dump(out, fh, indent=1)
+        fh.write("\n")
+    log("wrote", args.summary_out, f"{out['hbm_bytes_per_launch']:.0f} B per launch over {len(fk)} dispatches")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -534,7 +622,21 @@ def main():
     ap.add_argument("--slots", type=int, default=256, help="serve: most requests per run")
     ap.add_argument("--workers", type=int, default=4, help="serve: runs in flight at once")
     ap.add_argument("--run-pins", type=int, default=4 << 20, help="serve: input pins per run")
+    ap.add_argument("--summarize-stats", metavar="CSV", help="write a profiles/ summary of a rocprofv3 "
+                    "kernel_stats.csv instead of benchmarking")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write a profiles/ HBM traffic summary from two rocprofv3 --pmc runs")
+    ap.add_argument("--summary-kernel", default="k_seg_select")
+    ap.add_argument("--summary-title", default="")
+    ap.add_argument("--summary-command", default="")
+    ap.add_argument("--summary-steps", type=int, default=1)
+    ap.add_argument("--summary-top", type=int, default=30)
+    ap.add_argument("--summary-out", default="")
     args = ap.parse_args()
+    if args.summarize_stats:
+        return summarize_stats(args)
+    if args.summarize_traffic:
+        return summarize_traffic(args)
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(see the sharding plan in DESIGN.md); run with --gpus 1", file=sys.stderr)

@@ -230,7 +230,8 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
  * the time.  Process-wide; a call uses the schedule current when it starts.
  */
 typedef struct {
-    int32_t incremental_min_pins;  /* levels with at least this many pins update balance-round gains
+    int32_t incremental_min_pins;  /* levels with at least this many pins plus nodes (a full gain
+                                      pass reads both) update balance-round gains
                                       from the moves; INT32_MAX: always recompute (default 262144) */
     int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes select
                                       and move in one workgroup per segment (capped at 16384 for

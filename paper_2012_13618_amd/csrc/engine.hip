@@ -440,11 +440,11 @@ static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, co
         BalFinish bf{};
         bf.side = L.side;
         if (L.maxseg_nodes <= seg_select_max<0, kSegThreadsSmall>())
-            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
+            launch(cx.lc, "seg_select", 6.0 * L.N, k_seg_select<0, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                    L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
                    bf, go, (uint8_t *)nullptr, ChunkArgs{});
         else
-            launch(cx.lc, "seg_select", 10.0 * L.N, k_seg_select<0, kSegThreads>, L.S, kSegThreads, 0, L.S,
+            launch(cx.lc, "seg_select", 6.0 * L.N, k_seg_select<0, kSegThreads>, L.S, kSegThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
                    bf, go, (uint8_t *)nullptr, ChunkArgs{});
         return;
@@ -643,7 +643,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // the gains from the hyperedges of the nodes the previous round moved
     // incremental gains pay off once a full recomputation is long against
     // the three short launches they take
-    bool incr = L.P >= cx.sched.incremental_min_pins && !fuse_all(cx, L);
+    bool incr = (int64_t)L.P + L.N >= cx.sched.incremental_min_pins && !fuse_all(cx, L);
     Arena &ar = *cx.ar;
     MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
     uint32_t *bits = nullptr;
@@ -719,25 +719,23 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         }
         if (seg) {
             if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsSmall>())
-                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
+                launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                        L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
                        (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
             else if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsBal>())
-                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreadsBal>, L.S, kSegThreadsBal, 0, L.S,
+                launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreadsBal>, L.S, kSegThreadsBal, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
                        (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
             else
-                launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kSegThreads>, L.S, kSegThreads, 0, L.S,
+                launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreads>, L.S, kSegThreads, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
                        (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
             return;
         }
         if (chunk) {
-            launch(lc, "seg_select", 10.0 * L.N, k_seg_select<1, kChunkThreads, true>, nct, kChunkThreads, 0, L.S,
+            launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kChunkThreads, true>, nct, kChunkThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf,
                    gc, ml.moved, ca);
-            launch(lc, "balance", 0.0, k_bal_merge, L.S, 1024, 0, L.S, (const int32_t *)L.nbase,
-                   (const int32_t *)sg.m, ca, bf, gc);
             return;
         }
         run_select(cx, L, sg, gain, gc, sg.cand_stride);

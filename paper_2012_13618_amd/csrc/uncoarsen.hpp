@@ -967,6 +967,96 @@ template <int TH> __device__ __forceinline__ void clear_bytes(uint8_t *p, int32_
     if (t < n - t0) p[t0 + t] = 0;
 }
 
+// The merge of a balancing segment's chunk lists (1024 threads of one
+// workgroup, the last of the segment's chunks): each node of the chunks'
+// ascending lists is ranked among all of them (its index in its
+// own list plus, by binary search, the smaller keys of every other list); the
+// first min(total, m) in order are the segment's chosen nodes.  Then the
+// balance prefix (Algorithm 5) over them, with their weights staged in LDS by
+// the ranking threads: one scan, as the chosen nodes fit the workgroup.
+__device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, const int32_t *m, ChunkArgs ca,
+                                              BalFinish bf)
+{
+    static_assert(kChunkKeys <= 1024, "the chosen nodes fit the workgroup");
+    __shared__ uint64_t a[kChunkMax * kChunkKeys];
+    __shared__ uint64_t out[kChunkKeys];
+    __shared__ int64_t wts[kChunkKeys];
+    __shared__ int64_t lds64[16];
+    __shared__ int32_t cnt[kChunkMax], p1s, fits;
+    __shared__ int64_t movedw;
+    int32_t n = nbase[s + 1] - nbase[s];
+    int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
+    const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
+    // every slot of the segment's lists (past a list's count: unused), with the counts
+    const uint64_t *src = ca.cand + (int64_t)s * kChunkMax * kChunkKeys;
+    for (int32_t f = tid; f < nslot; f += 1024) a[f] = src[f];
+    if (tid < kChunkMax) cnt[tid] = tid < ng ? ca.ccnt[s * kChunkMax + tid] : 0;
+    if (tid == 0) movedw = 0;
+    __syncthreads();
+    int32_t tot = 0;
+    for (int q = 0; q < ng; q++) tot += cnt[q];
+    int32_t take = min(tot, m[s]);
+    for (int32_t f = tid; f < nslot; f += 1024) {
+        int q = f / kChunkKeys;
+        int32_t i = f % kChunkKeys;
+        if (i >= cnt[q]) continue;
+        uint64_t x = a[f];
+        int32_t rank = i;
+        for (int o = 0; o < ng && rank < take; o++) {
+            if (o == q) continue;
+            const uint64_t *b = a + o * kChunkKeys;
+            int32_t lo = 0, hi = cnt[o];
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (b[mid] < x) lo = mid + 1;
+                else hi = mid;
+            }
+            rank += lo;
+        }
+        if (rank < take) {
+            out[rank] = x;
+            wts[rank] = bf.nw[(uint32_t)(x & 0xffffffffu)];
+        }
+    }
+    if (tid == 0) {
+        p1s = take;
+        fits = 0;
+    }
+    __syncthreads();
+    // the shortest prefix reaching the excess, cut to what fits the room
+    // (weights are non-negative: prefix weights ascend)
+    int h = (bf.mode[s] & kList1) ? 1 : 0;
+    int64_t nd = bf.need[s], rm = bf.room[s];
+    int64_t w = tid < take ? wts[tid] : 0, wt;
+    int64_t incl = block_excl_scan(w, lds64, &wt) + w;
+    if (tid < take && incl >= nd) atomicMin(&p1s, tid + 1);
+    if (tid < take && incl <= rm) atomicAdd(&fits, 1);
+    __syncthreads();
+    int32_t p = min(p1s, fits);
+    if (tid < p) bf.side[(uint32_t)(out[tid] & 0xffffffffu)] = (uint8_t)(1 - h);
+    if (p > 0 && tid == p - 1) movedw = incl;
+    if (bf.ml.cnode) log_moves(p, out, bf.ml, lds64);
+    __syncthreads();
+    if (tid == 0) {
+        int64_t moved = movedw;
+        if (p == 0) {
+            bf.stuck[s] = 1;
+            bf.done[s] = 1;
+        } else {
+            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
+            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
+            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            bf.bal_moved[2 * s] = mw;
+            bf.bal_moved[2 * s + 1] = mr;
+            int64_t rest = nd - moved;
+            if (rest > 0) {
+                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
+                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
+            }
+        }
+    }
+}
+
 // One workgroup per segment of at most seg_select_max<KIND, TH>() nodes: each list's
 // r-th key by the same 12-bit radix select as the multi-workgroup passes,
 // with the segment's gains in registers and the histogram in LDS, then the
@@ -1216,6 +1306,20 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         uint64_t *dst = ca.cand + ((int64_t)s * kChunkMax + gi) * kChunkKeys;
         for (int32_t i = threadIdx.x; i < cnt; i += TH) dst[i] = sorted[i];
         if (threadIdx.x == 0) ca.ccnt[s * kChunkMax + gi] = cnt;
+        // the segment's last chunk to finish (ticket) merges the lists
+        __shared__ int32_t last;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int32_t nch = (sv.nbase[s + 1] - sv.nbase[s] + kChunkNodes - 1) / kChunkNodes;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            last = atomicAdd(&st.tick[s], 1) == nch - 1;
+            if (last) {
+                st.tick[s] = 0;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        __syncthreads();
+        if (last) bal_merge_seg(s, sv.nbase, sv.m, ca, bf);
         return;
     }
     if (threadIdx.x < 64) bal_take_prefix_wave(s, sorted, cnt, bf);
@@ -1244,100 +1348,6 @@ __global__ __launch_bounds__(1024) void k_chunk_table(int32_t S, const int32_t *
         __syncthreads();
     }
     if (threadIdx.x == 0) count[0] = carry;
-}
-
-// One workgroup per balancing segment of the chunked selection: each node of
-// the chunks' ascending lists is ranked among all of them (its index in its
-// own list plus, by binary search, the smaller keys of every other list); the
-// first min(total, m) in order are the segment's chosen nodes.  Then the
-// balance prefix (Algorithm 5) over them, with their weights staged in LDS by
-// the ranking threads: one scan, as the chosen nodes fit the workgroup.
-__global__ __launch_bounds__(1024) void k_bal_merge(int32_t S, const int32_t *nbase, const int32_t *m,
-                                                    ChunkArgs ca, BalFinish bf, const int32_t *go)
-{
-    static_assert(kChunkKeys <= 1024, "the chosen nodes fit the workgroup");
-    __shared__ uint64_t a[kChunkMax * kChunkKeys];
-    __shared__ uint64_t out[kChunkKeys];
-    __shared__ int64_t wts[kChunkKeys];
-    __shared__ int64_t lds64[16];
-    __shared__ int32_t cnt[kChunkMax], p1s, fits;
-    __shared__ int64_t movedw;
-    // the round's flag, the mode and the bounds loaded together (s < S)
-    const int32_t gv = go ? *go : 1;
-    int32_t s = blockIdx.x;
-    uint8_t md = bf.mode[s];
-    int32_t n = nbase[s + 1] - nbase[s];
-    if (gv == 0 || !md) return;
-    int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
-    const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
-    // every slot of the segment's lists (past a list's count: unused), with the counts
-    const uint64_t *src = ca.cand + (int64_t)s * kChunkMax * kChunkKeys;
-    for (int32_t f = tid; f < nslot; f += 1024) a[f] = src[f];
-    if (tid < kChunkMax) cnt[tid] = tid < ng ? ca.ccnt[s * kChunkMax + tid] : 0;
-    if (tid == 0) movedw = 0;
-    __syncthreads();
-    int32_t tot = 0;
-    for (int q = 0; q < ng; q++) tot += cnt[q];
-    int32_t take = min(tot, m[s]);
-    for (int32_t f = tid; f < nslot; f += 1024) {
-        int q = f / kChunkKeys;
-        int32_t i = f % kChunkKeys;
-        if (i >= cnt[q]) continue;
-        uint64_t x = a[f];
-        int32_t rank = i;
-        for (int o = 0; o < ng && rank < take; o++) {
-            if (o == q) continue;
-            const uint64_t *b = a + o * kChunkKeys;
-            int32_t lo = 0, hi = cnt[o];
-            while (lo < hi) {
-                int32_t mid = (lo + hi) >> 1;
-                if (b[mid] < x) lo = mid + 1;
-                else hi = mid;
-            }
-            rank += lo;
-        }
-        if (rank < take) {
-            out[rank] = x;
-            wts[rank] = bf.nw[(uint32_t)(x & 0xffffffffu)];
-        }
-    }
-    if (tid == 0) {
-        p1s = take;
-        fits = 0;
-    }
-    __syncthreads();
-    // the shortest prefix reaching the excess, cut to what fits the room
-    // (weights are non-negative: prefix weights ascend)
-    int h = (bf.mode[s] & kList1) ? 1 : 0;
-    int64_t nd = bf.need[s], rm = bf.room[s];
-    int64_t w = tid < take ? wts[tid] : 0, wt;
-    int64_t incl = block_excl_scan(w, lds64, &wt) + w;
-    if (tid < take && incl >= nd) atomicMin(&p1s, tid + 1);
-    if (tid < take && incl <= rm) atomicAdd(&fits, 1);
-    __syncthreads();
-    int32_t p = min(p1s, fits);
-    if (tid < p) bf.side[(uint32_t)(out[tid] & 0xffffffffu)] = (uint8_t)(1 - h);
-    if (p > 0 && tid == p - 1) movedw = incl;
-    if (bf.ml.cnode) log_moves(p, out, bf.ml, lds64);
-    __syncthreads();
-    if (tid == 0) {
-        int64_t moved = movedw;
-        if (p == 0) {
-            bf.stuck[s] = 1;
-            bf.done[s] = 1;
-        } else {
-            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
-            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
-            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
-            bf.bal_moved[2 * s] = mw;
-            bf.bal_moved[2 * s + 1] = mr;
-            int64_t rest = nd - moved;
-            if (rest > 0) {
-                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
-                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
-            }
-        }
-    }
 }
 
 // ---- moves ---------------------------------------------------------------------------------
