@@ -336,19 +336,20 @@ void run_gains(Ctx &cx, Level &L, Segs &sg, int32_t *gain, bool stats, const int
     cx.pins_refined += L.P;
     int64_t hv = std::max<int64_t>(ceil_div(L.E, kBlock) + ceil_div(L.nmid, kBlock / 64) + L.nbig,
                                    ceil_div(L.nbig_bound, kBlock));
-    double hb = 8.0 * L.E + 4.0 * L.E + 4.0 * L.P + 1.0 * L.P + 8.0 * L.E;
+    double cb = L.cc_pk ? 4.0 : 8.0;  // bytes of one contribution pair
+    double hb = 8.0 * L.E + 4.0 * L.E + 4.0 * L.P + 1.0 * L.P + cb * L.E;
     launch(lc, "gain_hedges", hb, k_gain_hedges, hv, kBlock, 0, L.E, (const int32_t *)L.lmid, L.nmid,
            (const int32_t *)L.lbig, L.nbig, (const int32_t *)L.off, (const int32_t *)L.pins,
            (const int32_t *)L.hw, (const int32_t *)L.hseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, L.cc, go, (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gain,
+           (const uint8_t *)L.side, (void *)L.cc, L.cc_pk, go, (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gain,
            L.big_done);
     int32_t nw = (int32_t)std::min<int64_t>(ceil_div(L.nmid_bound, kBlock / 64), kReduceBlocks);
     int64_t nv = reduce_grid(L.N) + nw + L.nchunk_bound;
-    double nb = 8.0 * L.N + 4.0 * L.P + 8.0 * L.P + 1.0 * L.N + 4.0 * L.N;
+    double nb = 8.0 * L.N + 4.0 * L.P + cb * L.P + 1.0 * L.N + 4.0 * L.N;
     launch(lc, "gain_nodes", nb, k_gain_nodes, nv, kBlock, 0, L.N, (const int32_t *)L.lnmid,
            (const int32_t *)L.lnbig, (const int32_t *)L.ncount, (const int32_t *)L.noff,
            (const int32_t *)L.inc, (const int32_t *)L.nseg, (const uint8_t *)sg.gmask,
-           (const uint8_t *)L.side, (const int2 *)L.cc, gain, (const uint8_t *)sg.mode,
+           (const uint8_t *)L.side, (const void *)L.cc, L.cc_pk, gain, (const uint8_t *)sg.mode,
            stats ? sg.st.tot : nullptr, sg.st.gmax, sg.st.gmin, go, (const int32_t *)L.chunk_node,
            (const int32_t *)L.chunk_beg, (const int32_t *)L.chunk_big, (const int32_t *)L.big_chunks,
            L.big_done, L.S, nw);
@@ -709,7 +710,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
                    (const int32_t *)L.noff, (const int32_t *)L.inc, bits);
             launch(lc, "gain_update", 0.0, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
-                   (const uint8_t *)L.side, (const uint8_t *)ml.moved, L.cc, gain, (const int32_t *)L.bigslot,
+                   (const uint8_t *)L.side, (const uint8_t *)ml.moved, (void *)L.cc, L.cc_pk, gain, (const int32_t *)L.bigslot,
                    (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count, ubytes);
             if (!seg && !chunk)
                 launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
@@ -822,6 +823,7 @@ void bisect_all(Ctx &cx, Level &L0, Segs &sg, int32_t active0)
             int bits = 0;
             while (bits < 32 && ((unsigned __int128)1 << bits) <= span) bits++;
             lv[j].span_bits = bits;
+            lv[j].cc_pk = hb[2 * j + 1] < 32768;
         }
     }
 

@@ -45,6 +45,7 @@ struct Level {
     // w(e) over v's hyperedges <= 2 (max degree)(max hyperedge weight)
     int32_t span_bits = 32;
     int2 *cc = nullptr;         // [E] per-hyperedge gain contributions (scratch)
+    int32_t cc_pk = 0;          // contributions packed as two int16 (every w(e) < 2^15)
 };
 
 // Sizes and counters read back once per level.

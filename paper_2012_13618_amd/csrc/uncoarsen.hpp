@@ -33,13 +33,31 @@ constexpr int kSelNodes = 1024;           // nodes per workgroup in histogram pa
 
 __device__ __forceinline__ int bitlen_u32(uint32_t x) { return x ? 32 - __clz((int)x) : 0; }
 
+// Per-hyperedge gain contributions (what a pin on side 0 / side 1 gains from
+// the hyperedge: +w, -w or 0).  When every hyperedge weight of the level is
+// below 2^15 (pk) the pair is stored as two 16-bit halves of one word, which
+// halves the bytes of the node pass's random gathers; else as an int2.
+__device__ __forceinline__ int2 cc_get(const void *cc, int pk, int32_t e)
+{
+    if (pk) {
+        uint32_t v = ((const uint32_t *)cc)[e];
+        return make_int2((int32_t)(int16_t)(v & 0xffffu), (int32_t)(int16_t)(v >> 16));
+    }
+    return ((const int2 *)cc)[e];
+}
+__device__ __forceinline__ void cc_put(void *cc, int pk, int32_t e, int2 c)
+{
+    if (pk) ((uint32_t *)cc)[e] = (uint32_t)(uint16_t)(int16_t)c.x | ((uint32_t)(uint16_t)(int16_t)c.y << 16);
+    else ((int2 *)cc)[e] = c;
+}
+
 // ---- gains -------------------------------------------------------------------------
 
 template <int S>
 __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int stride, const int32_t *off,
                                                   const int32_t *pins, const int32_t *hw,
                                                   const int32_t *hseg, const uint8_t *gmask,
-                                                  const uint8_t *side, int2 *cc, int32_t *lds)
+                                                  const uint8_t *side, void *cc, int pk, int32_t *lds)
 {
     int32_t b = off[e], d = off[e + 1] - b;
     if (S == SMALL && d > kSmallMax) return;
@@ -65,7 +83,7 @@ __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int strid
         int2 c;
         c.x = n0 == 1 ? w : (n0 == d ? -w : 0);
         c.y = n1 == 1 ? w : (n1 == d ? -w : 0);
-        cc[e] = c;
+        cc_put(cc, pk, e, c);
     }
 }
 
@@ -74,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
                                                         const int32_t *off, const int32_t *pins,
                                                         const int32_t *hw, const int32_t *hseg,
                                                         const uint8_t *gmask, const uint8_t *side,
-                                                        int2 *cc, const int32_t *go,
+                                                        void *cc, int pk, const int32_t *go,
                                                         const int32_t *lnbig, const int32_t *ncount,
                                                         int32_t *gain, int32_t *big_done)
 {
@@ -90,14 +108,14 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
     int64_t vb = blockIdx.x;
     if (vb < ns) {
         int64_t e = xcd_block(vb, ns) * kBlock + threadIdx.x;
-        if (e < E) hedge_contrib_one<SMALL>((int32_t)e, 0, 1, off, pins, hw, hseg, gmask, side, cc, lds);
+        if (e < E) hedge_contrib_one<SMALL>((int32_t)e, 0, 1, off, pins, hw, hseg, gmask, side, cc, pk, lds);
     } else if (vb < ns + nw) {
         int64_t i = (vb - ns) * (kBlock / 64) + (threadIdx.x >> 6);
         if (i < nmid)
-            hedge_contrib_one<WAVE>(lmid[i], threadIdx.x & 63, 64, off, pins, hw, hseg, gmask, side, cc, lds);
+            hedge_contrib_one<WAVE>(lmid[i], threadIdx.x & 63, 64, off, pins, hw, hseg, gmask, side, cc, pk, lds);
     } else if (vb - ns - nw < nbig) {
         hedge_contrib_one<BLOCK>(lbig[vb - ns - nw], threadIdx.x, blockDim.x, off, pins, hw, hseg, gmask,
-                                 side, cc, lds);
+                                 side, cc, pk, lds);
     }
 }
 
@@ -214,7 +232,7 @@ __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, c
 // in and out), 10 per pin (id, side, move flag, gain).
 __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t *bits, const int32_t *off,
                                                         const int32_t *pins, const int32_t *hw,
-                                                        const uint8_t *side, const uint8_t *moved, int2 *cc,
+                                                        const uint8_t *side, const uint8_t *moved, void *cc, int pk,
                                                         int32_t *gain, const int32_t *bigslot,
                                                         const int32_t *lnbig, const int32_t *ncount,
                                                         const int32_t *go, int32_t *logcount,
@@ -259,7 +277,8 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             int32_t e = queue[q];
             int32_t b = off[e], d = off[e + 1] - b;
             if (abytes) atomicAdd(&npins, d);
-            if (d <= kSmallMax) cc[e] = recount_small(e, b, d, pins, hw, side, moved, cc[e], bigslot, slot, gain);
+            if (d <= kSmallMax)
+                cc_put(cc, pk, e, recount_small(e, b, d, pins, hw, side, moved, cc_get(cc, pk, e), bigslot, slot, gain));
             else if (d <= kUpdWaveMax) bigq[atomicAdd(&nbq, 1)] = e;
             else bigq[kUpdQueue - 1 - atomicAdd(&nhq, 1)] = e;  // front and back never meet
         }
@@ -269,7 +288,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             int32_t e = bigq[q];
             int32_t b = off[e], d = off[e + 1] - b;
             int32_t w = hw[e];
-            int2 oc = cc[e];
+            int2 oc = cc_get(cc, pk, e);
             // up to kUpdWaveMax / 64 pins a lane, held in registers: their ids,
             // then their sides and move flags, each group of loads in flight
             // together, and used by both the count and the deltas
@@ -296,13 +315,13 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                 int32_t delta = (sn[k] ? nc.y : nc.x) - (o ? oc.y : oc.x);
                 if (delta) add_gain(u[k], delta, bigslot, slot, gain);
             }
-            if (lane == 0) cc[e] = nc;
+            if (lane == 0) cc_put(cc, pk, e, nc);
         }
         // the largest ones by the whole workgroup, one after another
         for (int32_t q = 0; q < nhuge; q++) {
             int32_t e = bigq[kUpdQueue - 1 - q];
             int32_t b = off[e], d = off[e + 1] - b;
-            int2 oc = cc[e];
+            int2 oc = cc_get(cc, pk, e);
             int32_t w = hw[e];
             if (d <= kUpdHugeRegs * kBlock) {
                 // up to kUpdHugeRegs pins a thread in registers (loaded once, in
@@ -329,7 +348,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                     if (delta) add_gain(u[k], delta, bigslot, slot, gain);
                 }
                 __syncthreads();  // every thread has read the old contribution
-                if (threadIdx.x == 0) cc[e] = nc;
+                if (threadIdx.x == 0) cc_put(cc, pk, e, nc);
                 continue;
             }
             int32_t n1 = 0;
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                 if (delta) add_gain(u, delta, bigslot, slot, gain);
             }
             __syncthreads();  // every thread has read the old contribution
-            if (threadIdx.x == 0) cc[e] = nc;
+            if (threadIdx.x == 0) cc_put(cc, pk, e, nc);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -373,7 +392,7 @@ template <int S>
 __device__ __forceinline__ void node_gain_one(int32_t v, int lane, int stride, const int32_t *noff,
                                               const int32_t *inc, const int32_t *nseg,
                                               const uint8_t *gmask, const uint8_t *side,
-                                              const int2 *cc, int32_t *gain, int32_t *lds,
+                                              const void *cc, int pk, int32_t *gain, int32_t *lds,
                                               const uint8_t *mode, int32_t *tot, int32_t *gmax,
                                               int32_t *gmin, bool stats)
 {
@@ -392,14 +411,14 @@ __device__ __forceinline__ void node_gain_one(int32_t v, int lane, int stride, c
             for (int k = 0; k < 8; k++) e8[k] = inc[b + min(i0 + k, d - 1)];
 #pragma unroll
             for (int k = 0; k < 8; k++) {
-                int2 c = cc[e8[k]];
+                int2 c = cc_get(cc, pk, e8[k]);
                 if (i0 + k < d) g += sd ? c.y : c.x;
             }
         }
     } else {
 #pragma unroll 4
         for (int i = lane; i < d; i += stride) {
-            int2 c = cc[inc[b + i]];
+            int2 c = cc_get(cc, pk, inc[b + i]);
             g += sd ? c.y : c.x;
         }
     }
@@ -421,7 +440,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
                                                        const int32_t *lnbig, const int32_t *ncount,
                                                        const int32_t *noff, const int32_t *inc,
                                                        const int32_t *nseg, const uint8_t *gmask,
-                                                       const uint8_t *side, const int2 *cc,
+                                                       const uint8_t *side, const void *cc, int pk,
                                                        int32_t *gain, const uint8_t *mode,
                                                        int32_t *tot, int32_t *gmax, int32_t *gmin,
                                                        const int32_t *go, const int32_t *chunk_node,
@@ -463,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
                 for (int k = 0; k < 8; k++) e8[k] = inc[b + min(i0 + k, d - 1)];
 #pragma unroll
                 for (int k = 0; k < 8; k++) {
-                    int2 c = cc[e8[k]];
+                    int2 c = cc_get(cc, pk, e8[k]);
                     if (i0 + k < d) g += sd ? c.y : c.x;
                 }
             }
@@ -508,7 +527,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
             int32_t g = 0;
 #pragma unroll 4
             for (int j = lane; j < d; j += 64) {
-                int2 c = cc[inc[b + j]];
+                int2 c = cc_get(cc, pk, inc[b + j]);
                 g += sd ? c.y : c.x;
             }
             g = wave_sum(g);
@@ -545,7 +564,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
         int32_t b = chunk_beg[q], e = min(b + kNodeChunk, noff[v + 1]);
         int32_t g = 0;
         for (int32_t i = b + threadIdx.x; i < e; i += blockDim.x) {
-            int2 c = cc[inc[i]];
+            int2 c = cc_get(cc, pk, inc[i]);
             g += sd ? c.y : c.x;
         }
         g = block_sum(g, lds);

@@ -216,6 +216,11 @@ PARTITION_CASES = [
     ("huge-k2", lambda: _huge_graph(6), 2, 0.05),
     ("vlsi20k-k16", lambda: I.vlsi(seed=15, n=20000), 16, 0.05),
     ("tiny-k7", lambda: I.tiny(), 7, 0.05),
+    # hyperedge weights at the edge of the 16-bit contribution encoding: the
+    # finest level has w(e) up to 2^15 - 1 (packed), coarser levels sum
+    # merged duplicates past it (int2); and weights past it from the start
+    ("hw-32767", lambda: I.random_small(60000, 70000, 2, 6, 12, weighted_hedges=True, max_w=32767), 4, 0.05),
+    ("hw-60000", lambda: I.random_small(6000, 7000, 2, 10, 11, weighted_hedges=True, max_w=60000), 4, 0.05),
 ]
 
 
