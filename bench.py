@@ -15,6 +15,7 @@ k = 2), tiny, batch, serve.
 import argparse
 import json
 import os
+import re
 import sys
 import time
 
@@ -205,7 +206,8 @@ def profiled_step(step, workload=None):
     for s in stats[:25]:
         gbs = s["bytes"] / (s["total_ms"] * 1e6) if s["total_ms"] > 0 else 0
         log(f"  {s['name']:<16} {s['launches']:6d} launches {s['total_ms']:8.3f} ms "
-            f"(net {corr(s):8.3f}) avg {1000 * s['total_ms'] / s['launches']:8.2f} us  {gbs:8.1f} GB/s")
+            f"(net {corr(s):8.3f}) avg {1000 * s['total_ms'] / s['launches']:8.2f} us  {gbs:8.1f} GB/s "
+            f"{s['bytes'] / s['launches']:12.0f} B/launch")
     phases = {}
     for ph, fams in PHASE_OF.items():
         sel = [s for s in stats if s["name"] in fams]
@@ -589,6 +591,21 @@ def summarize_traffic(args):
                 "fetch_bytes_per_launch": fpd * 1024.0 * ff, "write_bytes_per_launch": wpd * 1024.0 * wf,
                 "kernel_sources": KERNEL_SOURCES, "sources_sha256": h.hexdigest(),
                 "commands": args.summary_command.split(" ;; ")})
+    if args.summary_log:
+        # the family's algorithmic bytes per launch, from the per-family table
+        # that the profiled step of a plain run of the same workload logged
+        alg = None
+        pat = re.compile(r"^\s*(\S+)\s+(\d+) launches\s+([\d.]+) ms .*?([\d.]+) GB/s(?:\s+(\d+) B/launch)?")
+        with open(args.summary_log) as fh:
+            for line in fh:
+                m = pat.match(line)
+                if m and m.group(1) == args.summary_family:
+                    n, ms, gbs = int(m.group(2)), float(m.group(3)), float(m.group(4))
+                    alg = float(m.group(5)) if m.group(5) else gbs * ms * 1e6 / n
+        if alg:
+            out["family"] = args.summary_family
+            out["algorithmic_bytes_per_launch"] = round(alg)
+            out["traffic_over_algorithmic"] = round(out["hbm_bytes_per_launch"] / alg, 3)
     with open(args.summary_out, "w") as fh:
         json.dump(out, fh, indent=1)
         fh.write("\n")
@@ -632,6 +649,9 @@ def main():
     ap.add_argument("--summary-steps", type=int, default=1)
     ap.add_argument("--summary-top", type=int, default=30)
     ap.add_argument("--summary-out", default="")
+    ap.add_argument("--summary-log", default="", help="bench log whose profiled-step table gives the "
+                    "family's algorithmic bytes per launch")
+    ap.add_argument("--summary-family", default="seg_select")
     args = ap.parse_args()
     if args.summarize_stats:
         return summarize_stats(args)
