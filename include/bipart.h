@@ -232,7 +232,7 @@ bp_status bp_partition_batch_device(int32_t n, const bp_hypergraph *graphs, cons
 typedef struct {
     int32_t incremental_min_pins;  /* levels with at least this many pins plus nodes (a full gain
                                       pass reads both) update balance-round gains
-                                      from the moves; INT32_MAX: always recompute (default 262144) */
+                                      from the moves; INT32_MAX: always recompute (default 65536) */
     int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes select
                                       and move in one workgroup per segment (capped at 16384 for
                                       swaps, 32768 for balance); 0: never (default 32768) */
