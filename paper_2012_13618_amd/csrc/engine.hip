@@ -443,11 +443,11 @@ static void select_and_flip(Ctx &cx, Level &L, Segs &sg, const int32_t *gain, co
         if (L.maxseg_nodes <= seg_select_max<0, kSegThreadsSmall>())
             launch(cx.lc, "seg_select", 6.0 * L.N, k_seg_select<0, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                    L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
-                   bf, go, (uint8_t *)nullptr, ChunkArgs{});
+                   bf, go, ChunkArgs{});
         else
             launch(cx.lc, "seg_select", 6.0 * L.N, k_seg_select<0, kSegThreads>, L.S, kSegThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w,
-                   bf, go, (uint8_t *)nullptr, ChunkArgs{});
+                   bf, go, ChunkArgs{});
         return;
     }
     run_select(cx, L, sg, gain, go);
@@ -646,19 +646,18 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
     // the three short launches they take
     bool incr = (int64_t)L.P + L.N >= cx.sched.incremental_min_pins && !fuse_all(cx, L);
     Arena &ar = *cx.ar;
-    MoveLog ml{L.noff, nullptr, nullptr, nullptr, nullptr};
+    MoveLog ml{L.noff, nullptr, nullptr, nullptr};
     uint32_t *bits = nullptr;
     int64_t nbits = ceil_div(L.E, 32);
     Fills zf;
     zf.add(sg.go, 8, 0).add(sg.bal_moved, (int64_t)2 * L.S, (int64_t)0);
     if (incr) {
         int64_t chunks = (int64_t)L.P / kLogChunk + L.N + 1;
-        ml.moved = ar.get<uint8_t>(L.N);
         ml.cnode = ar.get<int32_t>(chunks);
         ml.cbeg = ar.get<int32_t>(chunks);
         ml.count = ar.get<int32_t>(4);
         bits = ar.get<uint32_t>(nbits);
-        zf.add(ml.moved, (int64_t)L.N, (uint8_t)0).add(bits, nbits, 0u).add(ml.count, 4, 0);
+        zf.add(bits, nbits, 0u).add(ml.count, 4, 0);
     }
     zf.run(lc);
     // small segments: the whole balance step in one workgroup each; when every
@@ -707,36 +706,37 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
             // the round's test and the marking of the last round's moves: one launch
             launch(lc, "round", 0.0, k_round_balance_log, gs + lg, kBlock, 0, gs, rb, sg.st, sg.go, ri,
                    (const int32_t *)ml.count, (const int32_t *)ml.cnode, (const int32_t *)ml.cbeg,
-                   (const int32_t *)L.noff, (const int32_t *)L.inc, bits);
+                   (const int32_t *)L.noff, (const int32_t *)L.inc, bits, (const void *)L.cc, L.cc_pk,
+                   (const uint8_t *)L.side, gain);
             launch(lc, "gain_update", 0.0, k_gain_update, ugrid, kBlock, 0, nbits, bits,
                    (const int32_t *)L.off, (const int32_t *)L.pins, (const int32_t *)L.hw,
-                   (const uint8_t *)L.side, (const uint8_t *)ml.moved, (void *)L.cc, L.cc_pk, gain, (const int32_t *)L.bigslot,
+                   (const uint8_t *)L.side, (void *)L.cc, L.cc_pk, gain, (const int32_t *)L.bigslot,
                    (const int32_t *)L.lnbig, (const int32_t *)L.ncount, gc, ml.count, ubytes);
             if (!seg && !chunk)
                 launch(lc, "gain_stats", 10.0 * L.N, k_gain_stats, reduce_grid(L.N), kBlock, 0, L.N,
                    (const int32_t *)L.nseg, (const uint8_t *)sg.gmask, (const uint8_t *)L.side,
                    (const int32_t *)gain, (const uint8_t *)sg.mode, sg.st.tot, sg.st.gmax, sg.st.gmin,
-                   ml.moved, ml.count, gc);
+                   ml.count, gc);
         }
         if (seg) {
             if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsSmall>())
                 launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreadsSmall>, L.S, kSegThreadsSmall, 0,
                        L.S, sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
+                       (unsigned long long *)sg.w, bf, gc, ChunkArgs{});
             else if (L.maxseg_nodes <= seg_select_max<1, kSegThreadsBal>())
                 launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreadsBal>, L.S, kSegThreadsBal, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
+                       (unsigned long long *)sg.w, bf, gc, ChunkArgs{});
             else
                 launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kSegThreads>, L.S, kSegThreads, 0, L.S,
                        sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw,
-                       (unsigned long long *)sg.w, bf, gc, ml.moved, ChunkArgs{});
+                       (unsigned long long *)sg.w, bf, gc, ChunkArgs{});
             return;
         }
         if (chunk) {
             launch(lc, "seg_select", 6.0 * L.N, k_seg_select<1, kChunkThreads, true>, nct, kChunkThreads, 0, L.S,
                    sel_view(L, sg, gain), sg.st, id_bits(L), (const int32_t *)L.nw, (unsigned long long *)sg.w, bf,
-                   gc, ml.moved, ca);
+                   gc, ca);
             return;
         }
         run_select(cx, L, sg, gain, gc, sg.cand_stride);

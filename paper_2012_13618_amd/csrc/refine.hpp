@@ -59,12 +59,11 @@ __global__ __launch_bounds__(kBlock) void k_side_weights(int32_t N, const int32_
 
 constexpr int kLogChunk = 64;  // incidences of a moved node per logged chunk
 
-// What a balance round moved, for the next round's gain update: moved[v] is
-// set for every moved node, and its incidence range is logged in chunks of
-// 64 (node, first incidence) so that the next step is evenly parallel.
+// What a balance round moved, for the next round's gain update: every moved
+// node's incidence range, logged in chunks of 64 (node, first incidence) so
+// that the next step is evenly parallel.
 struct MoveLog {
     const int32_t *noff;
-    uint8_t *moved;
     int32_t *cnode, *cbeg;
     int32_t *count;  // [0] logged chunks, [1] listed small hyperedges, [2] listed big ones
 };
@@ -80,7 +79,6 @@ __device__ __forceinline__ void log_moves(int32_t p, const uint64_t *a, const Mo
             v = (int32_t)(uint32_t)(a[i] & 0xffffffffu);
             b = ml.noff[v];
             c = (int32_t)ceil_div(ml.noff[v + 1] - b, kLogChunk);
-            ml.moved[v] = 1;
         }
         int64_t tot;
         int64_t ex = block_excl_scan((int64_t)c, lds64, &tot);
@@ -191,7 +189,6 @@ __device__ __forceinline__ void log_moves_wave(int32_t p, const uint64_t *a, con
             v = (int32_t)(uint32_t)(a[i] & 0xffffffffu);
             b = ml.noff[v];
             c = (int32_t)ceil_div(ml.noff[v + 1] - b, kLogChunk);
-            ml.moved[v] = 1;
         }
         int32_t incl = wave_incl_scan(c);
         int32_t tot = __shfl(incl, 63, 64);

@@ -126,9 +126,17 @@ __global__ __launch_bounds__(kBlock) void k_gain_hedges(int32_t E, const int32_t
 // bitmap word are adjacent and the first lane of each run sets the run's bits
 // with one atomic (none when they are all set already).  Here: blocks b of nb
 // (kBlock threads each) of the marking of the n logged chunks.
+//
+// It also settles the moved node's side change in its gain.  The gain update
+// that follows treats every pin as unmoved (new contribution minus old, both
+// for the pin's side now); a node that moved from side o to side s had gained
+// the old contribution for o, so it is owed old[s] - old[o] per hyperedge,
+// added here while the contributions are still the old ones.  That way the
+// update reads one side byte per pin and no move flags.
 __device__ __forceinline__ void log_hedges_blocks(int64_t b, int64_t nb, int32_t n, const int32_t *cnode,
                                                   const int32_t *cbeg, const int32_t *noff, const int32_t *inc,
-                                                  uint32_t *bits)
+                                                  uint32_t *bits, const void *cc, int pk, const uint8_t *side,
+                                                  int32_t *gain)
 {
     int lane = threadIdx.x & 63;
     const int64_t wpb = kBlock / 64;
@@ -137,6 +145,14 @@ __device__ __forceinline__ void log_hedges_blocks(int64_t b, int64_t nb, int32_t
         int32_t j = cbeg[i] + lane, end = noff[v + 1];
         bool valid = j < end;
         int32_t e = valid ? inc[j] : 0;
+        int sv = side[v];
+        int32_t corr = 0;
+        if (valid) {
+            int2 oc = cc_get(cc, pk, e);
+            corr = sv ? oc.y - oc.x : oc.x - oc.y;
+        }
+        corr = wave_sum(corr);
+        if (lane == 0 && corr) atomicAdd(&gain[v], corr);
         int32_t w = valid ? (e >> 5) : -1;
         uint32_t bit = valid ? 1u << (e & 31) : 0u;
         int32_t pw = __shfl_up(w, 1, 64);
@@ -187,39 +203,35 @@ constexpr int kUpdHugeRegs = 8;            // ... whose pins fit kUpdHugeRegs a 
 // recount of hyperedge e (pins b .. b + d, d <= kSmallMax) after a round:
 // its new contribution, with each pin's gain change added
 __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, const int32_t *pins,
-                                              const int32_t *hw, const uint8_t *side, const uint8_t *moved,
-                                              int2 oc, const int32_t *bigslot, int32_t *slot, int32_t *gain)
+                                              const int32_t *hw, const uint8_t *side, int2 oc,
+                                              const int32_t *bigslot, int32_t *slot, int32_t *gain)
 {
     // straight-line loads (past the degree: pin 0 again), so that they fly together
     int32_t u[kSmallMax];
-    uint32_t sn[kSmallMax], so[kSmallMax];
+    uint32_t sn[kSmallMax];
     int32_t n1 = 0;
 #pragma unroll
     for (int j = 0; j < kSmallMax; j++) u[j] = pins[b + (j < d ? j : 0)];
 #pragma unroll
-    for (int j = 0; j < kSmallMax; j++) {
-        sn[j] = side[u[j]];
-        so[j] = moved[u[j]];
-    }
+    for (int j = 0; j < kSmallMax; j++) sn[j] = side[u[j]];
 #pragma unroll
-    for (int j = 0; j < kSmallMax; j++) {
-        so[j] ^= sn[j];
+    for (int j = 0; j < kSmallMax; j++)
         if (j < d) n1 += sn[j];
-    }
     int2 nc = hedge_contrib_value(hw[e], d, n1);
 #pragma unroll
     for (int j = 0; j < kSmallMax; j++)
         if (j < d) {
-            int32_t delta = (sn[j] ? nc.y : nc.x) - (so[j] ? oc.y : oc.x);
+            int32_t delta = sn[j] ? nc.y - oc.y : nc.x - oc.x;
             if (delta) add_gain(u[j], delta, bigslot, slot, gain);
         }
     return nc;
 }
 
 // Marked hyperedges, found by sweeping the bitmap: recount the sides, replace
-// the contribution, and add the change to every pin's gain (a pin that moved
-// trades its old side's contribution for its new side's).  Integer sums, so
-// the result equals a recomputation.  The sweep clears the bitmap.
+// the contribution, and add the change to every pin's gain, as if no pin had
+// moved (the marking launch has already settled what the moved nodes are
+// owed for changing sides).  Integer sums, so the result equals a
+// recomputation.  The sweep clears the bitmap.
 //
 // The bitmap is dealt out in chunks of 8 words (256 hyperedges, in id order),
 // chunk c to workgroup c mod G: a moved node's hyperedges crowd into a few
@@ -228,11 +240,11 @@ __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, c
 // lists their marked hyperedges in LDS (popcount scan), then degree <= 8 go
 // one per thread, up to 512 one per wavefront, larger ones to the whole
 // workgroup.  When abytes is set (profiling), adds the algorithmic bytes it
-// moved: 4 per bitmap word, 28 per hyperedge (offsets, weight, contribution
-// in and out), 10 per pin (id, side, move flag, gain).
+// moved: 4 per bitmap word, per hyperedge 12 (offsets, weight) plus the
+// contribution in and out, 9 per pin (id, side, gain).
 __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t *bits, const int32_t *off,
                                                         const int32_t *pins, const int32_t *hw,
-                                                        const uint8_t *side, const uint8_t *moved, void *cc, int pk,
+                                                        const uint8_t *side, void *cc, int pk,
                                                         int32_t *gain, const int32_t *bigslot,
                                                         const int32_t *lnbig, const int32_t *ncount,
                                                         const int32_t *go, int32_t *logcount,
@@ -278,7 +290,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             int32_t b = off[e], d = off[e + 1] - b;
             if (abytes) atomicAdd(&npins, d);
             if (d <= kSmallMax)
-                cc_put(cc, pk, e, recount_small(e, b, d, pins, hw, side, moved, cc_get(cc, pk, e), bigslot, slot, gain));
+                cc_put(cc, pk, e, recount_small(e, b, d, pins, hw, side, cc_get(cc, pk, e), bigslot, slot, gain));
             else if (d <= kUpdWaveMax) bigq[atomicAdd(&nbq, 1)] = e;
             else bigq[kUpdQueue - 1 - atomicAdd(&nhq, 1)] = e;  // front and back never meet
         }
@@ -290,18 +302,15 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             int32_t w = hw[e];
             int2 oc = cc_get(cc, pk, e);
             // up to kUpdWaveMax / 64 pins a lane, held in registers: their ids,
-            // then their sides and move flags, each group of loads in flight
-            // together, and used by both the count and the deltas
+            // then their sides, each group of loads in flight together, and
+            // used by both the count and the deltas
             constexpr int kR = kUpdWaveMax / 64;
             int32_t u[kR];
-            uint32_t sn[kR], so[kR];
+            uint32_t sn[kR];
 #pragma unroll
             for (int k = 0; k < kR; k++) u[k] = pins[b + min(lane + 64 * k, d - 1)];
 #pragma unroll
-            for (int k = 0; k < kR; k++) {
-                sn[k] = side[u[k]];
-                so[k] = moved[u[k]];
-            }
+            for (int k = 0; k < kR; k++) sn[k] = side[u[k]];
             int32_t n1 = 0;
 #pragma unroll
             for (int k = 0; k < kR; k++)
@@ -311,8 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
 #pragma unroll
             for (int k = 0; k < kR; k++) {
                 if (lane + 64 * k >= d) continue;
-                uint32_t o = sn[k] ^ so[k];
-                int32_t delta = (sn[k] ? nc.y : nc.x) - (o ? oc.y : oc.x);
+                int32_t delta = sn[k] ? nc.y - oc.y : nc.x - oc.x;
                 if (delta) add_gain(u[k], delta, bigslot, slot, gain);
             }
             if (lane == 0) cc_put(cc, pk, e, nc);
@@ -327,14 +335,11 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
                 // up to kUpdHugeRegs pins a thread in registers (loaded once, in
                 // flight together) for both the count and the deltas
                 int32_t u[kUpdHugeRegs];
-                uint32_t sn[kUpdHugeRegs], so[kUpdHugeRegs];
+                uint32_t sn[kUpdHugeRegs];
 #pragma unroll
                 for (int k = 0; k < kUpdHugeRegs; k++) u[k] = pins[b + min((int32_t)threadIdx.x + kBlock * k, d - 1)];
 #pragma unroll
-                for (int k = 0; k < kUpdHugeRegs; k++) {
-                    sn[k] = side[u[k]];
-                    so[k] = moved[u[k]];
-                }
+                for (int k = 0; k < kUpdHugeRegs; k++) sn[k] = side[u[k]];
                 int32_t n1 = 0;
 #pragma unroll
                 for (int k = 0; k < kUpdHugeRegs; k++)
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
 #pragma unroll
                 for (int k = 0; k < kUpdHugeRegs; k++) {
                     if ((int32_t)threadIdx.x + kBlock * k >= d) continue;
-                    int32_t delta = (sn[k] ? nc.y : nc.x) - ((sn[k] ^ so[k]) ? oc.y : oc.x);
+                    int32_t delta = sn[k] ? nc.y - oc.y : nc.x - oc.x;
                     if (delta) add_gain(u[k], delta, bigslot, slot, gain);
                 }
                 __syncthreads();  // every thread has read the old contribution
@@ -359,8 +364,8 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
 #pragma unroll 4
             for (int j = threadIdx.x; j < d; j += blockDim.x) {
                 int32_t u = pins[b + j];
-                int sn = side[u], so = sn ^ moved[u];
-                int32_t delta = (sn ? nc.y : nc.x) - (so ? oc.y : oc.x);
+                int sn = side[u];
+                int32_t delta = sn ? nc.y - oc.y : nc.x - oc.x;
                 if (delta) add_gain(u, delta, bigslot, slot, gain);
             }
             __syncthreads();  // every thread has read the old contribution
@@ -377,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
     for (int i = threadIdx.x; i < nb; i += blockDim.x)
         if (slot[i]) atomicAdd(&gain[lnbig[i]], slot[i]);
     if (abytes && threadIdx.x == 0 && words_done)
-        atomicAdd(abytes, (unsigned long long)(4 * words_done + 28 * hedges_done + 10 * pins_done));
+        atomicAdd(abytes, (unsigned long long)(4 * words_done + (pk ? 20 : 28) * hedges_done + 9 * pins_done));
 }
 
 // eligibility of a node for its list under the segment's selection mode
@@ -592,7 +597,7 @@ __global__ __launch_bounds__(kBlock) void k_gain_nodes(int32_t N, const int32_t 
 __global__ __launch_bounds__(kBlock) void k_gain_stats(int32_t N, const int32_t *nseg, const uint8_t *gmask,
                                                        const uint8_t *side, const int32_t *gain,
                                                        const uint8_t *mode, int32_t *tot, int32_t *gmax,
-                                                       int32_t *gmin, uint8_t *moved, int32_t *counts,
+                                                       int32_t *gmin, int32_t *counts,
                                                        const int32_t *go)
 {
     __shared__ int32_t at[kAggLists], amax[kAggLists], amin[kAggLists];
@@ -610,7 +615,6 @@ __global__ __launch_bounds__(kBlock) void k_gain_stats(int32_t N, const int32_t 
     }
     __syncthreads();
     for (int64_t v = lo + threadIdx.x; v < hi; v += blockDim.x) {
-        if (moved[v]) moved[v] = 0;
         int32_t s = nseg[v];
         if (!gmask[s]) continue;
         int sd = side[v];
@@ -971,21 +975,6 @@ struct ChunkArgs {
     int32_t *ccnt;                     // [S][kChunkMax]: how many
 };
 
-// Zeroes p[0, n) with 16-byte stores (byte stores at the unaligned ends); the
-// threads of one workgroup, TH of them.
-template <int TH> __device__ __forceinline__ void clear_bytes(uint8_t *p, int32_t n)
-{
-    int32_t t = threadIdx.x;
-    int32_t head = (int32_t)((16 - ((uintptr_t)p & 15)) & 15);
-    head = head < n ? head : n;
-    if (t < head) p[t] = 0;
-    int32_t nv = (n - head) >> 4;
-    uint4 *q = (uint4 *)(p + head);
-    for (int32_t i = t; i < nv; i += TH) q[i] = make_uint4(0u, 0u, 0u, 0u);
-    int32_t t0 = head + (nv << 4);
-    if (t < n - t0) p[t0 + t] = 0;
-}
-
 // The merge of a balancing segment's chunk lists (1024 threads of one
 // workgroup, the last of the segment's chunks): each node of the chunks'
 // ascending lists is ranked among all of them (its index in its
@@ -1092,7 +1081,7 @@ template <int KIND, int TH, bool CH = false>
 __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits_lv,
                                                            const int32_t *nw,
                                                            unsigned long long *segw, BalFinish bf,
-                                                           const int32_t *go, uint8_t *moved, ChunkArgs ca)
+                                                           const int32_t *go, ChunkArgs ca)
 {
     static_assert(!CH || (KIND == 1 && TH * 16 == kChunkNodes), "chunks: balance, 16 nodes a thread");
     constexpr int kSegItems = CH ? 16 : seg_items<KIND, TH>();
@@ -1148,9 +1137,6 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
             g[j] = sv.gain[a0 + (i < n ? i : 0)];
         }
     }
-    // the previous round's move marks, in every segment (the gain update has
-    // used them); stored after the loads are issued, so that none waits for them
-    if (moved) clear_bytes<TH>(moved + a0, n);
     if (!md) return;
     if (n > 0) {
         // the sides staged in LDS
@@ -1578,7 +1564,8 @@ __global__ __launch_bounds__(kBlock) void k_round_balance_log(int64_t gs, RoundB
                                                               int32_t ri, const int32_t *count,
                                                               const int32_t *cnode, const int32_t *cbeg,
                                                               const int32_t *noff, const int32_t *inc,
-                                                              uint32_t *bits)
+                                                              uint32_t *bits, const void *cc, int pk,
+                                                              const uint8_t *side, int32_t *gain)
 {
     if ((int64_t)blockIdx.x < gs) {
         round_balance_seg(blockIdx.x * blockDim.x + threadIdx.x, rb, st, go, ri);
@@ -1587,7 +1574,8 @@ __global__ __launch_bounds__(kBlock) void k_round_balance_log(int64_t gs, RoundB
     // the previous round's counter and its log size, loaded together
     const int32_t prev = go[4 + (ri + 2) % 3], n = count[0];
     if (prev == 0) return;  // the previous round moved nothing
-    log_hedges_blocks((int64_t)blockIdx.x - gs, (int64_t)gridDim.x - gs, n, cnode, cbeg, noff, inc, bits);
+    log_hedges_blocks((int64_t)blockIdx.x - gs, (int64_t)gridDim.x - gs, n, cnode, cbeg, noff, inc, bits, cc, pk,
+                      side, gain);
 }
 
 
