@@ -149,10 +149,33 @@ __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t
         else atomicAdd(&cut[hseg[e]], c);
     };
     if (S == SMALL) {
-        for (int64_t e = lo + threadIdx.x; e < hi; e += blockDim.x) {
-            if (off[e + 1] - off[e] > kSmallMax) continue;
-            int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
-            if (lam > 1) add((int32_t)e, lam);
+        // a wavefront's hyperedges nearly always belong to one graph: the lanes
+        // of each graph present add up their cuts first, so that one lane adds
+        // for all of them (per-lane LDS atomics on one address serialize)
+        const int lane = threadIdx.x & 63;
+        for (int64_t base = lo; base < hi; base += blockDim.x) {
+            int64_t e = base + threadIdx.x;
+            unsigned long long c = 0;
+            int32_t g = -1;
+            if (e < hi && off[e + 1] - off[e] <= kSmallMax) {
+                int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
+                if (lam > 1) {
+                    c = (unsigned long long)hw[e] * (lam - 1);
+                    g = hseg[e];
+                }
+            }
+            unsigned long long left = __ballot(c != 0);
+            while (left) {
+                int32_t gl = __shfl(g, __ffsll((long long)left) - 1, 64);
+                bool mine = c != 0 && g == gl;
+                unsigned long long sum = wave_sum(mine ? c : 0ull);
+                if (lane == __ffsll((long long)left) - 1) {
+                    int32_t q = gl - s0;
+                    if (q >= 0 && q < kAggLists) atomicAdd(&acc[q], sum);
+                    else atomicAdd(&cut[gl], sum);
+                }
+                left &= ~__ballot(mine);
+            }
         }
     } else if (S == WAVE) {
         for (int64_t i = lo + (threadIdx.x >> 6); i < hi; i += blockDim.x >> 6) {

@@ -1359,7 +1359,7 @@ std::vector<BatchOut> partition_batch(Ctx &cx, const std::vector<BatchItem> &it,
         fill(lc, acc, 2 * S, 0ull);
         fill(lc, pw, kb[S], 0ull);
         check_lists(root);
-        launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, reduce_grid(root.E), kBlock,
+        launch(lc, "cut_small", 8.0 * root.E + 8.0 * root.P, k_cut_seg<SMALL>, cut_grid<SMALL>(root.E), kBlock,
                0, root.E, (const int32_t *)nullptr, (const int32_t *)root.off, (const int32_t *)root.pins,
                (const int32_t *)root.hw, (const int32_t *)root.hseg, (const int32_t *)part, kmax, acc);
         launch(lc, "cut_wave", 0.0, k_cut_seg<WAVE>, cut_grid<WAVE>(root.nmid), kBlock, 0, root.nmid,

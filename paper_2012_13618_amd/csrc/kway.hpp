@@ -374,14 +374,17 @@ __device__ __forceinline__ int32_t hedge_lambda(int32_t e, int lane, int stride,
 // hyperedges of degree <= 8, one per thread; WAVE / BLOCK: the listed ones).
 // Each workgroup writes its sum to partial[blockIdx.x] (no same-address
 // atomics); k_sum_u64 adds the partial sums up.  SMALL: contiguous chunks of
-// hyperedges over at most kReduceBlocks workgroups; WAVE / BLOCK: the listed
+// about two hyperedges a thread (at most kCutBlocks workgroups); WAVE / BLOCK: the listed
 // hyperedges, as many workgroups as keep every wavefront on about one
 // hyperedge (at most kCutBlocks).
 constexpr int64_t kCutBlocks = 16384;
 
 template <int S> inline int64_t cut_grid(int64_t count)
 {
-    if (S == SMALL) return reduce_grid(count);
+    if (S == SMALL) {  // two hyperedges a thread: enough loads in flight to cover the gathers
+        int64_t g = ceil_div(count, (int64_t)2 * kBlock);
+        return g < kCutBlocks ? g : kCutBlocks;
+    }
     int64_t g = S == WAVE ? sched_grid<WAVE>(count) : count;
     return g < kCutBlocks ? g : kCutBlocks;
 }
