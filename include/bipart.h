@@ -235,7 +235,7 @@ typedef struct {
                                       from the moves; INT32_MAX: always recompute (default 65536) */
     int32_t seg_select_max_nodes;  /* levels whose segments all have at most this many nodes select
                                       and move in one workgroup per segment (capped at 16384 for
-                                      swaps, 32768 for balance); 0: never (default 32768) */
+                                      swaps, 32768 for balance); 0: never (default 16384) */
     int32_t round_chunk_max;       /* most rounds issued between host checks, 1..64 (default 32) */
     int32_t fused_pick_lists;      /* up to this many lists the digit picks run in the histogram
                                       launch's last workgroup, above in per-segment ones,

@@ -18,7 +18,7 @@ struct Input {
 // Launch schedule (results never depend on it): see bp_schedule.
 struct Schedule {
     int32_t incremental_min_pins = 1 << 16;
-    int32_t seg_select_max_nodes = 1 << 15;
+    int32_t seg_select_max_nodes = 1 << 14;
     int32_t round_chunk_max = 32;
     int32_t fused_pick_lists = 8;
     int32_t fuse_max_pins = 1 << 17;

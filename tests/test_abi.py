@@ -95,7 +95,7 @@ def test_batch_host_validation_errors():
 
 def test_schedule_defaults_and_validation():
     d = bp.schedule_default()
-    assert d.as_dict() == {"incremental_min_pins": 1 << 16, "seg_select_max_nodes": 1 << 15,
+    assert d.as_dict() == {"incremental_min_pins": 1 << 16, "seg_select_max_nodes": 1 << 14,
                            "round_chunk_max": 32, "fused_pick_lists": 8, "fuse_max_pins": 1 << 17,
                            "chunk_select_max_nodes": 1 << 18, "graph_rounds": 0}
     old = bp.schedule_get()

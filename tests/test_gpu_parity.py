@@ -305,18 +305,22 @@ def _zero_weights(h, every=3):
 CHUNKS = 1 << 18  # the chunked selection's default (and largest) segment size
 
 
-@pytest.mark.parametrize("n,fuse,chunk,zw", [
-    (8192, 1 << 30, CHUNKS, False), (8193, 1 << 30, CHUNKS, False), (20000, 0, CHUNKS, False),
-    (30000, 0, CHUNKS, False), (6000, 1 << 30, CHUNKS, True), (40000, 0, CHUNKS, False),
-    (40000, 0, 0, False), (CHUNKS, 0, CHUNKS, False), (CHUNKS + 1, 0, CHUNKS, False), (50000, 0, CHUNKS, True),
-    (32769, 0, CHUNKS, False)],
+SEG = 1 << 15  # the one-workgroup selections' largest segment (balance)
+
+
+@pytest.mark.parametrize("n,fuse,chunk,zw,seg", [
+    (8192, 1 << 30, CHUNKS, False, SEG), (8193, 1 << 30, CHUNKS, False, SEG), (20000, 0, CHUNKS, False, SEG),
+    (30000, 0, CHUNKS, False, SEG), (6000, 1 << 30, CHUNKS, True, SEG), (40000, 0, CHUNKS, False, SEG),
+    (40000, 0, 0, False, SEG), (CHUNKS, 0, CHUNKS, False, SEG), (CHUNKS + 1, 0, CHUNKS, False, SEG),
+    (50000, 0, CHUNKS, True, SEG), (32769, 0, CHUNKS, False, SEG), (20000, 0, CHUNKS, False, 1 << 14)],
     ids=["fused-at-limit", "fused-over-limit", "select-768", "select-1024", "fused-zero-w", "chunked",
-         "multi-workgroup", "chunked-at-limit", "chunked-over-limit", "chunked-zero-w", "chunked-one-node-tail"])
-def test_balance_size_limits(bp, n, fuse, chunk, zw):
+         "multi-workgroup", "chunked-at-limit", "chunked-over-limit", "chunked-zero-w", "chunked-one-node-tail",
+         "chunked-two"])
+def test_balance_size_limits(bp, n, fuse, chunk, zw, seg):
     """Balance steps at the size limits of the one-workgroup kernels (the fused
     rounds at 8192 nodes, the 768- and 1024-thread selections, the chunked
-    selection at 16 chunks of 16384 nodes), on the multi-workgroup passes, and
-    with zero-weight nodes, against the oracle."""
+    selection at 16 chunks of 16384 nodes and at two), on the multi-workgroup
+    passes, and with zero-weight nodes, against the oracle."""
     import torch
     h = I.random_small(n, int(1.1 * n), 2, 12, 40 + n % 97, weighted_nodes=True, weighted_hedges=True)
     if zw:
@@ -326,6 +330,7 @@ def test_balance_size_limits(bp, n, fuse, chunk, zw):
         s = bp.schedule_default()
         s.fuse_max_pins = fuse
         s.chunk_select_max_nodes = chunk
+        s.seg_select_max_nodes = seg
         s.incremental_min_pins = 0  # the later rounds update their gains from the moves
         bp.schedule_set(s)
         say("balance limits", h.name, s.as_dict())
