@@ -1138,6 +1138,8 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         }
     }
     if (!md) return;
+    // the histogram starts cleared; each radix pass clears the bins it read
+    for (int i = threadIdx.x; i < kBins; i += TH) hist[i] = 0;
     if (n > 0) {
         // the sides staged in LDS
 #pragma unroll
@@ -1222,9 +1224,6 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         int32_t rem = (int32_t)r;
         for (int p = 0;; p++) {
             int hi = T - kDigit * p, lo = hi - kDigit > 0 ? hi - kDigit : 0;
-            for (int j = 0; j < per; j++)
-                if (threadIdx.x * per + j < kBins) hist[threadIdx.x * per + j] = 0;
-            __syncthreads();
             uint64_t mine = ebits & (sd ? sbits : ~sbits);
 #pragma unroll
             for (int j = 0; j < kSegItems; j++) {
@@ -1252,6 +1251,9 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
                     acc += x;
                 }
             }
+            // only this thread reads its bins: clear them for the next pass
+            for (int j = 0; j < per; j++)
+                if (threadIdx.x * per + j < kBins) hist[threadIdx.x * per + j] = 0;
             __syncthreads();
             int32_t bin = sbin, left = rem - sbefore, inb = sin_;
             __syncthreads();
