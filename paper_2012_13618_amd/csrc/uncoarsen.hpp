@@ -1234,10 +1234,17 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
                 atomicAdd(&hist[dig], 1u);
             }
             __syncthreads();
-            int64_t loc = 0, tot;
+            int64_t loc = 0;
             for (int j = 0; j < per; j++)
                 if (threadIdx.x * per + j < kBins) loc += hist[threadIdx.x * per + j];
-            int64_t ex = block_excl_scan(loc, lds64, &tot);
+            // exclusive scan of the bin sums over the workgroup: the barrier
+            // above already separates these LDS writes from the last pass's
+            // reads, and the one below the bin pick from the next pass's writes
+            int64_t ex = wave_incl_scan(loc);
+            if ((threadIdx.x & 63) == 63) lds64[threadIdx.x >> 6] = ex;
+            __syncthreads();
+            for (int w = 0; w < (int)(threadIdx.x >> 6); w++) ex += lds64[w];
+            ex -= loc;
             if (ex < rem && rem <= ex + loc) {
                 int64_t acc = ex;
                 for (int j = 0; j < per; j++) {
@@ -1255,8 +1262,8 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
             for (int j = 0; j < per; j++)
                 if (threadIdx.x * per + j < kBins) hist[threadIdx.x * per + j] = 0;
             __syncthreads();
+            // (the next pass writes the pick only after two more barriers)
             int32_t bin = sbin, left = rem - sbefore, inb = sin_;
-            __syncthreads();
             pre |= (uint64_t)bin << lo;
             rem = left;
             if (left == inb || lo == 0) {
