@@ -1138,8 +1138,10 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         }
     }
     if (!md) return;
-    // the histogram starts cleared; each radix pass clears the bins it read
+    // the histogram starts cleared (each radix pass clears the bins it read),
+    // the balance key list empty
     for (int i = threadIdx.x; i < kBins; i += TH) hist[i] = 0;
+    if (threadIdx.x == 0) nkeys = 0;
     if (n > 0) {
         // the sides staged in LDS
 #pragma unroll
@@ -1195,7 +1197,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
             lmin[0] = min(lmin[0], red[w][4]);
             lmin[1] = min(lmin[1], red[w][5]);
         }
-        __syncthreads();
+        // (red is not written again: no barrier before what follows)
     }
     uint64_t thr[2] = {0, 0};
     int32_t rr[2] = {0, 0};
@@ -1300,8 +1302,6 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     }
     // balance: the chosen nodes of the over-weight side, sorted, then the prefix
     int h = (md & kList1) ? 1 : 0;
-    if (threadIdx.x == 0) nkeys = 0;
-    __syncthreads();
     if (rr[h] > 0) {
         uint64_t mine = ebits & (h ? sbits : ~sbits);
 #pragma unroll
