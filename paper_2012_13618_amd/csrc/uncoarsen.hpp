@@ -980,15 +980,14 @@ struct ChunkArgs {
 // ascending lists is ranked among all of them (its index in its
 // own list plus, by binary search, the smaller keys of every other list); the
 // first min(total, m) in order are the segment's chosen nodes.  Then the
-// balance prefix (Algorithm 5) over them, with their weights staged in LDS by
-// the ranking threads: one scan, as the chosen nodes fit the workgroup.
+// balance prefix (Algorithm 5) over them: one scan of their weights, one
+// chosen node a thread, as they fit the workgroup.
 __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, const int32_t *m, ChunkArgs ca,
                                               BalFinish bf)
 {
     static_assert(kChunkKeys <= 1024, "the chosen nodes fit the workgroup");
     __shared__ uint64_t a[kChunkMax * kChunkKeys];
     __shared__ uint64_t out[kChunkKeys];
-    __shared__ int64_t wts[kChunkKeys];
     __shared__ int64_t lds64[16];
     __shared__ int32_t cnt[kChunkMax], p1s, fits;
     __shared__ int64_t movedw;
@@ -1021,10 +1020,7 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
             }
             rank += lo;
         }
-        if (rank < take) {
-            out[rank] = x;
-            wts[rank] = bf.nw[(uint32_t)(x & 0xffffffffu)];
-        }
+        if (rank < take) out[rank] = x;
     }
     if (tid == 0) {
         p1s = take;
@@ -1032,13 +1028,21 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     }
     __syncthreads();
     // the shortest prefix reaching the excess, cut to what fits the room
-    // (weights are non-negative: prefix weights ascend)
+    // (weights are non-negative: prefix weights ascend, so each wavefront's
+    // first reaching lane and its fitting lanes come from two ballots); the
+    // chosen nodes' weights are gathered once, one a thread, after the ranking
     int h = (bf.mode[s] & kList1) ? 1 : 0;
     int64_t nd = bf.need[s], rm = bf.room[s];
-    int64_t w = tid < take ? wts[tid] : 0, wt;
-    int64_t incl = block_excl_scan(w, lds64, &wt) + w;
-    if (tid < take && incl >= nd) atomicMin(&p1s, tid + 1);
-    if (tid < take && incl <= rm) atomicAdd(&fits, 1);
+    int64_t w = tid < take ? (int64_t)bf.nw[(uint32_t)(out[tid] & 0xffffffffu)] : 0;
+    int64_t incl = wave_incl_scan(w);
+    if ((tid & 63) == 63) lds64[tid >> 6] = incl;
+    __syncthreads();
+    for (int q = 0; q < (tid >> 6); q++) incl += lds64[q];
+    unsigned long long reach = __ballot(tid < take && incl >= nd), fit = __ballot(tid < take && incl <= rm);
+    if ((tid & 63) == 0) {
+        if (reach) atomicMin(&p1s, (tid & ~63) + __ffsll((long long)reach));
+        if (fit) atomicAdd(&fits, __popcll(fit));
+    }
     __syncthreads();
     int32_t p = min(p1s, fits);
     if (tid < p) bf.side[(uint32_t)(out[tid] & 0xffffffffu)] = (uint8_t)(1 - h);
