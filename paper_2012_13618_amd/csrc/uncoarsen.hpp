@@ -53,6 +53,11 @@ __device__ __forceinline__ void cc_put(void *cc, int pk, int32_t e, int2 c)
 
 // ---- gains -------------------------------------------------------------------------
 
+// The hyperedge pass takes hyperedges of up to this many pins one a thread
+// (eight pins' loads in flight at a time); a wavefront per hyperedge would
+// leave most of its lanes idle on them and add a reduction.
+constexpr int32_t kHedgeThreadMax = 32;
+
 template <int S>
 __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int stride, const int32_t *off,
                                                   const int32_t *pins, const int32_t *hw,
@@ -60,18 +65,22 @@ __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int strid
                                                   const uint8_t *side, void *cc, int pk, int32_t *lds)
 {
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
+    if (S == SMALL && d > kHedgeThreadMax) return;
+    if (S == WAVE && d <= kHedgeThreadMax) return;  // taken one a thread
     if (!gmask[hseg[e]]) return;
     int32_t n1 = 0;
     if (S == SMALL) {
-        // straight-line loads (past the degree: pin 0 again), in flight together
-        int32_t u[kSmallMax];
+        // eight pins at a time, straight-line loads (past the degree: the
+        // last pin again) in flight together
+        for (int32_t i0 = 0; i0 < d; i0 += 8) {
+            int32_t u[8];
 #pragma unroll
-        for (int i = 0; i < kSmallMax; i++) u[i] = pins[b + (i < d ? i : 0)];
+            for (int i = 0; i < 8; i++) u[i] = pins[b + min(i0 + i, d - 1)];
 #pragma unroll
-        for (int i = 0; i < kSmallMax; i++) {
-            int32_t x = side[u[i]];
-            if (i < d) n1 += x;
+            for (int i = 0; i < 8; i++) {
+                int32_t x = side[u[i]];
+                if (i0 + i < d) n1 += x;
+            }
         }
     } else {
 #pragma unroll 4
