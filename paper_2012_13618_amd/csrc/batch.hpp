@@ -157,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t
             int64_t e = base + threadIdx.x;
             unsigned long long c = 0;
             int32_t g = -1;
-            if (e < hi && off[e + 1] - off[e] <= kSmallMax) {
+            if (e < hi && thread_split<SMALL>(off[e + 1] - off[e])) {
                 int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
                 if (lam > 1) {
                     c = (unsigned long long)hw[e] * (lam - 1);
@@ -180,6 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_cut_seg(int32_t count, const int32_t
     } else if (S == WAVE) {
         for (int64_t i = lo + (threadIdx.x >> 6); i < hi; i += blockDim.x >> 6) {
             int32_t e = list[i];
+            if (!thread_split<WAVE>(off[e + 1] - off[e])) continue;
             int32_t lam = hedge_lambda<WAVE>(e, threadIdx.x & 63, 64, off, pins, part, mask64, orl, lds);
             if ((threadIdx.x & 63) == 0 && lam > 1) add(e, lam);
         }

@@ -125,7 +125,7 @@ __device__ __forceinline__ void AttachOp::run(int64_t vb, int32_t count, const i
     int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
+    if (!thread_split<S>(d)) return;
     if ((cg[e] >> 32) != 1 || !sact[hseg[e]]) return;
     unsigned long long best = kNoKey, uu = kNoKey;
     for (int i = lane; i < d; i += stride) {
@@ -571,7 +571,7 @@ __device__ __forceinline__ void CopyPinsOp::run(int64_t vb, int32_t count, const
     int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e];
-    if (S == SMALL && off[e + 1] - b > kSmallMax) return;
+    if (!thread_split<S>(off[e + 1] - b)) return;
     if (rep[e] != e) return;
     int32_t len = qlen[e], dst = hdst[e];
     for (int i = lane; i < len; i += stride) cpins[dst + i] = qpins[b + i];

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void k_count_side1(int32_t count, const int
     int32_t e = sched_hedge<S>(count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
+    if (!thread_split<S>(d)) return;
     int32_t n1 = 0;
     for (int i = lane; i < d; i += stride) n1 += side[pins[b + i]];
     n1 = group_sum<S>(n1, lds);
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void k_extract_hedges(
     int32_t e = sched_hedge<S>(count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
+    if (!thread_split<S>(d)) return;
     int32_t s = hseg[e];
     int32_t cnt1 = n1[e];
     for (int sd = 0; sd < 2; sd++) {
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void k_cut(int32_t count, const int32_t *li
     if (S == SMALL) {
         for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
              e += (int64_t)gridDim.x * blockDim.x) {
-            if (off[e + 1] - off[e] > kSmallMax) continue;
+            if (!thread_split<SMALL>(off[e + 1] - off[e])) continue;
             int32_t lam = hedge_lambda<SMALL>((int32_t)e, 0, 1, off, pins, part, mask64, orl, lds);
             if (lam > 1) contrib += (int64_t)(hw ? hw[e] : 1) * (lam - 1);
         }
@@ -409,6 +409,7 @@ __global__ __launch_bounds__(kBlock) void k_cut(int32_t count, const int32_t *li
         int64_t wpb = blockDim.x >> 6;
         for (int64_t i = (int64_t)blockIdx.x * wpb + (threadIdx.x >> 6); i < count; i += (int64_t)gridDim.x * wpb) {
             int32_t e = list[i];
+            if (!thread_split<WAVE>(off[e + 1] - off[e])) continue;
             int32_t lam = hedge_lambda<WAVE>(e, threadIdx.x & 63, 64, off, pins, part, mask64, orl, lds);
             if ((threadIdx.x & 63) == 0 && lam > 1) contrib += (int64_t)(hw ? hw[e] : 1) * (lam - 1);
         }

@@ -3,9 +3,10 @@
 // A sweep over hyperedges runs as up to three launches: SMALL covers every
 // hyperedge of degree <= 8 with one thread each (the vast majority in
 // netlist and sparse-matrix hypergraphs), WAVE gives each listed hyperedge of
-// degree 9..256 a wavefront, BLOCK gives each listed larger hyperedge a
-// workgroup.  All per-pin updates are integer atomics (min/add), so results
-// do not depend on which schedule processed a hyperedge.
+// degree 9..256 a wavefront (sweeps split by thread_split below take those of
+// up to 32 pins one a thread as well), BLOCK gives each listed larger
+// hyperedge a workgroup.  All per-pin updates are integer atomics (min/add), so
+// results do not depend on which schedule processed a hyperedge.
 #pragma once
 #include "common.hpp"
 
@@ -13,9 +14,21 @@ namespace bp {
 
 enum Sched { SMALL = 0, WAVE = 1, BLOCK = 2 };
 
+// Sweeps whose per-hyperedge work is a plain loop over the pins take the
+// listed hyperedges of up to kHedgeThreadMax pins one a thread as well: a
+// wavefront on a 9..32-pin hyperedge leaves most lanes idle and adds a
+// reduction.  thread_split<S>(d): whether schedule S takes a hyperedge of d
+// pins in such a sweep (SMALL up to the limit, WAVE above it).
+constexpr int32_t kHedgeThreadMax = 32;
+template <int S> __device__ __forceinline__ bool thread_split(int32_t d)
+{
+    return S == SMALL ? d <= kHedgeThreadMax : (S == WAVE ? d > kHedgeThreadMax : true);
+}
+
 // Hyperedge handled by this thread's group in block vb of its schedule, or
 // -1.  lane/stride give the thread's position within the group.  For SMALL
-// the caller still has to skip hyperedges above kSmallMax.
+// the caller still has to skip hyperedges above kSmallMax (or, in a sweep
+// split by thread_split, above kHedgeThreadMax, which WAVE then skips).
 template <int S>
 __device__ __forceinline__ int32_t sched_hedge_at(int64_t vb, int32_t count, const int32_t *list, int &lane,
                                                   int &stride)

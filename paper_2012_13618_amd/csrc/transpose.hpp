@@ -112,7 +112,7 @@ __device__ __forceinline__ void ExpandPairsOp::run(int64_t vb, int32_t count, co
     int32_t e = sched_hedge_at<S>(vb, count, list, lane, stride);
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kSmallMax) return;
+    if (!thread_split<S>(d)) return;
     for (int i = lane; i < d; i += stride) {
         keys[b + i] = (uint32_t)pins[b + i];
         vals[b + i] = e;

@@ -53,11 +53,6 @@ __device__ __forceinline__ void cc_put(void *cc, int pk, int32_t e, int2 c)
 
 // ---- gains -------------------------------------------------------------------------
 
-// The hyperedge pass takes hyperedges of up to this many pins one a thread
-// (eight pins' loads in flight at a time); a wavefront per hyperedge would
-// leave most of its lanes idle on them and add a reduction.
-constexpr int32_t kHedgeThreadMax = 32;
-
 template <int S>
 __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int stride, const int32_t *off,
                                                   const int32_t *pins, const int32_t *hw,
@@ -65,8 +60,7 @@ __device__ __forceinline__ void hedge_contrib_one(int32_t e, int lane, int strid
                                                   const uint8_t *side, void *cc, int pk, int32_t *lds)
 {
     int32_t b = off[e], d = off[e + 1] - b;
-    if (S == SMALL && d > kHedgeThreadMax) return;
-    if (S == WAVE && d <= kHedgeThreadMax) return;  // taken one a thread
+    if (!thread_split<S>(d)) return;  // (eight pins' loads in flight at a time below)
     if (!gmask[hseg[e]]) return;
     int32_t n1 = 0;
     if (S == SMALL) {
@@ -236,6 +230,43 @@ __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, c
     return nc;
 }
 
+// The same for 9..kHedgeThreadMax pins by one thread, eight pins' loads in
+// flight at a time; the pins are read again (from cache) for the deltas, unless
+// the contribution did not change, when no pin's gain does.
+__device__ __forceinline__ int2 recount_thread(int32_t e, int32_t b, int32_t d, const int32_t *pins,
+                                               const int32_t *hw, const uint8_t *side, int2 oc,
+                                               const int32_t *bigslot, int32_t *slot, int32_t *gain)
+{
+    int32_t n1 = 0;
+    for (int32_t i0 = 0; i0 < d; i0 += 8) {
+        int32_t u[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) u[j] = pins[b + min(i0 + j, d - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+            int32_t x = side[u[j]];
+            if (i0 + j < d) n1 += x;
+        }
+    }
+    int2 nc = hedge_contrib_value(hw[e], d, n1);
+    if (nc.x == oc.x && nc.y == oc.y) return nc;
+    for (int32_t i0 = 0; i0 < d; i0 += 8) {
+        int32_t u[8];
+        uint32_t sn[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) u[j] = pins[b + min(i0 + j, d - 1)];
+#pragma unroll
+        for (int j = 0; j < 8; j++) sn[j] = side[u[j]];
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            if (i0 + j < d) {
+                int32_t delta = sn[j] ? nc.y - oc.y : nc.x - oc.x;
+                if (delta) add_gain(u[j], delta, bigslot, slot, gain);
+            }
+    }
+    return nc;
+}
+
 // Marked hyperedges, found by sweeping the bitmap: recount the sides, replace
 // the contribution, and add the change to every pin's gain, as if no pin had
 // moved (the marking launch has already settled what the moved nodes are
@@ -246,7 +277,7 @@ __device__ __forceinline__ int2 recount_small(int32_t e, int32_t b, int32_t d, c
 // chunk c to workgroup c mod G: a moved node's hyperedges crowd into a few
 // chunks (ids follow locality), and consecutive chunks go to different
 // workgroups.  Each step a workgroup takes 8 of its chunks; one wavefront
-// lists their marked hyperedges in LDS (popcount scan), then degree <= 8 go
+// lists their marked hyperedges in LDS (popcount scan), then degree <= 32 go
 // one per thread, up to 512 one per wavefront, larger ones to the whole
 // workgroup.  When abytes is set (profiling), adds the algorithmic bytes it
 // moved: 4 per bitmap word, per hyperedge 12 (offsets, weight) plus the
@@ -300,6 +331,8 @@ __global__ __launch_bounds__(kBlock) void k_gain_update(int64_t nwords, uint32_t
             if (abytes) atomicAdd(&npins, d);
             if (d <= kSmallMax)
                 cc_put(cc, pk, e, recount_small(e, b, d, pins, hw, side, cc_get(cc, pk, e), bigslot, slot, gain));
+            else if (d <= kHedgeThreadMax)
+                cc_put(cc, pk, e, recount_thread(e, b, d, pins, hw, side, cc_get(cc, pk, e), bigslot, slot, gain));
             else if (d <= kUpdWaveMax) bigq[atomicAdd(&nbq, 1)] = e;
             else bigq[kUpdQueue - 1 - atomicAdd(&nhq, 1)] = e;  // front and back never meet
         }
