@@ -186,9 +186,52 @@ __device__ __forceinline__ uint64_t fp_term(int32_t q, uint64_t salt)
     return mix64((uint64_t)(uint32_t)q + salt);
 }
 
+// Parents of a hyperedge of up to N pins (N a power of two) sorted by one thread
+// in registers by a bitonic network (padding INT32_MAX sorts last), then the
+// distinct ones written in order with their fingerprint.
+template <int N>
+__device__ __forceinline__ void qbuild_regs(int64_t e, int32_t b, int32_t d, const int32_t *pins,
+                                            const int32_t *parent, int32_t *qpins, int32_t *qlen, uint64_t *fp)
+{
+    int32_t q[N];
+#pragma unroll
+    for (int i = 0; i < N; i++) q[i] = i < d ? parent[pins[b + i]] : INT32_MAX;
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < N; i++) {
+                int p = i ^ j;
+                if (p > i) {
+                    bool up = (i & k) == 0;
+                    int32_t x = q[i], y = q[p];
+                    bool sw = (x > y) == up;
+                    q[i] = sw ? y : x;
+                    q[p] = sw ? x : y;
+                }
+            }
+    int32_t len = 0;
+    uint64_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < N; i++) {
+        bool first = i < d && (i == 0 || q[i] != q[i - 1]);
+        if (first) {
+            qpins[b + len] = q[i];
+            sum += fp_term(q[i], 0);
+            len++;
+        }
+    }
+    qlen[e] = len >= 2 ? len : 0;
+    fp[e] = fp_finish(sum, len);
+}
+
 // Third loop of Algorithm 2 for hyperedges of degree <= 8: parents sorted in
-// registers by an odd-even transposition network.
-// block vb of the one-thread-per-hyperedge sweep (degree <= kSmallMax)
+// registers by an odd-even transposition network; 9..16 pins by the bitonic
+// network above (a wavefront's shuffles would cost more per hyperedge; a
+// 32-key network would take registers the common small case needs for
+// occupancy).  Block vb of the one-thread-per-hyperedge sweep.
+constexpr int32_t kQbuildThreadMax = 16;
 __device__ __forceinline__ void qbuild_small(int64_t vb, int32_t E, const int32_t *off, const int32_t *pins,
                                              const int32_t *hseg, const uint8_t *sact, const int32_t *parent,
                                              int32_t *qpins, int32_t *qlen, uint64_t *fp)
@@ -196,9 +239,13 @@ __device__ __forceinline__ void qbuild_small(int64_t vb, int32_t E, const int32_
     int64_t e = vb * blockDim.x + threadIdx.x;
     if (e >= E) return;
     int32_t b = off[e], d = off[e + 1] - b;
-    if (d > kSmallMax) return;
+    if (d > kQbuildThreadMax) return;
     if (!sact[hseg[e]]) {
         qlen[e] = 0;
+        return;
+    }
+    if (d > kSmallMax) {
+        qbuild_regs<kQbuildThreadMax>(e, b, d, pins, parent, qpins, qlen, fp);
         return;
     }
     int32_t q[kSmallMax];
@@ -297,7 +344,7 @@ __device__ __forceinline__ int32_t wave_unique_emit(const int32_t (&x)[R], int32
     return len;
 }
 
-// Degree 9..256: one wavefront per hyperedge, parents sorted in registers
+// Degree 17..256: one wavefront per hyperedge, parents sorted in registers
 // (block vb of that sweep).
 __device__ __forceinline__ void qbuild_wave(int64_t vb, int32_t count, const int32_t *list, const int32_t *off,
                                             const int32_t *pins, const int32_t *hseg, const uint8_t *sact,
@@ -308,6 +355,7 @@ __device__ __forceinline__ void qbuild_wave(int64_t vb, int32_t count, const int
     if (w >= count) return;
     int32_t e = list[w];
     int32_t b = off[e], d = off[e + 1] - b;
+    if (d <= kQbuildThreadMax) return;  // the one-thread sweep took it
     if (!sact[hseg[e]]) {
         if (lane == 0) qlen[e] = 0;
         return;
