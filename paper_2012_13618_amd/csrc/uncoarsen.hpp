@@ -1031,16 +1031,25 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     __shared__ uint64_t a[kChunkMax * kChunkKeys];
     __shared__ uint64_t out[kChunkKeys];
     __shared__ int64_t lds64[16];
-    __shared__ int32_t cnt[kChunkMax], p1s, fits;
+    __shared__ int32_t cnt_scan[16];
+    __shared__ int32_t cnt[kChunkMax], p1s, fits, logbase;
     __shared__ int64_t movedw;
     int32_t n = nbase[s + 1] - nbase[s];
     int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
     const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
-    // every slot of the segment's lists (past a list's count: unused), with the counts
+    // every slot of the segment's lists (past a list's count: unused), with the
+    // counts; the segment's balance state is loaded with them
     const uint64_t *src = ca.cand + (int64_t)s * kChunkMax * kChunkKeys;
     for (int32_t f = tid; f < nslot; f += 1024) a[f] = src[f];
     if (tid < kChunkMax) cnt[tid] = tid < ng ? ca.ccnt[s * kChunkMax + tid] : 0;
-    if (tid == 0) movedw = 0;
+    const int h = (bf.mode[s] & kList1) ? 1 : 0;
+    const int64_t nd = bf.need[s], rm = bf.room[s];
+    int64_t bm0 = 0, bm1 = 0;
+    if (tid == 0) {
+        bm0 = bf.bal_moved[2 * s];
+        bm1 = bf.bal_moved[2 * s + 1];
+        movedw = 0;
+    }
     __syncthreads();
     int32_t tot = 0;
     for (int q = 0; q < ng; q++) tot += cnt[q];
@@ -1071,15 +1080,33 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     __syncthreads();
     // the shortest prefix reaching the excess, cut to what fits the room
     // (weights are non-negative: prefix weights ascend, so each wavefront's
-    // first reaching lane and its fitting lanes come from two ballots); the
-    // chosen nodes' weights are gathered once, one a thread, after the ranking
-    int h = (bf.mode[s] & kList1) ? 1 : 0;
-    int64_t nd = bf.need[s], rm = bf.room[s];
-    int64_t w = tid < take ? (int64_t)bf.nw[(uint32_t)(out[tid] & 0xffffffffu)] : 0;
+    // first reaching lane and its fitting lanes come from two ballots).  One
+    // chosen node a thread: its weight and, for the move log, its incidence
+    // range are gathered together after the ranking, and the log's chunk
+    // counts are scanned with the weights (the logged nodes are a prefix of
+    // the chosen ones, so their offsets are the same prefix sums)
+    const bool logm = bf.ml.cnode != nullptr;
+    int32_t v = 0, nb = 0, nc = 0;
+    int64_t w = 0;
+    if (tid < take) {
+        v = (int32_t)(uint32_t)(out[tid] & 0xffffffffu);
+        w = bf.nw[v];
+        if (logm) {
+            nb = bf.ml.noff[v];
+            nc = (int32_t)ceil_div(bf.ml.noff[v + 1] - nb, kLogChunk);
+        }
+    }
     int64_t incl = wave_incl_scan(w);
-    if ((tid & 63) == 63) lds64[tid >> 6] = incl;
+    int32_t cincl = wave_incl_scan(nc);
+    if ((tid & 63) == 63) {
+        lds64[tid >> 6] = incl;
+        cnt_scan[tid >> 6] = cincl;
+    }
     __syncthreads();
-    for (int q = 0; q < (tid >> 6); q++) incl += lds64[q];
+    for (int q = 0; q < (tid >> 6); q++) {
+        incl += lds64[q];
+        cincl += cnt_scan[q];
+    }
     unsigned long long reach = __ballot(tid < take && incl >= nd), fit = __ballot(tid < take && incl <= rm);
     if ((tid & 63) == 0) {
         if (reach) atomicMin(&p1s, (tid & ~63) + __ffsll((long long)reach));
@@ -1087,10 +1114,19 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     }
     __syncthreads();
     int32_t p = min(p1s, fits);
-    if (tid < p) bf.side[(uint32_t)(out[tid] & 0xffffffffu)] = (uint8_t)(1 - h);
-    if (p > 0 && tid == p - 1) movedw = incl;
-    if (bf.ml.cnode) log_moves(p, out, bf.ml, lds64);
+    if (tid < p) bf.side[v] = (uint8_t)(1 - h);
+    if (p > 0 && tid == p - 1) {
+        movedw = incl;
+        if (logm) logbase = cincl ? atomicAdd(&bf.ml.count[0], cincl) : 0;
+    }
     __syncthreads();
+    if (logm && tid < p) {
+        int32_t o = logbase + cincl - nc;
+        for (int32_t j = 0; j < nc; j++) {
+            bf.ml.cnode[o + j] = v;
+            bf.ml.cbeg[o + j] = nb + j * kLogChunk;
+        }
+    }
     if (tid == 0) {
         int64_t moved = movedw;
         if (p == 0) {
@@ -1099,7 +1135,7 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
         } else {
             atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
             atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
-            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            int64_t mw = bm0 + moved, mr = bm1 + 1;
             bf.bal_moved[2 * s] = mw;
             bf.bal_moved[2 * s + 1] = mr;
             int64_t rest = nd - moved;
