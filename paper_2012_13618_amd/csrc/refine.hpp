@@ -178,71 +178,82 @@ __device__ __forceinline__ void bal_take_prefix(int32_t s, const uint64_t *a, in
     }
 }
 
-// log_moves by one wavefront.
-__device__ __forceinline__ void log_moves_wave(int32_t p, const uint64_t *a, const MoveLog &ml)
+// The balance prefix (Algorithm 5) over the first take keys of a (ascending
+// order keys, take <= the workgroup's threads), by the whole workgroup: the
+// shortest prefix reaching the excess, cut to what fits the room, moved and
+// logged.  h, nd, rm: the segment's over-weight side, excess and room; bm0,
+// bm1 (thread 0): its moved weight and rounds so far - loaded by the caller
+// ahead of its own work.
+__device__ __forceinline__ void bal_finish_block(int32_t s, const uint64_t *a, int32_t take, const BalFinish &bf,
+                                                 int h, int64_t nd, int64_t rm, int64_t bm0, int64_t bm1)
 {
-    int lane = threadIdx.x & 63;
-    for (int32_t base = 0; base < p; base += 64) {
-        int32_t i = base + lane;
-        int32_t v = 0, b = 0, c = 0;
-        if (i < p) {
-            v = (int32_t)(uint32_t)(a[i] & 0xffffffffu);
-            b = ml.noff[v];
-            c = (int32_t)ceil_div(ml.noff[v + 1] - b, kLogChunk);
-        }
-        int32_t incl = wave_incl_scan(c);
-        int32_t tot = __shfl(incl, 63, 64);
-        int32_t o = 0;
-        if (lane == 0 && tot) o = atomicAdd(&ml.count[0], tot);
-        o = __shfl(o, 0, 64) + incl - c;
-        for (int32_t j = 0; j < c; j++) {
-            ml.cnode[o + j] = v;
-            ml.cbeg[o + j] = b + j * kLogChunk;
+    __shared__ int64_t lds64[16];
+    __shared__ int32_t cnt_scan[16], p1s, fits, logbase;
+    __shared__ int64_t movedw;
+    const int32_t tid = threadIdx.x;
+    if (tid == 0) {
+        p1s = take;
+        fits = 0;
+        movedw = 0;
+    }
+    // the shortest prefix reaching the excess, cut to what fits the room
+    // (weights are non-negative: prefix weights ascend, so each wavefront's
+    // first reaching lane and its fitting lanes come from two ballots).  One
+    // chosen node a thread: its weight and, for the move log, its incidence
+    // range are gathered together after the ranking, and the log's chunk
+    // counts are scanned with the weights (the logged nodes are a prefix of
+    // the chosen ones, so their offsets are the same prefix sums)
+    const bool logm = bf.ml.cnode != nullptr;
+    int32_t v = 0, nb = 0, nc = 0;
+    int64_t w = 0;
+    if (tid < take) {
+        v = (int32_t)(uint32_t)(a[tid] & 0xffffffffu);
+        w = bf.nw[v];
+        if (logm) {
+            nb = bf.ml.noff[v];
+            nc = (int32_t)ceil_div(bf.ml.noff[v + 1] - nb, kLogChunk);
         }
     }
-}
-
-// bal_take_prefix by one wavefront (no workgroup barriers).  Node weights
-// are non-negative, so the prefix weights ascend: the shortest prefix
-// reaching the excess ends at the first chunk position that reaches it, and
-// the longest prefix within the room is min(that length, the number of
-// positions whose prefix weight fits).
-__device__ __forceinline__ void bal_take_prefix_wave(int32_t s, const uint64_t *a, int32_t cnt, const BalFinish &bf)
-{
-    int lane = threadIdx.x & 63;
-    int h = (bf.mode[s] & kList1) ? 1 : 0;
-    int64_t nd = bf.need[s], rm = bf.room[s];
-    int32_t p1 = cnt, fit = 0;
-    int64_t carry = 0;
-    for (int32_t base = 0; base < cnt; base += 64) {
-        int32_t i = base + lane;
-        int64_t w = i < cnt ? (int64_t)bf.nw[(uint32_t)(a[i] & 0xffffffffu)] : 0;
-        int64_t incl = wave_incl_scan(w) + carry;
-        unsigned long long hit = __ballot(i < cnt && incl >= nd);
-        fit += __popcll(__ballot(i < cnt && incl <= rm));
-        if (hit) {
-            p1 = base + __ffsll((long long)hit);
-            break;
+    int64_t incl = wave_incl_scan(w);
+    int32_t cincl = wave_incl_scan(nc);
+    if ((tid & 63) == 63) {
+        lds64[tid >> 6] = incl;
+        cnt_scan[tid >> 6] = cincl;
+    }
+    __syncthreads();
+    for (int q = 0; q < (tid >> 6); q++) {
+        incl += lds64[q];
+        cincl += cnt_scan[q];
+    }
+    unsigned long long reach = __ballot(tid < take && incl >= nd), fit = __ballot(tid < take && incl <= rm);
+    if ((tid & 63) == 0) {
+        if (reach) atomicMin(&p1s, (tid & ~63) + __ffsll((long long)reach));
+        if (fit) atomicAdd(&fits, __popcll(fit));
+    }
+    __syncthreads();
+    int32_t p = min(p1s, fits);
+    if (tid < p) bf.side[v] = (uint8_t)(1 - h);
+    if (p > 0 && tid == p - 1) {
+        movedw = incl;
+        if (logm) logbase = cincl ? atomicAdd(&bf.ml.count[0], cincl) : 0;
+    }
+    __syncthreads();
+    if (logm && tid < p) {
+        int32_t o = logbase + cincl - nc;
+        for (int32_t j = 0; j < nc; j++) {
+            bf.ml.cnode[o + j] = v;
+            bf.ml.cbeg[o + j] = nb + j * kLogChunk;
         }
-        carry = __shfl(incl, 63, 64);
     }
-    int32_t p = fit < p1 ? fit : p1;
-    int64_t moved = 0;
-    for (int32_t i = lane; i < p; i += 64) {
-        uint32_t v = (uint32_t)(a[i] & 0xffffffffu);
-        bf.side[v] = (uint8_t)(1 - h);
-        moved += bf.nw[v];
-    }
-    moved = wave_sum(moved);
-    if (bf.ml.cnode) log_moves_wave(p, a, bf.ml);
-    if (lane == 0) {
+    if (tid == 0) {
+        int64_t moved = movedw;
         if (p == 0) {
             bf.stuck[s] = 1;
             bf.done[s] = 1;
         } else {
             atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
             atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
-            int64_t mw = bf.bal_moved[2 * s] + moved, mr = bf.bal_moved[2 * s + 1] + 1;
+            int64_t mw = bm0 + moved, mr = bm1 + 1;
             bf.bal_moved[2 * s] = mw;
             bf.bal_moved[2 * s + 1] = mr;
             int64_t rest = nd - moved;
@@ -268,8 +279,17 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
     extern __shared__ uint64_t keys_lds[];
     __shared__ int64_t lds64[16];
     int32_t s = blockIdx.x;
-    if (!bf.mode[s]) return;
+    const uint8_t md = bf.mode[s];
+    if (!md) return;
     int32_t cnt = ccount[s];
+    // the segment's balance state, loaded ahead of the candidates' ordering
+    const int h = (md & kList1) ? 1 : 0;
+    const int64_t nd = bf.need[s], rm = bf.room[s];
+    int64_t bm0 = 0, bm1 = 0;
+    if (threadIdx.x == 0) {
+        bm0 = bf.bal_moved[2 * s];
+        bm1 = bf.bal_moved[2 * s + 1];
+    }
     // a selection that stopped at a whole bin gathered more nodes than the
     // list chose: the chosen ones are the first rsel in order
     int32_t take = cnt;
@@ -282,7 +302,7 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
         for (int i = threadIdx.x; i < cnt; i += blockDim.x) keys_lds[i] = src[i];
         __syncthreads();
         block_rank_sort(keys_lds, keys_lds + cnt, cnt);
-        if (threadIdx.x < 64) bal_take_prefix_wave(s, keys_lds + cnt, take, bf);
+        bal_finish_block(s, keys_lds + cnt, take, bf, h, nd, rm, bm0, bm1);
         return;
     }
     int n2 = next_pow2(cnt > 0 ? cnt : 1);
@@ -291,7 +311,9 @@ __global__ __launch_bounds__(1024) void k_bal_finish(int32_t S, const int32_t *c
         a[i] = i < cnt ? src[i] : kNoKey;
     __syncthreads();
     block_bitonic_sort(a, n2);
-    bal_take_prefix(s, a, take, bf, lds64);
+    __syncthreads();
+    if (take <= (int32_t)blockDim.x) bal_finish_block(s, a, take, bf, h, nd, rm, bm0, bm1);
+    else bal_take_prefix(s, a, take, bf, lds64);
 }
 
 }  // namespace bp

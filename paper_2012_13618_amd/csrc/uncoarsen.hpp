@@ -1022,18 +1022,15 @@ struct ChunkArgs {
 // ascending lists is ranked among all of them (its index in its
 // own list plus, by binary search, the smaller keys of every other list); the
 // first min(total, m) in order are the segment's chosen nodes.  Then the
-// balance prefix (Algorithm 5) over them: one scan of their weights, one
-// chosen node a thread, as they fit the workgroup.
+// balance prefix over them (bal_finish_block: one chosen node a thread, as
+// they fit the workgroup).
 __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, const int32_t *m, ChunkArgs ca,
                                               BalFinish bf)
 {
     static_assert(kChunkKeys <= 1024, "the chosen nodes fit the workgroup");
     __shared__ uint64_t a[kChunkMax * kChunkKeys];
     __shared__ uint64_t out[kChunkKeys];
-    __shared__ int64_t lds64[16];
-    __shared__ int32_t cnt_scan[16];
-    __shared__ int32_t cnt[kChunkMax], p1s, fits, logbase;
-    __shared__ int64_t movedw;
+    __shared__ int32_t cnt[kChunkMax];
     int32_t n = nbase[s + 1] - nbase[s];
     int ng = (int)((n + kChunkNodes - 1) / kChunkNodes);  // <= kChunkMax, checked by the caller
     const int32_t tid = threadIdx.x, nslot = ng * kChunkKeys;
@@ -1048,7 +1045,6 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     if (tid == 0) {
         bm0 = bf.bal_moved[2 * s];
         bm1 = bf.bal_moved[2 * s + 1];
-        movedw = 0;
     }
     __syncthreads();
     int32_t tot = 0;
@@ -1073,78 +1069,8 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
         }
         if (rank < take) out[rank] = x;
     }
-    if (tid == 0) {
-        p1s = take;
-        fits = 0;
-    }
     __syncthreads();
-    // the shortest prefix reaching the excess, cut to what fits the room
-    // (weights are non-negative: prefix weights ascend, so each wavefront's
-    // first reaching lane and its fitting lanes come from two ballots).  One
-    // chosen node a thread: its weight and, for the move log, its incidence
-    // range are gathered together after the ranking, and the log's chunk
-    // counts are scanned with the weights (the logged nodes are a prefix of
-    // the chosen ones, so their offsets are the same prefix sums)
-    const bool logm = bf.ml.cnode != nullptr;
-    int32_t v = 0, nb = 0, nc = 0;
-    int64_t w = 0;
-    if (tid < take) {
-        v = (int32_t)(uint32_t)(out[tid] & 0xffffffffu);
-        w = bf.nw[v];
-        if (logm) {
-            nb = bf.ml.noff[v];
-            nc = (int32_t)ceil_div(bf.ml.noff[v + 1] - nb, kLogChunk);
-        }
-    }
-    int64_t incl = wave_incl_scan(w);
-    int32_t cincl = wave_incl_scan(nc);
-    if ((tid & 63) == 63) {
-        lds64[tid >> 6] = incl;
-        cnt_scan[tid >> 6] = cincl;
-    }
-    __syncthreads();
-    for (int q = 0; q < (tid >> 6); q++) {
-        incl += lds64[q];
-        cincl += cnt_scan[q];
-    }
-    unsigned long long reach = __ballot(tid < take && incl >= nd), fit = __ballot(tid < take && incl <= rm);
-    if ((tid & 63) == 0) {
-        if (reach) atomicMin(&p1s, (tid & ~63) + __ffsll((long long)reach));
-        if (fit) atomicAdd(&fits, __popcll(fit));
-    }
-    __syncthreads();
-    int32_t p = min(p1s, fits);
-    if (tid < p) bf.side[v] = (uint8_t)(1 - h);
-    if (p > 0 && tid == p - 1) {
-        movedw = incl;
-        if (logm) logbase = cincl ? atomicAdd(&bf.ml.count[0], cincl) : 0;
-    }
-    __syncthreads();
-    if (logm && tid < p) {
-        int32_t o = logbase + cincl - nc;
-        for (int32_t j = 0; j < nc; j++) {
-            bf.ml.cnode[o + j] = v;
-            bf.ml.cbeg[o + j] = nb + j * kLogChunk;
-        }
-    }
-    if (tid == 0) {
-        int64_t moved = movedw;
-        if (p == 0) {
-            bf.stuck[s] = 1;
-            bf.done[s] = 1;
-        } else {
-            atomicAdd(&bf.segw[2 * s + h], (unsigned long long)(-moved));
-            atomicAdd(&bf.segw[2 * s + 1 - h], (unsigned long long)moved);
-            int64_t mw = bm0 + moved, mr = bm1 + 1;
-            bf.bal_moved[2 * s] = mw;
-            bf.bal_moved[2 * s + 1] = mr;
-            int64_t rest = nd - moved;
-            if (rest > 0) {
-                int64_t est = mw > 0 ? (rest * mr + mw - 1) / mw : 1;
-                atomicMax(&bf.go[3], (int32_t)(est < (1 << 20) ? est : (1 << 20)));
-            }
-        }
-    }
+    bal_finish_block(s, out, take, bf, h, nd, rm, bm0, bm1);
 }
 
 // One workgroup per segment of at most seg_select_max<KIND, TH>() nodes: each list's
@@ -1181,6 +1107,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     const int32_t gv = go ? *go : 1;
     int32_t s, a0, n;
     uint8_t md;
+    int64_t bnd = 0, brm = 0, bm0 = 0, bm1 = 0;  // balance (one workgroup): the segment's state, loaded early
     if (CH) {
         int32_t ci = blockIdx.x;
         int32_t cc = ca.count[0];
@@ -1194,6 +1121,12 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         a0 = sv.nbase[s];
         int32_t a1 = sv.nbase[s + 1];
         md = sv.mode[s];
+        if (KIND == 1) {
+            bnd = bf.need[s];
+            brm = bf.room[s];
+            bm0 = bf.bal_moved[2 * s];
+            bm1 = bf.bal_moved[2 * s + 1];
+        }
         if (gv == 0) return;
         n = a1 - a0;
     }
@@ -1418,7 +1351,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         if (last) bal_merge_seg(s, sv.nbase, sv.m, ca, bf);
         return;
     }
-    if (threadIdx.x < 64) bal_take_prefix_wave(s, sorted, cnt, bf);
+    bal_finish_block(s, sorted, cnt, bf, h, bnd, brm, bm0, bm1);
 }
 
 // The chunk table of a level: segment s gets ceil(n_s / kChunkNodes)
