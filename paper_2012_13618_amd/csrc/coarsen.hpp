@@ -426,6 +426,54 @@ __device__ void block_unique_emit(int32_t *a, int n2, int32_t d, int32_t b, int3
     *sum_out = sum;
 }
 
+// Big hyperedges (the listed ones above 256 pins), in two launches: up to
+// kQWaveMax pins a wavefront each, the parents sorted in registers (8 or 16 a
+// lane), four at once in a workgroup and without barriers
+// (k_qbuild_big_waves, workgroup b takes list entries 4b .. 4b+3); the larger
+// ones (up to kBigMax) a workgroup each, sorted in LDS (k_qbuild_block).
+constexpr int32_t kQWaveMax = 1024;
+
+template <int R>
+__device__ __forceinline__ void qbuild_wave_regs(int32_t e, int32_t b, int32_t d, const int32_t *pins,
+                                                 const int32_t *parent, int32_t *qpins, int32_t *qlen, uint64_t *fp)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t x[R];
+#pragma unroll
+    for (int t = 0; t < R; t++) {
+        int i = lane * R + t;
+        x[t] = i < d ? parent[pins[b + i]] : INT32_MAX;
+    }
+    wave_sort_regs<R>(x);
+    uint64_t sum;
+    int32_t len = wave_unique_emit<R>(x, d, qpins + b, &sum);
+    if (lane == 0) {
+        qlen[e] = len >= 2 ? len : 0;
+        fp[e] = fp_finish(sum, len);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_qbuild_big_waves(int32_t count, const int32_t *list,
+                                                             const int32_t *off, const int32_t *pins,
+                                                             const int32_t *hseg, const uint8_t *sact,
+                                                             const int32_t *parent, int32_t *qpins,
+                                                             int32_t *qlen, uint64_t *fp)
+{
+    const int lane = threadIdx.x & 63;
+    int64_t i = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    if (i >= count) return;
+    int32_t e = list[i];
+    int32_t b = off[e], d = off[e + 1] - b;
+    if (d > kQWaveMax) return;  // k_qbuild_block's
+    if (!sact[hseg[e]]) {
+        if (lane == 0) qlen[e] = 0;
+    } else if (d <= 512) {
+        qbuild_wave_regs<8>(e, b, d, pins, parent, qpins, qlen, fp);
+    } else {
+        qbuild_wave_regs<16>(e, b, d, pins, parent, qpins, qlen, fp);
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_qbuild_block(int32_t count, const int32_t *list,
                                                          const int32_t *off, const int32_t *pins,
                                                          const int32_t *hseg,
@@ -436,7 +484,7 @@ __global__ __launch_bounds__(kBlock) void k_qbuild_block(int32_t count, const in
     extern __shared__ int32_t dyn[];
     int32_t e = list[blockIdx.x];
     int32_t b = off[e], d = off[e + 1] - b;
-    if (d > kBigMax) return;  // handled by k_qbuild_huge
+    if (d <= kQWaveMax || d > kBigMax) return;  // a wavefront's, or k_qbuild_huge's
     if (!sact[hseg[e]]) {
         if (threadIdx.x == 0) qlen[e] = 0;
         return;

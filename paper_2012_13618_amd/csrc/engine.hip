@@ -150,6 +150,9 @@ void coarsen_level(Ctx &cx, Level &f, Segs &sg, uint8_t *&sact, uint8_t *&sact_n
     launch(lc, "qbuild", 4.0 * E + 12.0 * P, k_qbuild_sw, ceil_div(E, kBlock) + ceil_div(f.nmid, kBlock / 64),
            kBlock, 0, E, f.nmid, (const int32_t *)f.lmid, (const int32_t *)f.off, (const int32_t *)f.pins,
            (const int32_t *)f.hseg, (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
+    launch(lc, "qbuild_block", 0.0, k_qbuild_big_waves, ceil_div(f.nbig, kBlock / 64), kBlock, 0, f.nbig,
+           (const int32_t *)f.lbig, (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
+           (const uint8_t *)sact, (const int32_t *)f.parent, b.qpins, b.qlen, b.fp);
     launch(lc, "qbuild_block", 0.0, k_qbuild_block, sched_grid<BLOCK>(f.nbig), kBlock,
            (size_t)kBigMax * sizeof(int32_t), f.nbig, (const int32_t *)f.lbig,
            (const int32_t *)f.off, (const int32_t *)f.pins, (const int32_t *)f.hseg,
