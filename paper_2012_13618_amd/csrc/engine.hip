@@ -687,7 +687,7 @@ static int64_t refine_level(Ctx &cx, Level &L, Segs &sg, int32_t j, int32_t *gai
         if (!sg.chunk_cand || nct > sg.chunk_tab_n)
             throw Error(BP_ERR_DEVICE, "chunked selection buffers missing");
         int32_t *tseg = sg.chunk_tab, *tbeg = sg.chunk_tab + sg.chunk_tab_n, *tcnt = sg.chunk_tab + 2 * sg.chunk_tab_n;
-        ca = ChunkArgs{tseg, tbeg, tcnt, sg.chunk_cand, sg.chunk_ccnt};
+        ca = ChunkArgs{tseg, tbeg, tcnt, L.N, sg.chunk_cand, sg.chunk_ccnt};
         launch(lc, "balance", 0.0, k_chunk_table, 1, 1024, 0, L.S, (const int32_t *)L.nbase, tseg, tbeg, tcnt);
     }
     int64_t lg = std::max<int64_t>(1, std::min<int64_t>(ceil_div((int64_t)L.P / kLogChunk + L.N, kBlock / 64), 1024));

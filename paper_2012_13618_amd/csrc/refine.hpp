@@ -178,14 +178,22 @@ __device__ __forceinline__ void bal_take_prefix(int32_t s, const uint64_t *a, in
     }
 }
 
+// The chosen nodes' weights and incidence ranges (noff[v], noff[v + 1]) in
+// their order, gathered by the caller while it ranked them; null: gathered
+// by the finish.
+struct BalPre {
+    const int32_t *w = nullptr, *nb = nullptr, *ne = nullptr;
+};
+
 // The balance prefix (Algorithm 5) over the first take keys of a (ascending
 // order keys, take <= the workgroup's threads), by the whole workgroup: the
 // shortest prefix reaching the excess, cut to what fits the room, moved and
 // logged.  h, nd, rm: the segment's over-weight side, excess and room; bm0,
 // bm1 (thread 0): its moved weight and rounds so far - loaded by the caller
-// ahead of its own work.
+// ahead of its own work, as pre may be.
 __device__ __forceinline__ void bal_finish_block(int32_t s, const uint64_t *a, int32_t take, const BalFinish &bf,
-                                                 int h, int64_t nd, int64_t rm, int64_t bm0, int64_t bm1)
+                                                 int h, int64_t nd, int64_t rm, int64_t bm0, int64_t bm1,
+                                                 BalPre pre = BalPre{})
 {
     __shared__ int64_t lds64[16];
     __shared__ int32_t cnt_scan[16], p1s, fits, logbase;
@@ -208,10 +216,18 @@ __device__ __forceinline__ void bal_finish_block(int32_t s, const uint64_t *a, i
     int64_t w = 0;
     if (tid < take) {
         v = (int32_t)(uint32_t)(a[tid] & 0xffffffffu);
-        w = bf.nw[v];
-        if (logm) {
-            nb = bf.ml.noff[v];
-            nc = (int32_t)ceil_div(bf.ml.noff[v + 1] - nb, kLogChunk);
+        if (pre.w) {
+            w = pre.w[tid];
+            if (logm) {
+                nb = pre.nb[tid];
+                nc = (int32_t)ceil_div(pre.ne[tid] - nb, kLogChunk);
+            }
+        } else {
+            w = bf.nw[v];
+            if (logm) {
+                nb = bf.ml.noff[v];
+                nc = (int32_t)ceil_div(bf.ml.noff[v + 1] - nb, kLogChunk);
+            }
         }
     }
     int64_t incl = wave_incl_scan(w);

@@ -125,12 +125,20 @@ template <typename K> __device__ void block_bitonic_sort(K *a, int n)
 // network's log^2 ones; O(cnt^2 / threads) comparisons, for short lists.
 template <typename K> __device__ __forceinline__ void block_rank_sort(const K *in, K *out, int cnt)
 {
-    for (int i = threadIdx.x; i < cnt; i += blockDim.x) {
-        K x = in[i];
+    // tpc adjacent lanes per key (a power of two up to 16, as the workgroup
+    // allows), each counting every tpc-th key; cnt is the same in every thread
+    int tpc = 1;
+    while (tpc < 16 && cnt * 2 * tpc <= (int)blockDim.x) tpc <<= 1;
+    for (int base = 0; base < cnt * tpc; base += blockDim.x) {
+        int t = base + (int)threadIdx.x, i = t / tpc, part = t & (tpc - 1);
+        K x = in[i < cnt ? i : 0];
         int r = 0;
+        if (i < cnt) {
 #pragma unroll 8
-        for (int j = 0; j < cnt; j++) r += in[j] < x;
-        out[r] = x;
+            for (int j = part; j < cnt; j += tpc) r += in[j] < x;
+        }
+        for (int o = 1; o < tpc; o <<= 1) r += __shfl_xor(r, o, 64);
+        if (i < cnt && part == 0) out[r] = x;
     }
     __syncthreads();
 }

@@ -1013,6 +1013,7 @@ constexpr int kChunkMax = 16;      // chunks per segment: segments up to 262144 
 constexpr int kChunkKeys = 512;    // per chunk: ceil(sqrt 262144) = 512 at most
 struct ChunkArgs {
     const int32_t *seg, *beg, *count;  // chunk table: segment, first node; count[0] chunks
+    int32_t N;                         // the level's nodes (bounds the chunk's loads)
     uint64_t *cand;                    // [S][kChunkMax][kChunkKeys]: each chunk's best, ascending
     int32_t *ccnt;                     // [S][kChunkMax]: how many
 };
@@ -1050,11 +1051,15 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
     int32_t tot = 0;
     for (int q = 0; q < ng; q++) tot += cnt[q];
     int32_t take = min(tot, m[s]);
+    // list-major slots (a wavefront's keys are neighbours in one list, so
+    // their searches read the same LDS words), the index range rotated by a
+    // wavefront per pass so that no thread ranks the heads of several lists,
+    // the keys with the most lists to search
     for (int32_t f = tid; f < nslot; f += 1024) {
         int q = f / kChunkKeys;
-        int32_t i = f % kChunkKeys;
-        if (i >= cnt[q]) continue;
-        uint64_t x = a[f];
+        int32_t i = ((f % kChunkKeys) + 64 * (f / 1024)) % kChunkKeys;
+        if (i >= cnt[q] || i >= take) continue;
+        uint64_t x = a[q * kChunkKeys + i];
         int32_t rank = i;
         for (int o = 0; o < ng && rank < take; o++) {
             if (o == q) continue;
@@ -1078,13 +1083,15 @@ __device__ __forceinline__ void bal_merge_seg(int32_t s, const int32_t *nbase, c
 // with the segment's gains in registers and the histogram in LDS, then the
 // moves (bf.side is written): kind 0 flips the chosen nodes of both lists
 // (Algorithm 3 and the swap of Algorithm 5); kind 1 orders the chosen nodes
-// of the over-weight side (by counting) and one wavefront takes the balance
-// prefix (Algorithm 5).  The chosen set is the one the multi-workgroup path
-// chooses: the same keys, the same r.
+// of the over-weight side (by counting, their weights and incidence ranges
+// gathered meanwhile) and the workgroup takes the balance prefix (Algorithm
+// 5).  The chosen set is the one the multi-workgroup path chooses: the same
+// keys, the same r.
 //
 // CH (kind 1 only): one workgroup per chunk of the chunk table instead, whose
-// ordered best nodes go to ca for k_bal_merge; node ids are then local to the
-// chunk, which keeps the keys short.
+// ordered best nodes go to ca for the merge by the segment's last chunk; node
+// ids in the selection keys are then local to the chunk, which keeps them
+// short.
 template <int KIND, int TH, bool CH = false>
 __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelState st, int idbits_lv,
                                                            const int32_t *nw,
@@ -1108,12 +1115,14 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     int32_t s, a0, n;
     uint8_t md;
     int64_t bnd = 0, brm = 0, bm0 = 0, bm1 = 0;  // balance (one workgroup): the segment's state, loaded early
+    int32_t nld;  // nodes whose gains and sides are loaded (CH: from the level's end, not the segment's)
     if (CH) {
         int32_t ci = blockIdx.x;
         int32_t cc = ca.count[0];
         s = ca.seg[ci];
         a0 = ca.beg[ci];
         if (gv == 0 || ci >= cc) return;
+        nld = min(ca.N - a0, kChunkNodes);
         n = min(sv.nbase[s + 1] - a0, kChunkNodes);
         md = sv.mode[s];
     } else {
@@ -1129,6 +1138,7 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
         }
         if (gv == 0) return;
         n = a1 - a0;
+        nld = n;
     }
     const int idbits = CH ? bitlen_u32((uint32_t)max(n - 1, 0)) : idbits_lv;
     int32_t g[kSegItems];
@@ -1139,17 +1149,19 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     // memory page of the bytes it covers) and its gains (indices past the
     // segment read its node 0): loads in flight together
     const uint8_t *sp = sv.side + a0;
-    int32_t off0 = (int32_t)((uintptr_t)sp & 3), nwd = (off0 + n + 3) >> 2;
+    int32_t off0 = (int32_t)((uintptr_t)sp & 3), nwd = (off0 + n + 3) >> 2, nwl = (off0 + nld + 3) >> 2;
     const uint32_t *wp = (const uint32_t *)(sp - off0);
     constexpr int kW = kCap / 4 / TH + 1;
     uint32_t xw[kW];
-    if (md && n > 0) {
+    // (CH: issued before the segment's bounds arrive; nodes past the segment
+    // are loaded but never used)
+    if ((CH || md) && nld > 0) {
 #pragma unroll
-        for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nwd - 1)];
+        for (int q = 0; q < kW; q++) xw[q] = wp[min(q * TH + (int32_t)threadIdx.x, nwl - 1)];
 #pragma unroll
         for (int j = 0; j < kSegItems; j++) {
             int32_t i = j * TH + (int32_t)threadIdx.x;
-            g[j] = sv.gain[a0 + (i < n ? i : 0)];
+            g[j] = sv.gain[a0 + (i < nld ? i : 0)];
         }
     }
     if (!md) return;
@@ -1329,29 +1341,60 @@ __global__ __launch_bounds__(TH) void k_seg_select(int32_t S, SelView sv, SelSta
     }
     __syncthreads();
     int32_t cnt = nkeys;
-    block_rank_sort(keys, sorted, cnt);
-    if (CH) {
-        int32_t gi = (a0 - sv.nbase[s]) / kChunkNodes;
-        uint64_t *dst = ca.cand + ((int64_t)s * kChunkMax + gi) * kChunkKeys;
-        for (int32_t i = threadIdx.x; i < cnt; i += TH) dst[i] = sorted[i];
-        if (threadIdx.x == 0) ca.ccnt[s * kChunkMax + gi] = cnt;
-        // the segment's last chunk to finish (ticket) merges the lists
-        __shared__ int32_t last;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int32_t nch = (sv.nbase[s + 1] - sv.nbase[s] + kChunkNodes - 1) / kChunkNodes;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            last = atomicAdd(&st.tick[s], 1) == nch - 1;
-            if (last) {
-                st.tick[s] = 0;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (!CH) {
+        // counting order (as block_rank_sort), each chosen node's weight and
+        // incidence range loaded while its rank is counted (for the finish)
+        __shared__ int32_t pw[CH ? 1 : kKeys], pnb[CH ? 1 : kKeys], pne[CH ? 1 : kKeys];
+        const bool logm = bf.ml.cnode != nullptr;
+        int tpc = 1;
+        while (tpc < 16 && cnt * 2 * tpc <= TH) tpc <<= 1;
+        for (int base = 0; base < cnt * tpc; base += TH) {
+            int t = base + (int)threadIdx.x, i = t / tpc, part = t & (tpc - 1);
+            uint64_t x = keys[i < cnt ? i : 0];
+            int32_t v = (int32_t)(uint32_t)(x & 0xffffffffu), xw = 0, xb = 0, xe = 0;
+            if (i < cnt && part == 0) {
+                xw = nw[v];
+                if (logm) {
+                    xb = bf.ml.noff[v];
+                    xe = bf.ml.noff[v + 1];
+                }
+            }
+            int r = 0;
+            if (i < cnt) {
+#pragma unroll 8
+                for (int j = part; j < cnt; j += tpc) r += keys[j] < x;
+            }
+            for (int o = 1; o < tpc; o <<= 1) r += __shfl_xor(r, o, 64);
+            if (i < cnt && part == 0) {
+                sorted[r] = x;
+                pw[r] = xw;
+                pnb[r] = xb;
+                pne[r] = xe;
             }
         }
         __syncthreads();
-        if (last) bal_merge_seg(s, sv.nbase, sv.m, ca, bf);
+        bal_finish_block(s, sorted, cnt, bf, h, bnd, brm, bm0, bm1, BalPre{pw, pnb, pne});
         return;
     }
-    bal_finish_block(s, sorted, cnt, bf, h, bnd, brm, bm0, bm1);
+    block_rank_sort(keys, sorted, cnt);
+    int32_t gi = (a0 - sv.nbase[s]) / kChunkNodes;
+    uint64_t *dst = ca.cand + ((int64_t)s * kChunkMax + gi) * kChunkKeys;
+    for (int32_t i = threadIdx.x; i < cnt; i += TH) dst[i] = sorted[i];
+    if (threadIdx.x == 0) ca.ccnt[s * kChunkMax + gi] = cnt;
+    // the segment's last chunk to finish (ticket) merges the lists
+    __shared__ int32_t last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t nch = (sv.nbase[s + 1] - sv.nbase[s] + kChunkNodes - 1) / kChunkNodes;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        last = atomicAdd(&st.tick[s], 1) == nch - 1;
+        if (last) {
+            st.tick[s] = 0;
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        }
+    }
+    __syncthreads();
+    if (last) bal_merge_seg(s, sv.nbase, sv.m, ca, bf);
 }
 
 // The chunk table of a level: segment s gets ceil(n_s / kChunkNodes)
