@@ -4,7 +4,7 @@
 // Built by a stable LSD radix sort of (node id, hyperedge id) pairs taken in
 // pin order, 8-bit digits: per-tile digit histograms, one prefix scan of the
 // (digit, tile) counts, and a stable scatter whose in-tile ranks come from
-// wavefront ballots.  Node offsets are binary searches into the sorted keys.
+// wavefront ballots and which writes each tile out in digit order.  Node offsets are binary searches into the sorted keys.
 //
 // With it, the per-node steps - the 64-bit minimum of Algorithm 1 and the gain
 // sum of Algorithm 4 (uncoarsen.hpp) - are gathers over a node's own
@@ -39,38 +39,43 @@ __global__ __launch_bounds__(kBlock) void k_rs_hist(const uint32_t *keys, int64_
     counts[(int64_t)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-// Stable scatter of one tile.  Items are taken round by round (item r*256+t
-// of the tile in round r), which is their original order.
+// Stable scatter of one tile.  Each wavefront ranks its own 1024 consecutive
+// items (64 a step, in order) against a digit counter row of its own, so no
+// workgroup barrier separates the steps; one scan over the digits then gives
+// every item its place in the tile's digit order, the tile is staged in that
+// order in LDS, and it is written out from there: consecutive threads write
+// consecutive addresses of a digit's run.
+static_assert(kBlock == 256, "one digit per thread");
 __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, const int32_t *vin,
                                                        int64_t n, int shift,
                                                        const uint32_t *offs, int64_t ntiles,
                                                        uint32_t *kout, int32_t *vout)
 {
-    __shared__ uint32_t base[256], run[256];
-    __shared__ uint32_t wcnt[kBlock / 64][256];
-    int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    __shared__ uint32_t base[256], tstart[256];
+    __shared__ uint32_t wrun[kBlock / 64][256];
+    __shared__ uint32_t lk[kRsTile];
+    __shared__ int32_t lv[kRsTile];
+    __shared__ uint32_t lds[16];
+    const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+    const unsigned long long below = (1ull << lane) - 1;
+    const int64_t tile = (int64_t)blockIdx.x * kRsTile, wb = tile + (int64_t)w * (kRsItems * 64);
     base[t] = offs[(int64_t)t * ntiles + blockIdx.x];
-    run[t] = 0;
-    unsigned long long below = (1ull << lane) - 1;
-    int64_t tile = (int64_t)blockIdx.x * kRsTile;
-    // the whole tile in registers first: its loads in flight together
-    uint32_t keys[kRsItems];
+    // this wavefront's items in registers first: their loads in flight together
+    uint32_t keys[kRsItems], rk[kRsItems];
     int32_t vals[kRsItems];
 #pragma unroll
     for (int r = 0; r < kRsItems; r++) {
-        int64_t i = tile + r * kBlock + t;
+        int64_t i = wb + r * 64 + lane;
         keys[r] = i < n ? kin[i] : 0u;
         vals[r] = i < n ? vin[i] : 0;
     }
+    for (int d = lane; d < 256; d += 64) wrun[w][d] = 0;
+    // rank of each item among the earlier items of its wavefront with its digit
+    // (the row is this wavefront's alone; its LDS accesses execute in order)
 #pragma unroll
     for (int r = 0; r < kRsItems; r++) {
-        for (int j = t; j < (kBlock / 64) * 256; j += kBlock) (&wcnt[0][0])[j] = 0;
-        int64_t i = tile + r * kBlock + t;
-        bool valid = i < n;
-        uint32_t key = keys[r];
-        int32_t val = vals[r];
-        uint32_t dig = (key >> shift) & 255u;
-        // lanes holding the same digit
+        bool valid = wb + r * 64 + lane < n;
+        uint32_t dig = (keys[r] >> shift) & 255u;
         unsigned long long same = __ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -78,22 +83,46 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, cons
             same &= ((dig >> b) & 1u) ? m : ~m;
         }
         int rank = __popcll(same & below);
-        __syncthreads();  // wcnt cleared, base/run visible
-        if (valid && rank == 0) wcnt[w][dig] = (uint32_t)__popcll(same);
-        __syncthreads();
-        if (valid) {
-            uint32_t pre = 0;
-            for (int x = 0; x < w; x++) pre += wcnt[x][dig];
-            uint32_t pos = base[dig] + run[dig] + pre + (uint32_t)rank;
-            kout[pos] = key;
-            vout[pos] = val;
-        }
-        __syncthreads();
-        uint32_t add = 0;
+        uint32_t before = wrun[w][dig];
+        rk[r] = before + (uint32_t)rank;
+        if (valid && rank == 0) wrun[w][dig] = before + (uint32_t)__popcll(same);
+    }
+    __syncthreads();
+    // per digit (thread t): the earlier wavefronts' counts, and the digit's start
+    // in the tile's order
+    uint32_t c[kBlock / 64], tot = 0;
 #pragma unroll
-        for (int x = 0; x < kBlock / 64; x++) add += wcnt[x][t];
-        run[t] += add;
-        __syncthreads();
+    for (int x = 0; x < kBlock / 64; x++) {
+        c[x] = wrun[x][t];
+        tot += c[x];
+    }
+    uint32_t all;
+    uint32_t st = block_excl_scan(tot, lds, &all);
+    tstart[t] = st;
+    uint32_t acc = st;
+#pragma unroll
+    for (int x = 0; x < kBlock / 64; x++) {
+        wrun[x][t] = acc;
+        acc += c[x];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRsItems; r++) {
+        if (wb + r * 64 + lane >= n) continue;
+        uint32_t dig = (keys[r] >> shift) & 255u;
+        uint32_t lp = wrun[w][dig] + rk[r];
+        lk[lp] = keys[r];
+        lv[lp] = vals[r];
+    }
+    __syncthreads();
+    const int32_t tn = (int32_t)min<int64_t>(kRsTile, n - tile);
+#pragma unroll 4
+    for (int32_t j = t; j < tn; j += kBlock) {
+        uint32_t key = lk[j];
+        uint32_t dig = (key >> shift) & 255u;
+        uint32_t pos = base[dig] + ((uint32_t)j - tstart[dig]);
+        kout[pos] = key;
+        vout[pos] = lv[j];
     }
 }
 
