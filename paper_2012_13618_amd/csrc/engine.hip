@@ -260,31 +260,34 @@ void build_incidence(Ctx &cx, Level &L)
     const int32_t N = L.N, E = L.E, P = L.P;
     uint32_t *k0 = ar.get<uint32_t>(P), *k1 = ar.get<uint32_t>(P);
     int32_t *v0 = ar.get<int32_t>(P), *v1 = ar.get<int32_t>(P);
-    ExpandPairsOp eop{(const int32_t *)L.off, (const int32_t *)L.pins, k0, v0};
-    launch(lc, "incidence", 8.0 * P, k_buckets<ExpandPairsOp>, buckets_grid(E, L.nmid, L.nbig), kBlock, 0, eop, E,
+    ExpandPairsOp eop{(const int32_t *)L.off, v0};
+    launch(lc, "incidence", 4.0 * P, k_buckets<ExpandPairsOp>, buckets_grid(E, L.nmid, L.nbig), kBlock, 0, eop, E,
            L.nmid, (const int32_t *)L.lmid, L.nbig, (const int32_t *)L.lbig);
     int bits = 0;
     while (bits < 31 && ((int64_t)1 << bits) < (int64_t)N) bits++;
     int64_t ntiles = ceil_div(P > 0 ? P : 1, kRsTile);
     uint32_t *counts = ar.get<uint32_t>(256 * ntiles), *offs = ar.get<uint32_t>(256 * ntiles);
     uint32_t *tot = ar.get<uint32_t>(1);
+    // the first pass reads the keys (the pins) in place
+    const uint32_t *kin = (const uint32_t *)L.pins;
     for (int shift = 0; shift < bits && P > 0; shift += 8) {
-        launch(lc, "radix_hist", 4.0 * P, k_rs_hist, ntiles, kBlock, 0, (const uint32_t *)k0,
-               (int64_t)P, shift, counts, ntiles);
+        launch(lc, "radix_hist", 4.0 * P, k_rs_hist, ntiles, kBlock, 0, kin, (int64_t)P, shift, counts, ntiles);
         const uint32_t *cnt = counts;
         uint32_t *of = offs;
         scan<uint32_t>(
             lc, ar, "radix_scan", 256 * ntiles, [=] __device__(int64_t i) -> uint32_t { return cnt[i]; },
             [=] __device__(int64_t i, uint32_t ex, uint32_t) { of[i] = ex; }, tot);
-        launch(lc, "radix_scatter", 16.0 * P, k_rs_scatter, ntiles, kBlock, 0, (const uint32_t *)k0,
-               (const int32_t *)v0, (int64_t)P, shift, (const uint32_t *)offs, ntiles, k1, v1);
+        launch(lc, "radix_scatter", 16.0 * P, k_rs_scatter, ntiles, kBlock, 0, kin, (const int32_t *)v0,
+               (int64_t)P, shift, (const uint32_t *)offs, ntiles, k1, v1);
+        kin = k1;
         std::swap(k0, k1);
         std::swap(v0, v1);
     }
     L.inc = v0;
     L.noff = ar.get<int32_t>((int64_t)N + 1);
-    launch(lc, "incidence", 4.0 * N, k_node_offsets, ceil_div((int64_t)N + 1, kBlock), kBlock, 0,
-           (const uint32_t *)k0, (int64_t)P, N, L.noff);
+    // (kin: the sorted keys, or the pins themselves when no pass ran)
+    launch(lc, "incidence", 4.0 * N, k_node_offsets, ceil_div((int64_t)N + 1, kBlock), kBlock, 0, kin,
+           (int64_t)P, N, L.noff);
     L.nmid_bound = std::min<int64_t>(N, P / (kNodeSmallMax + 1)) + 1;
     L.nbig_bound = std::min<int64_t>(N, P / (kNodeMidMax + 1)) + 1;
     L.lnmid = ar.get<int32_t>(L.nmid_bound);

@@ -126,10 +126,10 @@ __global__ __launch_bounds__(kBlock) void k_rs_scatter(const uint32_t *kin, cons
     }
 }
 
-// pins -> (node, hyperedge) pairs in pin order
+// pins -> (node, hyperedge) pairs in pin order: the nodes are the pins
+// themselves, so only each pin's hyperedge is written
 struct ExpandPairsOp {
-    const int32_t *off, *pins;
-    uint32_t *keys;
+    const int32_t *off;
     int32_t *vals;
     template <int S> __device__ __forceinline__ void run(int64_t vb, int32_t count, const int32_t *list) const;
 };
@@ -142,10 +142,7 @@ __device__ __forceinline__ void ExpandPairsOp::run(int64_t vb, int32_t count, co
     if (e < 0) return;
     int32_t b = off[e], d = off[e + 1] - b;
     if (!thread_split<S>(d)) return;
-    for (int i = lane; i < d; i += stride) {
-        keys[b + i] = (uint32_t)pins[b + i];
-        vals[b + i] = e;
-    }
+    for (int i = lane; i < d; i += stride) vals[b + i] = e;
 }
 
 // noff[v] = first position of node v in the sorted keys (lower bound)
