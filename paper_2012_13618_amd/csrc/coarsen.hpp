@@ -397,32 +397,48 @@ __global__ __launch_bounds__(kBlock) void k_qbuild_sw(int32_t E, int32_t nmid, c
 }
 
 // Sorted distinct parents of one hyperedge by a whole workgroup: a is a
-// power-of-two buffer (LDS for degree <= 8192, else global scratch).
-__device__ void block_unique_emit(int32_t *a, int n2, int32_t d, int32_t b, int32_t *qpins,
+// power-of-two buffer (LDS for degree <= 8192, else global scratch), sorted,
+// its first d entries the hyperedge's parents.  Each wavefront walks its own
+// contiguous part of a, 64 entries a step: a first sweep counts the distinct
+// values by ballots, one pass over the wavefronts' counts gives each its
+// start, and a second sweep writes them - two barriers for the whole list.
+__device__ void block_unique_emit(const int32_t *a, int n2, int32_t d, int32_t b, int32_t *qpins,
                                   int32_t *len_out, uint64_t *sum_out)
 {
-    __shared__ int32_t ldsi[16];
+    __shared__ int32_t wtot[16];
     __shared__ uint64_t ldsu[16];
-    __shared__ int32_t carry;
-    if (threadIdx.x == 0) carry = 0;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int per = n2 / nw;  // a multiple of 64: n2 >= 64 * the wavefronts
+    const int i0 = w * per;
+    const unsigned long long below = (1ull << lane) - 1;
+    int32_t c = 0;
+    for (int st = 0; st < per && i0 + st < d; st += 64) {
+        int i = i0 + st + lane;
+        bool first = i < d && (i == 0 || a[i] != a[i - 1]);
+        c += __popcll(__ballot(first));
+    }
+    if (lane == 0) wtot[w] = c;
     __syncthreads();
+    int32_t at = 0, tot = 0;
+    for (int x = 0; x < nw; x++) {
+        int32_t v = wtot[x];
+        if (x < w) at += v;
+        tot += v;
+    }
     uint64_t sum = 0;
-    for (int base = 0; base < n2; base += blockDim.x) {
-        int i = base + threadIdx.x;
-        int32_t x = i < n2 ? a[i] : INT32_MAX;
+    for (int st = 0; st < per && i0 + st < d; st += 64) {
+        int i = i0 + st + lane;
+        int32_t x = a[i];
         bool first = i < d && (i == 0 || x != a[i - 1]);
-        int32_t tot;
-        int32_t ex = block_excl_scan((int32_t)first, ldsi, &tot);
+        unsigned long long bm = __ballot(first);
         if (first) {
-            qpins[b + carry + ex] = x;
+            qpins[b + at + __popcll(bm & below)] = x;
             sum += fp_term(x, 0);
         }
-        __syncthreads();
-        if (threadIdx.x == 0) carry += tot;
-        __syncthreads();
+        at += __popcll(bm);
     }
     sum = block_sum(sum, ldsu);
-    *len_out = carry;
+    *len_out = tot;
     *sum_out = sum;
 }
 
